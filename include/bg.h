@@ -1,0 +1,150 @@
+/*
+ * bg.h -- C ABI of the MI355X (gfx950) n-gluon tree-amplitude library.
+ *
+ * The library evaluates tree-level n-gluon squared matrix elements |M|^2 with
+ * the Berends-Giele recursion of "Many-gluon tree amplitudes on modern GPUs"
+ * (Bothmann, Giele, Hoeche, Isaacson, Knobbe, arXiv:2106.06507), one event per
+ * GPU lane, in two forms:
+ *   - colour-ordered (COBG, Section 2.3 eq. cobg): partial amplitudes for the
+ *     (n-2)! orderings A(1, sigma, n) of the adjoint decomposition (Section 2.2
+ *     eq. color_decomposition_adjoint), then |M|^2 = A^dagger C A
+ *     (eq. color_summed_analytic) with the colour matrix of
+ *     eq. color_coefficient_adjoint;
+ *   - colour-dressed (CDBG, Section 2.3 eq. color_dressed_currents) for one
+ *     sampled colour-flow assignment per event (eq. color_decomposition_colorflow).
+ *
+ * Conventions shared by every entry point
+ *   - Pointers named mom/hel/col/amp/me2/grad are DEVICE pointers owned by the
+ *     caller; the library never frees them and never retains them past the call.
+ *   - mom   : double [n][4][E], E fastest.  All momenta outgoing (incoming beams
+ *             negated), metric (+,-,-,-), any unit (GeV in the tests).
+ *   - hel   : int8 [n][E], each +1 or -1 (all-outgoing helicity labels).  A gluon
+ *             with label h and physical momentum k = sign(p^0) p uses the external
+ *             current (eps^h(k))* with eps^+-(k) = (e1 +- i e2)/sqrt2 in the
+ *             light-cone gauge with gauge vector (|k|, -k) (Section 2.1 eq.
+ *             tensor_axial): e1 = (r|k|^2 - (r.k)k)/|..|, e2 = (k x e1)/|k|,
+ *             e1^0 = e2^0 = 0, r = (3, -6, 2)/7.
+ *   - col   : int8 [2][n][E]: col[0][k] = i_k, col[1][k] = j_k in {0,1,2}, the
+ *             colour-flow pair of gluon k (3x3 unit matrix e_{j_k i_k}).
+ *   - amp   : double [2][K][E] (real plane then imaginary plane), K = (n-2)!,
+ *             sigma in lexicographic order of (sigma_2..sigma_{n-1}).
+ *   - me2   : double [E].  No spin/colour averaging, no symmetry factor.
+ *   - Couplings: g_s = sqrt(4 pi 0.118) (alpha_s of Section 5), SU(3), generators
+ *     normalised as Tr(T^a T^b) = delta^ab.
+ *   - stream: a hipStream_t passed as void*; NULL is the legacy default stream.
+ *     Every call is stream-ordered and asynchronous: host-detectable errors are
+ *     returned before anything is enqueued; device faults surface on a later
+ *     synchronisation.
+ *   - A context is bound to one device and is not thread-safe; use one per host
+ *     thread.  It owns the colour matrices and a reusable workspace.
+ */
+#ifndef BG_H_
+#define BG_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define BG_OK            0
+#define BG_EINVAL       -1   /* null pointer, bad enum, n or E out of range */
+#define BG_ERANGE       -2   /* size overflow or workspace too small */
+#define BG_ENODEV       -3   /* no usable gfx950 device */
+#define BG_EDEVICE      -4   /* a HIP runtime call failed */
+#define BG_ENOMEM       -5   /* device allocation failed */
+#define BG_EUNSUPPORTED -6   /* valid request the library does not implement */
+
+/* evaluation mode */
+#define BG_MODE_COBG 0       /* colour-ordered recursion + colour matrix */
+#define BG_MODE_CDBG 1       /* colour-dressed recursion, colours sampled (col required) */
+#define BG_MODE_AUTO 2       /* COBG for n <= 7, CDBG for n >= 8 */
+
+/* arithmetic of the recursion; contraction and |M|^2 sums are always FP64 */
+#define BG_PREC_FP64       0
+#define BG_PREC_FP32_MIXED 1 /* FP32 complex currents, FP64 invariants/contraction */
+
+#define BG_N_MIN 4
+#define BG_N_MAX 9
+
+typedef struct bg_context bg_context;
+
+/* Create a context on HIP device `device`.  Returns BG_ENODEV if the device is
+ * missing or not gfx950.  *out is set only on success. */
+int bg_context_create(bg_context** out, int device);
+void bg_context_destroy(bg_context* ctx);
+
+/* Static message for a status code (never NULL). */
+const char* bg_status_string(int status);
+
+/* Number of colour-ordered amplitudes K = (n-2)! for n in [BG_N_MIN, BG_N_MAX], else 0. */
+int64_t bg_num_orderings(int n);
+
+/* Host function, no device needed.  Writes the colour matrix C(n) of
+ * eq. color_coefficient_adjoint (Section 2.2), K x K row-major doubles, into
+ * HOST memory `out` of capacity `cap` doubles.  Entries are exact integers
+ * (N = 3).  n in [4, 8].  BG_ERANGE if cap < K*K. */
+int bg_color_matrix(int n, double* out, int64_t cap);
+
+/* Partial amplitudes A(1, sigma, n) for every sigma of the adjoint basis
+ * (Section 2.3 eqs. cobg and cobg_full_amplitude; the printed p^2_{1,n} is read
+ * as the inverse propagator of J(1..n-1), i.e. the top current is amputated).
+ * One helicity configuration per event (hel required).  precision selects the
+ * recursion arithmetic.  Output amp [2][K][E] as above.  n in [4, 7]. */
+int bg_currents(bg_context* ctx, int n, int64_t n_events, const double* mom,
+                const int8_t* hel, int precision, double* amp, void* stream);
+
+/* me2[e] = sum_{s,t} C_st Re(A_s conj(A_t)) (eq. color_summed_analytic) for
+ * amp [2][K][E] from bg_currents, in FP64 (matrix cores for K >= 24).
+ * If accumulate != 0 the result is added to me2 instead of stored.  n in [4, 7]. */
+int bg_color_contract(bg_context* ctx, int n, int64_t n_events, const double* amp,
+                      double* me2, int accumulate, void* stream);
+
+typedef struct bg_request {
+    int n;               /* gluons, BG_N_MIN..BG_N_MAX */
+    int mode;            /* BG_MODE_* */
+    int precision;       /* BG_PREC_* */
+    int reserved;        /* must be 0 */
+    int64_t n_events;    /* E >= 0 (0 is a no-op) */
+    const double* mom;   /* [n][4][E] */
+    const int8_t* hel;   /* [n][E], or NULL = sum over all 2^n helicities (COBG only) */
+    const int8_t* col;   /* [2][n][E] for CDBG, NULL for COBG */
+    double* me2;         /* [E] out */
+} bg_request;
+
+/* |M|^2 per event.  COBG: colour-summed (eq. color_summed_analytic), for one
+ * helicity per event or summed over helicities (hel NULL).  CDBG: |A|^2 of the
+ * colour-flow amplitude of the given assignment (eq. color_decomposition_colorflow
+ * via eq. color_dressed_currents); assignments without a closed colour chain
+ * give exactly 0. */
+int bg_me2(bg_context* ctx, const bg_request* req, void* stream);
+
+/* Gradient of the COBG colour-summed |M|^2 with respect to every momentum
+ * component, contracted with an upstream gradient:
+ *   grad_mom[i][mu][e] = grad_me2[e] * d me2[e] / d mom[i][mu][e]
+ * (grad_me2 NULL means 1).  The differentiated function is the one bg_me2
+ * computes, with the generic Minkowski P^2 and the polarization formulas above
+ * applied off the mass shell.  Also writes me2 if req->me2 is non-NULL.
+ * Requires mode COBG and hel non-NULL; n in [4, 7]. */
+int bg_me2_grad(bg_context* ctx, const bg_request* req, const double* grad_me2,
+                double* grad_mom, void* stream);
+
+/* Several requests (mixed multiplicities, uneven event counts) in one
+ * persistent launch; mode BG_MODE_AUTO picks COBG for n <= 7 and CDBG for
+ * n >= 8 per segment.  All segments share one precision. */
+int bg_me2_batch(bg_context* ctx, const bg_request* segs, int n_segs, void* stream);
+
+/* Self-test of the matrix-core operand layout used by bg_color_contract:
+ * runs one v_mfma_f64_16x16x4f64 with lane l supplying A[l%16][l/16] =
+ * (l%16 + 1) + 100 (l/16) and B[l/16][l%16] = (l%16 + 1) 8^(l/16), and copies
+ * the 64 lanes x 4 accumulator registers (out[4 l + r]) to HOST memory `out`
+ * (256 doubles).  The caller decodes which (row, column) of D each element is.
+ * Synchronous. */
+int bg_mfma_layout_probe(bg_context* ctx, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BG_H_ */

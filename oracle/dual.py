@@ -49,6 +49,11 @@ class Dual:
     def __rtruediv__(self, o):
         return Dual(o / self.v, -o * self.d / (self.v * self.v))
 
+    def __pow__(self, x):
+        """Real power (x a Python number): d(a^x) = x a^(x-1) da."""
+        vx = self.v ** x
+        return Dual(vx, x * self.v ** (x - 1) * self.d)
+
     def conj(self):
         return Dual(np.conj(self.v), np.conj(self.d))
 

@@ -1,0 +1,180 @@
+"""Torch-facing wrappers around the C ABI.
+
+PyTorch provides device memory and the current HIP stream; every step of the
+computation runs in the library's kernels.  Inputs follow include/bg.h:
+mom float64 [n, 4, E], hel int8 [n, E], col int8 [2, n, E], all on the GPU.
+"""
+import ctypes
+import math
+import threading
+
+import torch
+
+from . import _lib
+from ._lib import bg_request, check, lib
+
+_PREC = {"fp64": _lib.PREC_FP64, "fp32": _lib.PREC_FP32_MIXED, "mixed": _lib.PREC_FP32_MIXED}
+_MODE = {"cobg": _lib.MODE_COBG, "cdbg": _lib.MODE_CDBG, "auto": _lib.MODE_AUTO}
+
+
+class Context:
+    """Owns a bg_context (colour matrices, workspace) on one device."""
+
+    def __init__(self, device=None):
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        check(lib().bg_context_create(ctypes.byref(h), self.device), "bg_context_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().bg_context_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_ctx_lock = threading.Lock()
+_contexts = {}
+
+
+def default_context(device=None):
+    if device is None:
+        device = torch.cuda.current_device()
+    with _ctx_lock:
+        c = _contexts.get(device)
+        if c is None:
+            c = _contexts[device] = Context(device)
+        return c
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(None)
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check_mom(mom):
+    if not (mom.is_cuda and mom.dtype == torch.float64 and mom.dim() == 3 and mom.shape[1] == 4):
+        raise ValueError("mom must be a CUDA float64 tensor [n, 4, E]")
+    if not mom.is_contiguous():
+        raise ValueError("mom must be contiguous")
+    return mom.shape[0], mom.shape[2]
+
+
+def _check_i8(t, shape, name):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.int8 and tuple(t.shape) == tuple(shape) and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous CUDA int8 tensor of shape {tuple(shape)}")
+    return t
+
+
+def num_orderings(n):
+    return math.factorial(n - 2)
+
+
+def colour_matrix(n):
+    """Host-generated exact colour matrix C(n) (float64 CPU tensor [K, K])."""
+    K = num_orderings(n)
+    out = torch.empty((K, K), dtype=torch.float64)
+    check(lib().bg_color_matrix(n, ctypes.c_void_p(out.data_ptr()), K * K), "bg_color_matrix")
+    return out
+
+
+def currents(mom, hel, precision="fp64", ctx=None):
+    """Partial amplitudes A(1, sigma, n): float64 [2, K, E] (real, imaginary planes)."""
+    n, E = _check_mom(mom)
+    _check_i8(hel, (n, E), "hel")
+    ctx = ctx or default_context(mom.device.index)
+    amp = torch.empty((2, num_orderings(n), E), dtype=torch.float64, device=mom.device)
+    check(lib().bg_currents(ctx.handle, n, E, _ptr(mom), _ptr(hel), _PREC[precision], _ptr(amp),
+                            _stream(mom.device)), "bg_currents")
+    return amp
+
+
+def color_contract(amp, n, out=None, accumulate=False, ctx=None):
+    """|M|^2 = A^dagger C A per event from amp [2, K, E] (FP64)."""
+    K = num_orderings(n)
+    if not (amp.is_cuda and amp.dtype == torch.float64 and amp.shape[:2] == (2, K) and amp.is_contiguous()):
+        raise ValueError(f"amp must be a contiguous CUDA float64 tensor [2, {K}, E]")
+    E = amp.shape[2]
+    ctx = ctx or default_context(amp.device.index)
+    if out is None:
+        out = torch.empty(E, dtype=torch.float64, device=amp.device)
+    check(lib().bg_color_contract(ctx.handle, n, E, _ptr(amp), _ptr(out), int(accumulate),
+                                  _stream(amp.device)), "bg_color_contract")
+    return out
+
+
+def _request(mom, hel, col, mode, precision, me2):
+    n, E = _check_mom(mom)
+    _check_i8(hel, (n, E), "hel")
+    _check_i8(col, (2, n, E), "col")
+    r = bg_request()
+    r.n = n
+    r.mode = _MODE[mode]
+    r.precision = _PREC[precision]
+    r.reserved = 0
+    r.n_events = E
+    r.mom = mom.data_ptr()
+    r.hel = hel.data_ptr() if hel is not None else None
+    r.col = col.data_ptr() if col is not None else None
+    r.me2 = me2.data_ptr() if me2 is not None else None
+    return r
+
+
+def me2(mom, hel=None, col=None, mode="cobg", precision="fp64", out=None, ctx=None):
+    """Per-event |M|^2 (float64 [E]); hel None sums over helicities (COBG)."""
+    n, E = _check_mom(mom)
+    ctx = ctx or default_context(mom.device.index)
+    if out is None:
+        out = torch.empty(E, dtype=torch.float64, device=mom.device)
+    r = _request(mom, hel, col, mode, precision, out)
+    check(lib().bg_me2(ctx.handle, ctypes.byref(r), _stream(mom.device)), "bg_me2")
+    return out
+
+
+def me2_grad(mom, hel, grad_me2=None, precision="fp64", ctx=None, want_me2=True):
+    """(me2 [E], grad [n, 4, E]) with grad = grad_me2 * d me2 / d mom."""
+    n, E = _check_mom(mom)
+    ctx = ctx or default_context(mom.device.index)
+    out = torch.empty(E, dtype=torch.float64, device=mom.device) if want_me2 else None
+    grad = torch.empty_like(mom)
+    r = _request(mom, hel, None, "cobg", precision, out)
+    if grad_me2 is not None:
+        if not (grad_me2.is_cuda and grad_me2.dtype == torch.float64 and grad_me2.shape == (E,)):
+            raise ValueError("grad_me2 must be a CUDA float64 tensor [E]")
+        grad_me2 = grad_me2.contiguous()
+    check(lib().bg_me2_grad(ctx.handle, ctypes.byref(r), _ptr(grad_me2), _ptr(grad),
+                            _stream(mom.device)), "bg_me2_grad")
+    return out, grad
+
+
+class ME2(torch.autograd.Function):
+    """Differentiable colour-summed |M|^2 (COBG, one helicity per event)."""
+
+    @staticmethod
+    def forward(ctx, mom, hel, precision="fp64"):
+        ctx.save_for_backward(mom, hel)
+        ctx.precision = precision
+        return me2(mom, hel, precision=precision)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        mom, hel = ctx.saved_tensors
+        _, g = me2_grad(mom, hel, grad_me2=grad_out.contiguous(), precision=ctx.precision,
+                        want_me2=False)
+        return g, None, None

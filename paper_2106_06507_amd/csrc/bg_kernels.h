@@ -1,0 +1,39 @@
+// Internal launch interface between the C-ABI layer (bg_api.cpp) and the
+// HIP kernels.  Launchers return 0 on success, -1 on a launch error and -2 for
+// an unsupported size.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bg {
+
+template <int K>
+struct Factorial {
+  static constexpr int64_t value = K * Factorial<K - 1>::value;
+};
+template <>
+struct Factorial<0> {
+  static constexpr int64_t value = 1;
+};
+
+inline int64_t factorial(int k) {
+  int64_t r = 1;
+  for (int i = 2; i <= k; ++i) r *= i;
+  return r;
+}
+
+// Partial amplitudes amp [2][K][E] for one helicity per event.  hel may be
+// null, in which case helicity configuration `hconf` is used for every event
+// (bit n-1-i set means gluon i has helicity -1).
+int cobg_amplitudes(int n, bool fp32, int64_t E, const double* mom, const int8_t* hel, int hconf,
+                    double* amp, hipStream_t stream);
+
+// me2[e] (+)= sum_st C_st Re(A_s conj(A_t)); C is K x K row-major on device.
+int contract_valu(int K, int64_t E, const double* amp, const double* C, double* me2,
+                  int accumulate, hipStream_t stream);
+int mfma_probe(double* out_dev, hipStream_t stream);
+int contract_mfma(int K, int64_t E, const double* amp, const double* C_pad, int KP, double* me2,
+                  int accumulate, hipStream_t stream);
+
+}  // namespace bg

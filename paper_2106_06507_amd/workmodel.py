@@ -1,0 +1,67 @@
+"""Algorithmic work and traffic per event, used for roofline fractions.
+
+Flop constants are the real floating-point operations of the vertex formulas
+as written (a fused multiply-add counts 2, a complex product 6 = 4 mul + 2 add):
+  V3(P,Q;A,B) = (A.B)(P-Q) + ((2Q+P).A)B - ((2P+Q).B)A        166
+  V4(J1,J2,J3) = 2(J1.J3)J2 - (J2.J3)J1 - (J1.J2)J3            188
+  propagator (complex current times real 1/P^2)                   8
+  range momentum (four additions)                                 4
+  final contraction with the last polarization (+ coupling)      32
+Colour contraction x^T C x + y^T C y with K orderings:     4K^2 + 4K
+The colour-ordered recursion walks the orderings depth first and shares
+prefixes: column d (ranges ending at position d) is evaluated once per
+distinct prefix of length d+1, i.e. (n-2)!/(n-2-d)! times.
+"""
+import math
+
+FLOP_V3 = 166
+FLOP_V4 = 188
+FLOP_PROP = 8
+FLOP_PMOM = 4
+FLOP_TOP = 32
+
+
+def cobg_vertex_counts(n):
+    """(V3, V4, propagators, range momenta, tops) evaluated per event and helicity."""
+    M = n - 1
+    v3 = v4 = prop = pm = top = 0
+    for d in range(1, M):
+        times = math.factorial(n - 2) // math.factorial(n - 2 - d)
+        for a in range(d - 1, -1, -1):
+            L = d - a + 1
+            v3 += times * (L - 1)
+            v4 += times * ((L - 1) * (L - 2) // 2)
+            pm += times
+            if a == 0 and d == M - 1:
+                top += times
+            else:
+                prop += times
+    return v3, v4, prop, pm, top
+
+
+def cobg_flops_per_event(n):
+    v3, v4, prop, pm, top = cobg_vertex_counts(n)
+    return v3 * FLOP_V3 + v4 * FLOP_V4 + prop * FLOP_PROP + pm * FLOP_PMOM + top * FLOP_TOP
+
+
+def contraction_flops_per_event(n):
+    K = math.factorial(n - 2)
+    return 4 * K * K + 4 * K
+
+
+def cobg_bytes_per_event(n, amp_out=True):
+    """HBM bytes of the recursion kernel: momenta and helicities in, amplitudes out."""
+    K = math.factorial(n - 2)
+    return n * 4 * 8 + n * 1 + (2 * K * 8 if amp_out else 0)
+
+
+def contraction_bytes_per_event(n):
+    K = math.factorial(n - 2)
+    return 2 * K * 8 + 8
+
+
+# Published MI355X peaks (dense, no sparsity)
+PEAK_FP64_VALU_TFLOPS = 78.6
+PEAK_FP32_VALU_TFLOPS = 157.3
+PEAK_FP64_MFMA_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0

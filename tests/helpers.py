@@ -31,3 +31,29 @@ def mink(a, b):
 def sij(mom, i, j):
     """2 p_i.p_j from the momentum array [n][4][E]."""
     return 2.0 * mink(mom[i], mom[j])
+
+
+def nonvanishing(hel):
+    """Events whose helicity configuration has a non-zero tree amplitude.
+
+    All-equal and one-different configurations vanish identically at tree
+    level (the oracle pins this), so both implementations return rounding
+    noise there and a relative error is meaningless."""
+    m = np.sum(np.asarray(hel) < 0, axis=0)
+    n = np.asarray(hel).shape[0]
+    return (m >= 2) & (m <= n - 2)
+
+
+def amplitude_scale(n, sqrt_s=1000.0):
+    """Natural size g'^(n-2) sqrt(s)^(4-n) of an n-gluon tree amplitude."""
+    g = (4 * np.pi * 0.118) ** 0.5 / 2 ** 0.5
+    return g ** (n - 2) * sqrt_s ** (4 - n)
+
+
+def helicity_scale(mom):
+    """Helicity-averaged colour-summed |M|^2 per event from the oracle: the
+    natural scale of the sampled estimator 2^n |M|^2_h (its mean is the
+    helicity sum).  Used to state errors of sampled configurations whose own
+    |M|^2 is suppressed by many orders of magnitude."""
+    from oracle import me2 as ome2
+    return ome2.me2_cobg(mom, None) / 2 ** mom.shape[0]

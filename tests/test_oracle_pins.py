@@ -28,36 +28,36 @@ def _events(n, E, seed, cuts=True):
 def test_polarization_transverse_normalised_complete():
     ev = _events(6, 64, 11)
     mom = ev["mom"]
-    q = list(polarization.Q_REF)
     for i in range(6):
         p = [mom[i, mu] for mu in range(4)]
         k = [np.sign(p[0]) * p[mu] for mu in range(4)]
+        q = polarization.gauge_vector(p)
+        assert np.max(np.abs(mdot(q, q)) / q[0] ** 2) < 1e-14  # light-like
         ep = polarization.external_current(p, np.ones(64))
         em = polarization.external_current(p, -np.ones(64))
         scale = np.abs(k[0])
         for e in (ep, em):
-            size = np.max([np.abs(x) for x in e], axis=0)
-            assert np.max(np.abs(mdot(e, k)) / (scale * size)) < 1e-12
-            # rounding scales with the largest component (gauge part ~ q when k ~ q)
-            assert np.max(np.abs(mdot(e, q)) / size ** 2) < 1e-12
-            assert np.max(np.abs(mdot(e, [np.conj(x) for x in e]) + 1.0) / size ** 2) < 1e-12
-            assert np.max(np.abs(mdot(e, e)) / size ** 2) < 1e-12  # helicity states are null
+            assert np.max(np.abs(mdot(e, k)) / scale) < 1e-14
+            assert np.max(np.abs(mdot(e, q)) / scale) < 1e-14
+            assert np.max(np.abs(mdot(e, [np.conj(x) for x in e]) + 1.0)) < 1e-14
+            assert np.max(np.abs(mdot(e, e))) < 1e-14  # helicity states are null
+            assert np.max(np.abs(np.array(e))) <= 1.0 + 1e-15
         # eq. helicity_axial: sum_lambda eps eps^dagger = P(k, q) (both indices up)
         P = polarization.projector(k, q)
         for a in range(4):
             for b in range(4):
                 s = ep[a] * np.conj(ep[b]) + em[a] * np.conj(em[b])
-                assert np.max(np.abs(s - P[a][b]) / size ** 2) < 1e-10
+                assert np.max(np.abs(s - P[a][b])) < 1e-13
 
 
 def test_polarization_helicity_sign_along_z():
-    # k along +z: up to a gauge term along k (t and z components only) the
-    # transverse parts of (e1, e2) form a right-handed pair, so
-    # eps^+ = (e1 + i e2)/sqrt2 ~ (x + i y) carries J_z = +1.
+    # k along +z: (e1, e2, z) right-handed, so eps^+ = (e1 + i e2)/sqrt2 ~ (x + i y)
+    # carries J_z = +1.
     p = [np.array([1.0]), np.array([0.0]), np.array([0.0]), np.array([1.0])]
     e1, e2 = polarization.basis(p)
     cross_z = e1[1][0] * e2[2][0] - e1[2][0] * e2[1][0]
     assert cross_z == pytest.approx(1.0, abs=1e-14)
+    assert abs(e1[0][0]) == 0.0 and abs(e2[0][0]) == 0.0
 
 
 # --------------------------------------------------------------------------
@@ -193,22 +193,21 @@ def test_tensor_form_equals_explicit_v4(n):
     assert np.max(np.abs(a - b)) / np.max(np.abs(a)) < 1e-13
 
 
-def test_reference_vector_independence():
-    """|A|^2 does not depend on the gauge vector of the polarizations."""
-    n = 6
+@pytest.mark.parametrize("n", [5, 6])
+def test_gauge_vector_independence(n):
+    """|A|^2 is the same in the radiation gauge and in light-cone gauges with a
+    fixed gauge vector (eq. tensor_axial holds for any light-like k)."""
     E = 16
-    ev = _events(n, E, 800)
+    ev = _events(n, E, 800 + n)
     mom, hel = ev["mom"], ev["hel"]
+    ps = momenta_list(mom)
     a1 = np.abs(cobg.partial_amplitudes(mom, hel))
-    saved = polarization.Q_REF, polarization.R_REF
-    try:
-        polarization.Q_REF = (1.0, -6.0 / 7.0, 2.0 / 7.0, 3.0 / 7.0)
-        polarization.R_REF = (0.0, 3.0 / 7.0, 6.0 / 7.0, 2.0 / 7.0)
-        assert abs(mink(polarization.Q_REF, polarization.R_REF)) < 1e-15
-        a2 = np.abs(cobg.partial_amplitudes(mom, hel))
-    finally:
-        polarization.Q_REF, polarization.R_REF = saved
-    assert np.max(np.abs(a1 - a2)) / np.max(a1) < 1e-9
+    for q, r in (((1.0, 2 / 7, 3 / 7, 6 / 7), (0.0, 3 / 7, -6 / 7, 2 / 7)),
+                 ((1.0, -6 / 7, 2 / 7, 3 / 7), (0.0, 3 / 7, 6 / 7, 2 / 7))):
+        fn = lambda p, q=q, r=r: polarization.basis_lightcone(p, list(q), list(r))
+        eps = [polarization.external_current(ps[i], hel[i], basis_fn=fn) for i in range(n)]
+        a2 = np.abs(np.array([ordered_amplitude(ps, eps, o) for o in cobg.ddm_orderings(n)]))
+        assert np.max(np.abs(a1 - a2)) / np.max(a1) < 1e-9
 
 
 # --------------------------------------------------------------------------
