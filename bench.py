@@ -60,6 +60,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=32768,
                     help="events of the same workload timed on the oracle")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run device-to-device copies of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the events are "
@@ -67,6 +69,14 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_probe:
+        nbytes = args.copy_probe << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        ms = time_calls(lambda: dst.copy_(src), max(1, args.steps), 1)
+        print(json.dumps({"copy_probe_bytes": nbytes, "ms": ms,
+                          "GBs": 2 * nbytes / (ms * 1e-3) / 1e9}), flush=True)
+        return
     from bg_inputs import workload
     from paper_2106_06507_amd import api, workmodel as wm
 
