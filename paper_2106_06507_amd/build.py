@@ -27,7 +27,8 @@ COMMON = [
     "-Wall", "-Wno-unused-function",
 ]
 
-SOURCES = ["bg_api.cpp", "colour_matrix.cpp", "cobg.hip", "contract.hip"]
+SOURCES = ["bg_api.cpp", "colour_matrix.cpp", "cobg_pair.hip", "cobg_adj.hip", "cdbg.hip",
+           "contract.hip"]
 
 
 def _compile(src, extra):

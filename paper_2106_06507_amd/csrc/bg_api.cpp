@@ -7,6 +7,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <utility>
 #include <vector>
 
 #include "bg_kernels.h"
@@ -17,11 +18,17 @@ int64_t colour_matrix(int n, double* C);
 
 struct bg_context {
   int device;
+  int num_cus;
+  size_t lds_per_cu;
+  size_t lds_per_block;
+  unsigned* cws;                   // colour-dressed workspace (counters + event list)
+  size_t cws_bytes;
   double* C_dev[BG_N_MAX + 1];     // K x K colour matrix per n (lazy)
   double* Cpad_dev[BG_N_MAX + 1];  // KP x KP zero-padded copy for the matrix-core path
   int KP[BG_N_MAX + 1];
   double* ws;                      // workspace (partial amplitudes)
   size_t ws_bytes;
+  uint8_t* perms_dev[BG_N_MAX + 1];  // [K][n-2] middle gluons of each ordering (gradient)
 };
 
 namespace {
@@ -121,6 +128,37 @@ int ensure_ws(bg_context* ctx, size_t bytes) {
 
 bool valid_n(int n) { return n >= BG_N_MIN && n <= BG_N_MAX; }
 
+// Lexicographic orderings of the middle gluons 1..n-2, as bytes [K][n-2].
+int ensure_perms(bg_context* ctx, int n) {
+  if (ctx->perms_dev[n]) return BG_OK;
+  const int k = n - 2;
+  const int64_t K = bg::factorial(k);
+  std::vector<uint8_t> tab((size_t)(K * k));
+  std::vector<int> p(k);
+  for (int i = 0; i < k; ++i) p[i] = i + 1;
+  for (int64_t s = 0; s < K; ++s) {
+    for (int i = 0; i < k; ++i) tab[(size_t)(s * k + i)] = (uint8_t)p[i];
+    // next lexicographic permutation
+    int i = k - 2;
+    while (i >= 0 && p[i] > p[i + 1]) --i;
+    if (i < 0) break;
+    int j = k - 1;
+    while (p[j] < p[i]) --j;
+    std::swap(p[i], p[j]);
+    for (int a = i + 1, b = k - 1; a < b; ++a, --b) std::swap(p[a], p[b]);
+  }
+  uint8_t* d = nullptr;
+  int st = hip_status(hipMalloc(&d, tab.size()), "hipMalloc(perms)");
+  if (st) return st;
+  st = hip_status(hipMemcpy(d, tab.data(), tab.size(), hipMemcpyHostToDevice), "hipMemcpy(perms)");
+  if (st) {
+    (void)hipFree(d);
+    return st;
+  }
+  ctx->perms_dev[n] = d;
+  return BG_OK;
+}
+
 int check_events(int n, int64_t E) {
   if (E < 0) return BG_EINVAL;
   // [n][4][E] doubles must be addressable
@@ -180,6 +218,9 @@ int bg_context_create(bg_context** out, int device) {
   bg_context* ctx = (bg_context*)calloc(1, sizeof(bg_context));
   if (!ctx) return BG_ENOMEM;
   ctx->device = device;
+  ctx->num_cus = prop.multiProcessorCount;
+  ctx->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor;
+  ctx->lds_per_block = prop.sharedMemPerBlock;
   *out = ctx;
   return BG_OK;
 }
@@ -191,8 +232,10 @@ void bg_context_destroy(bg_context* ctx) {
   for (int n = 0; n <= BG_N_MAX; ++n) {
     if (ctx->C_dev[n]) (void)hipFree(ctx->C_dev[n]);
     if (ctx->Cpad_dev[n]) (void)hipFree(ctx->Cpad_dev[n]);
+    if (ctx->perms_dev[n]) (void)hipFree(ctx->perms_dev[n]);
   }
   if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->cws) (void)hipFree(ctx->cws);
   free(ctx);
 }
 
@@ -246,6 +289,34 @@ static int me2_cobg(bg_context* ctx, const bg_request* r, hipStream_t stream) {
   return BG_OK;
 }
 
+static int me2_cdbg(bg_context* ctx, const bg_request* r, hipStream_t stream) {
+  const int n = r->n;
+  const bool fp32 = r->precision == BG_PREC_FP32_MIXED;
+  const size_t lds = bg::cdbg_lds_bytes(n, fp32);
+  if (lds == 0 || lds > ctx->lds_per_block) return BG_EUNSUPPORTED;
+  const size_t need = sizeof(unsigned) * (size_t)(2 + r->n_events);
+  if (ctx->cws_bytes < need) {
+    if (ctx->cws) {
+      int st = hip_status(hipDeviceSynchronize(), "hipDeviceSynchronize");
+      if (st) return st;
+      (void)hipFree(ctx->cws);
+      ctx->cws = nullptr;
+      ctx->cws_bytes = 0;
+    }
+    int st = hip_status(hipMalloc(&ctx->cws, need), "hipMalloc(cdbg workspace)");
+    if (st) return st;
+    ctx->cws_bytes = need;
+  }
+  size_t per_cu = ctx->lds_per_cu ? ctx->lds_per_cu / lds : 1;
+  if (per_cu < 1) per_cu = 1;
+  if (per_cu > 8) per_cu = 8;
+  int64_t grid = (int64_t)ctx->num_cus * (int64_t)per_cu;
+  if (grid > r->n_events) grid = r->n_events;
+  if (grid < 1) grid = 1;
+  return launch_status(bg::cdbg_me2(n, fp32, r->n_events, r->mom, r->hel, r->col, ctx->cws, r->me2,
+                                    (int)grid, stream));
+}
+
 static int validate_request(const bg_request* r) {
   if (!r) return BG_EINVAL;
   if (!valid_n(r->n)) return BG_EINVAL;
@@ -255,7 +326,7 @@ static int validate_request(const bg_request* r) {
   int st = check_events(r->n, r->n_events);
   if (st) return st;
   if (r->n_events == 0) return BG_OK;
-  if (!r->mom || !r->me2) return BG_EINVAL;
+  if (!r->mom) return BG_EINVAL;
   const int mode = r->mode == BG_MODE_AUTO ? (r->n <= 7 ? BG_MODE_COBG : BG_MODE_CDBG) : r->mode;
   if (mode == BG_MODE_CDBG && (!r->col || !r->hel)) return BG_EINVAL;
   return BG_OK;
@@ -265,23 +336,44 @@ int bg_me2(bg_context* ctx, const bg_request* r, void* stream) {
   if (!ctx) return BG_EINVAL;
   int st = validate_request(r);
   if (st) return st;
+  if (r->n_events > 0 && !r->me2) return BG_EINVAL;
   if (r->n_events == 0) return BG_OK;
   DeviceGuard g(ctx->device);
   if (!g.ok) return BG_EDEVICE;
   const int mode = r->mode == BG_MODE_AUTO ? (r->n <= 7 ? BG_MODE_COBG : BG_MODE_CDBG) : r->mode;
   if (mode == BG_MODE_COBG) return me2_cobg(ctx, r, (hipStream_t)stream);
-  return BG_EUNSUPPORTED;
+  return me2_cdbg(ctx, r, (hipStream_t)stream);
 }
 
 int bg_me2_grad(bg_context* ctx, const bg_request* r, const double* grad_me2, double* grad_mom,
                 void* stream) {
-  (void)grad_me2;
-  (void)stream;
   if (!ctx) return BG_EINVAL;
   int st = validate_request(r);
   if (st) return st;
   if (r->n_events > 0 && !grad_mom) return BG_EINVAL;
-  return BG_EUNSUPPORTED;
+  const int mode = r->mode == BG_MODE_AUTO ? (r->n <= 7 ? BG_MODE_COBG : BG_MODE_CDBG) : r->mode;
+  if (mode != BG_MODE_COBG || r->n > 7) return BG_EUNSUPPORTED;
+  if (r->n_events > 0 && !r->hel) return BG_EINVAL;
+  if (r->n_events == 0) return BG_OK;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return BG_EDEVICE;
+  hipStream_t s = (hipStream_t)stream;
+  const int n = r->n;
+  const int64_t K = bg::factorial(n - 2);
+  const int64_t E = r->n_events;
+  const bool fp32 = r->precision == BG_PREC_FP32_MIXED;
+  st = ensure_colour(ctx, n);
+  if (!st) st = ensure_perms(ctx, n);
+  if (!st) st = ensure_ws(ctx, sizeof(double) * 4 * K * E);
+  if (st) return st;
+  double* amp = ctx->ws;
+  double* Y = ctx->ws + 2 * K * E;
+  st = launch_status(bg::cobg_amplitudes(n, fp32, E, r->mom, r->hel, 0, amp, s));
+  if (!st) st = launch_status(bg::contract_y((int)K, E, amp, ctx->C_dev[n], Y, r->me2, s));
+  if (!st)
+    st = launch_status(
+        bg::cobg_gradient(n, fp32, E, r->mom, r->hel, Y, grad_me2, ctx->perms_dev[n], grad_mom, s));
+  return st;
 }
 
 int bg_me2_batch(bg_context* ctx, const bg_request* segs, int n_segs, void* stream) {

@@ -110,33 +110,72 @@ __device__ __forceinline__ void v4_acc(C4<T>& acc, const C4<T>& J1, const C4<T>&
   }
 }
 
+// First-order dual number for forward-mode derivatives of the polarization.
+struct Dual {
+  double v, d;
+};
+__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+__device__ __forceinline__ Dual operator*(double a, Dual b) { return {a * b.v, a * b.d}; }
+__device__ __forceinline__ Dual dsqrt_inv(Dual a) {  // 1/sqrt(a)
+  const double r = 1.0 / sqrt(a.v);
+  return {r, -0.5 * r * r * r * a.d};
+}
+__device__ __forceinline__ double dval(double x) { return x; }
+__device__ __forceinline__ double dval(Dual x) { return x.v; }
+__device__ __forceinline__ double dsqrt_inv(double a) { return 1.0 / sqrt(a); }
+
 // External current (eps^h(k))* = (e1 - i h e2)/sqrt2 for the all-outgoing
-// momentum p (FP64), in the light-cone gauge whose gauge vector q = (|k|, -k)
-// points against the gluon (purely spatial, unit polarizations):
+// momentum p, in the light-cone gauge whose gauge vector q = (|k|, -k) points
+// against the gluon (purely spatial, unit polarizations):
 //   k = sign(p^0) p,  e1 = (r |k|^2 - (r.k) k) / |r |k|^2 - (r.k) k|,
 //   e2 = (k x e1) / |k|,  e1^0 = e2^0 = 0,  r = (3, -6, 2)/7.
-__device__ __forceinline__ void polarization(const double p[4], int h, double er[4],
-                                             double ei[4]) {
-  const double s = p[0] > 0.0 ? 1.0 : -1.0;
-  const double k1 = s * p[1], k2 = s * p[2], k3 = s * p[3];
-  const double kk = k1 * k1 + k2 * k2 + k3 * k3;
-  const double rk = kR1 * k1 + kR2 * k2 + kR3 * k3;
-  const double v1 = kR1 * kk - rk * k1, v2 = kR2 * kk - rk * k2, v3 = kR3 * kk - rk * k3;
-  const double inv_nv = 1.0 / sqrt(v1 * v1 + v2 * v2 + v3 * v3);
-  const double e1x = v1 * inv_nv, e1y = v2 * inv_nv, e1z = v3 * inv_nv;
-  const double inv_kap = 1.0 / sqrt(kk);
-  const double e2x = (k2 * e1z - k3 * e1y) * inv_kap;
-  const double e2y = (k3 * e1x - k1 * e1z) * inv_kap;
-  const double e2z = (k1 * e1y - k2 * e1x) * inv_kap;
+// R = double, or Dual for derivatives.
+template <typename R>
+__device__ __forceinline__ void polarization_t(const R p[4], int h, R er[4], R ei[4]) {
+  const double s = dval(p[0]) > 0.0 ? 1.0 : -1.0;
+  const R k1 = s * p[1], k2 = s * p[2], k3 = s * p[3];
+  const R kk = k1 * k1 + k2 * k2 + k3 * k3;
+  const R rk = kR1 * k1 + kR2 * k2 + kR3 * k3;
+  const R v1 = kR1 * kk - rk * k1, v2 = kR2 * kk - rk * k2, v3 = kR3 * kk - rk * k3;
+  const R inv_nv = dsqrt_inv(v1 * v1 + v2 * v2 + v3 * v3);
+  const R e1x = v1 * inv_nv, e1y = v2 * inv_nv, e1z = v3 * inv_nv;
+  const R inv_kap = dsqrt_inv(kk);
+  const R e2x = (k2 * e1z - k3 * e1y) * inv_kap;
+  const R e2y = (k3 * e1x - k1 * e1z) * inv_kap;
+  const R e2z = (k1 * e1y - k2 * e1x) * inv_kap;
   const double c = -(h > 0 ? 1.0 : -1.0) * kInvSqrt2;
-  er[0] = 0.0;
-  er[1] = e1x * kInvSqrt2;
-  er[2] = e1y * kInvSqrt2;
-  er[3] = e1z * kInvSqrt2;
-  ei[0] = 0.0;
+  er[0] = 0.0 * e1x;
+  er[1] = kInvSqrt2 * e1x;
+  er[2] = kInvSqrt2 * e1y;
+  er[3] = kInvSqrt2 * e1z;
+  ei[0] = 0.0 * e2x;
   ei[1] = c * e2x;
   ei[2] = c * e2y;
   ei[3] = c * e2z;
+}
+
+__device__ __forceinline__ void polarization(const double p[4], int h, double er[4],
+                                             double ei[4]) {
+  polarization_t<double>(p, h, er, ei);
+}
+
+// d eps_mu / d p^nu: dre[nu][mu], dim[nu][mu]
+__device__ __forceinline__ void polarization_jacobian(const double p[4], int h, double dre[4][4],
+                                                      double dim[4][4]) {
+#pragma unroll
+  for (int nu = 0; nu < 4; ++nu) {
+    Dual pd[4], er[4], ei[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) pd[m] = Dual{p[m], m == nu ? 1.0 : 0.0};
+    polarization_t<Dual>(pd, h, er, ei);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      dre[nu][m] = er[m].d;
+      dim[nu][m] = ei[m].d;
+    }
+  }
 }
 
 }  // namespace bg

@@ -29,6 +29,24 @@ inline int64_t factorial(int k) {
 int cobg_amplitudes(int n, bool fp32, int64_t E, const double* mom, const int8_t* hel, int hconf,
                     double* amp, hipStream_t stream);
 
+// Gradient of sum_st C_st Re(A_s conj(A_t)) scaled by gme2[e] (null = 1),
+// given Y = C A [2][K][E]; perms [K][n-2] lists the middle gluons of each
+// ordering; grad [n][4][E].
+int cobg_gradient(int n, bool fp32, int64_t E, const double* mom, const int8_t* hel,
+                  const double* Y, const double* gme2, const uint8_t* perms, double* grad,
+                  hipStream_t stream);
+
+// Y = C A [2][K][E] and me2 = Re sum A^* Y (FP64, one event per lane).
+int contract_y(int K, int64_t E, const double* amp, const double* C, double* Y, double* me2,
+               hipStream_t stream);
+
+// Colour-dressed |A|^2 for one colour-flow assignment per event.  ws holds
+// 2 + E unsigned (counters, compacted list of valid events); grid is the
+// number of persistent one-wave blocks.
+int cdbg_me2(int n, bool fp32, int64_t E, const double* mom, const int8_t* hel, const int8_t* col,
+             unsigned* ws, double* me2, int grid, hipStream_t stream);
+size_t cdbg_lds_bytes(int n, bool fp32);
+
 // me2[e] (+)= sum_st C_st Re(A_s conj(A_t)); C is K x K row-major on device.
 int contract_valu(int K, int64_t E, const double* amp, const double* C, double* me2,
                   int accumulate, hipStream_t stream);

@@ -130,6 +130,37 @@ int mfma_probe(double* out_dev, hipStream_t stream) {
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// Y = C A per event (both planes) and me2 = x.Cx + y.Cy, for the gradient.
+__global__ void __launch_bounds__(256) contract_y_kernel(int K, int64_t E,
+                                                        const double* __restrict__ amp,
+                                                        const double* __restrict__ C,
+                                                        double* __restrict__ Y,
+                                                        double* __restrict__ me2) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  double acc = 0.0;
+  for (int s = 0; s < K; ++s) {
+    double zx = 0.0, zy = 0.0;
+    for (int t = 0; t < K; ++t) {
+      const double c = C[s * K + t];
+      zx += c * amp[(int64_t)t * E + e];
+      zy += c * amp[((int64_t)K + t) * E + e];
+    }
+    Y[(int64_t)s * E + e] = zx;
+    Y[((int64_t)K + s) * E + e] = zy;
+    acc += amp[(int64_t)s * E + e] * zx + amp[((int64_t)K + s) * E + e] * zy;
+  }
+  if (me2) me2[e] = acc;
+}
+
+int contract_y(int K, int64_t E, const double* amp, const double* C, double* Y, double* me2,
+               hipStream_t stream) {
+  if (E <= 0) return 0;
+  hipLaunchKernelGGL(contract_y_kernel, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, stream, K,
+                     E, amp, C, Y, me2);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int contract_valu(int K, int64_t E, const double* amp, const double* C, double* me2,
                   int accumulate, hipStream_t stream) {
   if (E <= 0) return 0;
