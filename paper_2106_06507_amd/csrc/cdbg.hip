@@ -1,497 +1,8 @@
-// Colour-dressed Berends-Giele recursion (Section 2.3, eqs. cdcurrents and
-// color_dressed_currents, with the tensor auxiliary field of eqs. prop_pseudo,
-// cobg_tensor_current and cobg_tensor_vertex) for one sampled colour-flow
-// assignment per event (Section 2.2, eq. color_decomposition_colorflow).
-//
-// Colour structure.  Gluon k carries E_k = e_{j_k i_k}, a directed edge
-// j_k -> i_k between the three colours.  The dressed current of a subset S is
-// the sum over orderings of E_s1..E_sk J(s), so its 3x3 colour matrix is
-// non-zero only in entries (r, c) such that the edges of S form a trail from
-// r to c: if S is balanced (in = out degree at every colour) only diagonal
-// entries (v, v) with v touched by S survive; otherwise exactly one entry
-// (r, c) with out-in = +1 at r and -1 at c.  A subset whose edges are not
-// connected, or whose degrees allow no trail, has a zero current.  Each subset
-// therefore stores three slots: slot v = entry (v, v) when balanced, slot 0 =
-// entry (r, c) otherwise.  The matrix product J(S1) J(S2) in the recursion
-// then selects one operand pair per target slot:
-//   S1 (r1,c1), S2 (r2,c2):  needs c1 = r2, gives (r1, c2)
-//   S1 (r1,c1), S2 balanced: slots (0, c1) -> (r1, c1)
-//   S1 balanced, S2 (r2,c2): slots (r2, 0) -> (r2, c2)
-//   both balanced:           slots (v, v) -> (v, v).
-// An event's full amplitude is non-zero only if all n edges form a closed
-// circuit (balanced and connected); other events get exactly 0.
-//
-// Recursion (couplings g_s/sqrt2 factored out as in bg_device.h), summed over
-// ordered splits (S1, S2) of S:
-//   J(S) = 1/P_S^2 sum [ V3(P1, P2; J1, J2) + T2.J1 - T1.J2 ],
-//   T(S) = sum [ J1^a J2^b - J1^b J2^a ],     (T.J)^nu = T^{nu beta} J_beta,
-// and A = (g_s/sqrt2)^(n-2) eps_n . (P^2 J)_{i_n j_n}(1..n-1).
-//
-// Parallel layout (gfx950): one 64-lane wave per valid event, persistent
-// blocks pulling events from a compacted list.  Currents, tensors, momenta and
-// 1/P^2 of all subsets live in LDS.  Subsets are processed by size; the
-// (subset, slot) targets of a size are spread over the lanes, and when there
-// are fewer targets than lanes each target's splits are shared by q lanes
-// whose partial sums are added in a fixed order (deterministic results).
-#include <stdint.h>
-
-#include "bg_device.h"
-#include "bg_kernels.h"
+// Launchers of the colour-dressed recursion (templates in cdbg_impl.h).
+#include "cdbg_impl.h"
 
 namespace bg {
 namespace cdbgk {
-
-constexpr int kWave = 64;
-
-// LDS layout of one event (T = float or double), M = n - 1 gluons in subsets
-template <int N, typename T>
-struct Lay {
-  static constexpr int M = N - 1;
-  static constexpr int NS = 1 << M;          // subsets (mask 0 unused)
-  static constexpr int kJ = NS * 3 * 8;      // currents [mask][slot][re0..3, im0..3]
-  static constexpr int kT = NS * 3 * 12;     // tensors  [mask][slot][re6, im6]
-  static constexpr int kP = NS * 4;          // momenta  [mask][mu]
-  static constexpr int kI = NS;              // 1/P^2    [mask]
-  static constexpr int kPart = kWave * 20;   // partial sums [lane][8 + 12]
-  static constexpr int kItems = NS * 3;      // target list of one size
-  static constexpr size_t bytes() {
-    return sizeof(T) * (size_t)(kJ + kT + kP + kI + kPart) + sizeof(int) * (size_t)(NS + kItems + 2 * N + 4);
-  }
-};
-
-template <int N, typename T>
-struct Sm {
-  T* J;
-  T* Tt;
-  T* P;
-  T* ip2;
-  T* part;
-  int* code;   // per mask: 0 zero; 1 | r << 2 | c << 4 unbalanced; 2 | touched << 6 balanced
-  int* items;
-  int* ci;     // colours i_k
-  int* cj;     // colours j_k
-  int* misc;
-};
-
-template <int N, typename T>
-__device__ __forceinline__ Sm<N, T> carve(unsigned char* raw) {
-  using L = Lay<N, T>;
-  Sm<N, T> s;
-  T* t = reinterpret_cast<T*>(raw);
-  s.J = t;
-  s.Tt = s.J + L::kJ;
-  s.P = s.Tt + L::kT;
-  s.ip2 = s.P + L::kP;
-  s.part = s.ip2 + L::kI;
-  int* ip = reinterpret_cast<int*>(s.part + L::kPart);
-  s.code = ip;
-  s.items = s.code + L::NS;
-  s.ci = s.items + L::kItems;
-  s.cj = s.ci + N;
-  s.misc = s.cj + N;
-  return s;
-}
-
-// (T.J)^nu = T^{nu beta} g_beta beta J^beta for antisymmetric T stored as
-// components (01, 02, 03, 12, 13, 23); acc += sgn * T.J (complex).
-template <typename T>
-__device__ __forceinline__ void tdotj_acc(T* gre, T* gim, const T* tre, const T* tim,
-                                          const T* jre, const T* jim, T sgn) {
-  // complex product helper: (a + ib)(c + id)
-#define BG_CM(ar, ai, br, bi, outr, outi) \
-  outr = (ar) * (br) - (ai) * (bi);      \
-  outi = (ar) * (bi) + (ai) * (br);
-  T r, i, sr, si;
-  // nu = 0: -(T01 J1 + T02 J2 + T03 J3)
-  sr = 0; si = 0;
-  BG_CM(tre[0], tim[0], jre[1], jim[1], r, i) sr += r; si += i;
-  BG_CM(tre[1], tim[1], jre[2], jim[2], r, i) sr += r; si += i;
-  BG_CM(tre[2], tim[2], jre[3], jim[3], r, i) sr += r; si += i;
-  gre[0] -= sgn * sr; gim[0] -= sgn * si;
-  // nu = 1: -T01 J0 - T12 J2 - T13 J3
-  sr = 0; si = 0;
-  BG_CM(tre[0], tim[0], jre[0], jim[0], r, i) sr += r; si += i;
-  BG_CM(tre[3], tim[3], jre[2], jim[2], r, i) sr += r; si += i;
-  BG_CM(tre[4], tim[4], jre[3], jim[3], r, i) sr += r; si += i;
-  gre[1] -= sgn * sr; gim[1] -= sgn * si;
-  // nu = 2: -T02 J0 + T12 J1 - T23 J3
-  BG_CM(tre[1], tim[1], jre[0], jim[0], r, i) sr = -r; si = -i;
-  BG_CM(tre[3], tim[3], jre[1], jim[1], r, i) sr += r; si += i;
-  BG_CM(tre[5], tim[5], jre[3], jim[3], r, i) sr -= r; si -= i;
-  gre[2] += sgn * sr; gim[2] += sgn * si;
-  // nu = 3: -T03 J0 + T13 J1 + T23 J2
-  BG_CM(tre[2], tim[2], jre[0], jim[0], r, i) sr = -r; si = -i;
-  BG_CM(tre[4], tim[4], jre[1], jim[1], r, i) sr += r; si += i;
-  BG_CM(tre[5], tim[5], jre[2], jim[2], r, i) sr += r; si += i;
-  gre[3] += sgn * sr; gim[3] += sgn * si;
-#undef BG_CM
-}
-
-// Operand slots of split (S1, S2) feeding target slot t of S; false if none.
-__device__ __forceinline__ bool split_slots(int c1, int c2, int t, int& s1, int& s2) {
-  if (c1 == 0 || c2 == 0) return false;
-  const bool b1 = (c1 & 3) == 2, b2 = (c2 & 3) == 2;
-  if (!b1 && !b2) {
-    const int r1 = (c1 >> 2) & 3, cc1 = (c1 >> 4) & 3;
-    const int r2 = (c2 >> 2) & 3, cc2 = (c2 >> 4) & 3;
-    if (cc1 != r2) return false;
-    const int tt = (r1 == cc2) ? r1 : 0;
-    if (tt != t) return false;
-    s1 = 0;
-    s2 = 0;
-    return true;
-  }
-  if (!b1 && b2) {
-    if (t != 0) return false;
-    s1 = 0;
-    s2 = (c1 >> 4) & 3;
-    return true;
-  }
-  if (b1 && !b2) {
-    if (t != 0) return false;
-    s1 = (c2 >> 2) & 3;
-    s2 = 0;
-    return true;
-  }
-  s1 = t;
-  s2 = t;
-  return true;
-}
-
-// Accumulate the contribution of split (m1, m2) with operand slots (s1, s2).
-template <int N, typename T>
-__device__ __forceinline__ void split_contrib(const Sm<N, T>& sm, int m1, int m2, int s1, int s2,
-                                              bool want_tensor, T* gre, T* gim, T* tre, T* tim) {
-  const T* J1 = sm.J + (m1 * 3 + s1) * 8;
-  const T* J2 = sm.J + (m2 * 3 + s2) * 8;
-  T a_re[4], a_im[4], b_re[4], b_im[4], P1[4], P2[4];
-#pragma unroll
-  for (int mu = 0; mu < 4; ++mu) {
-    a_re[mu] = J1[mu];
-    a_im[mu] = J1[4 + mu];
-    b_re[mu] = J2[mu];
-    b_im[mu] = J2[4 + mu];
-    P1[mu] = sm.P[m1 * 4 + mu];
-    P2[mu] = sm.P[m2 * 4 + mu];
-  }
-  // V3(P1, P2; J1, J2) = (J1.J2)(P1-P2) + ((2P2+P1).J1) J2 - ((2P1+P2).J2) J1
-  T abr = a_re[0] * b_re[0] - a_im[0] * b_im[0];
-  T abi = a_re[0] * b_im[0] + a_im[0] * b_re[0];
-  T c1r = (T(2) * P2[0] + P1[0]) * a_re[0], c1i = (T(2) * P2[0] + P1[0]) * a_im[0];
-  T c2r = (T(2) * P1[0] + P2[0]) * b_re[0], c2i = (T(2) * P1[0] + P2[0]) * b_im[0];
-#pragma unroll
-  for (int mu = 1; mu < 4; ++mu) {
-    abr -= a_re[mu] * b_re[mu] - a_im[mu] * b_im[mu];
-    abi -= a_re[mu] * b_im[mu] + a_im[mu] * b_re[mu];
-    const T q = T(2) * P2[mu] + P1[mu], p = T(2) * P1[mu] + P2[mu];
-    c1r -= q * a_re[mu];
-    c1i -= q * a_im[mu];
-    c2r -= p * b_re[mu];
-    c2i -= p * b_im[mu];
-  }
-#pragma unroll
-  for (int mu = 0; mu < 4; ++mu) {
-    const T d = P1[mu] - P2[mu];
-    gre[mu] += abr * d + (c1r * b_re[mu] - c1i * b_im[mu]) - (c2r * a_re[mu] - c2i * a_im[mu]);
-    gim[mu] += abi * d + (c1r * b_im[mu] + c1i * b_re[mu]) - (c2r * a_im[mu] + c2i * a_re[mu]);
-  }
-  // tensor couplings: + T2.J1 - T1.J2
-  const T* T1 = sm.Tt + (m1 * 3 + s1) * 12;
-  const T* T2 = sm.Tt + (m2 * 3 + s2) * 12;
-  {
-    T t_re[6], t_im[6];
-#pragma unroll
-    for (int x = 0; x < 6; ++x) {
-      t_re[x] = T2[x];
-      t_im[x] = T2[6 + x];
-    }
-    tdotj_acc(gre, gim, t_re, t_im, a_re, a_im, T(1));
-#pragma unroll
-    for (int x = 0; x < 6; ++x) {
-      t_re[x] = T1[x];
-      t_im[x] = T1[6 + x];
-    }
-    tdotj_acc(gre, gim, t_re, t_im, b_re, b_im, T(-1));
-  }
-  if (want_tensor) {
-    // antisymmetric J1^a J2^b - J1^b J2^a for (ab) = 01, 02, 03, 12, 13, 23
-    const int ia[6] = {0, 0, 0, 1, 1, 2};
-    const int ib[6] = {1, 2, 3, 2, 3, 3};
-#pragma unroll
-    for (int x = 0; x < 6; ++x) {
-      const int a = ia[x], b = ib[x];
-      tre[x] += (a_re[a] * b_re[b] - a_im[a] * b_im[b]) - (a_re[b] * b_re[a] - a_im[b] * b_im[a]);
-      tim[x] += (a_re[a] * b_im[b] + a_im[a] * b_re[b]) - (a_re[b] * b_im[a] + a_im[b] * b_re[a]);
-    }
-  }
-}
-
-// Valid-flow classification and compaction: edges j_k -> i_k must be
-// balanced and connected.  Invalid events get me2 = 0.
-__global__ void __launch_bounds__(256) cdbg_classify_kernel(int n, int64_t E,
-                                                           const int8_t* __restrict__ col,
-                                                           double* __restrict__ me2,
-                                                           unsigned* __restrict__ list,
-                                                           unsigned* __restrict__ count) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool valid = false;
-  if (e < E) {
-    int deg[3] = {0, 0, 0};
-    int par[3] = {0, 1, 2};
-    int touched = 0;
-    bool in_range = true;
-    for (int k = 0; k < n; ++k) {
-      int ii = col[(int64_t)k * E + e];
-      int jj = col[((int64_t)n + k) * E + e];
-      if (ii < 0 || ii > 2 || jj < 0 || jj > 2) {  // not a colour: the event is invalid
-        in_range = false;
-        ii = 0;
-        jj = 0;
-      }
-      deg[jj] += 1;
-      deg[ii] -= 1;
-      touched |= (1 << ii) | (1 << jj);
-      int a = jj, b = ii;
-      while (par[a] != a) a = par[a];
-      while (par[b] != b) b = par[b];
-      if (a != b) par[a] = b;
-    }
-    bool conn = true;
-    int root = -1;
-    for (int v = 0; v < 3; ++v) {
-      if (!(touched & (1 << v))) continue;
-      int a = v;
-      while (par[a] != a) a = par[a];
-      if (root < 0) root = a;
-      else if (a != root) conn = false;
-    }
-    valid = in_range && conn && deg[0] == 0 && deg[1] == 0 && deg[2] == 0;
-    if (!valid) me2[e] = 0.0;
-  }
-  // one atomic per wave
-  const unsigned long long bal = __ballot(valid);
-  const int lane = threadIdx.x & 63;
-  unsigned base = 0;
-  if (lane == 0 && bal) base = atomicAdd(count, (unsigned)__popcll(bal));
-  base = __shfl(base, 0);
-  if (valid) {
-    const unsigned long long below = lane ? (bal & ((~0ull) >> (64 - lane))) : 0ull;
-    list[base + __popcll(below)] = (unsigned)e;
-  }
-}
-
-template <int N, typename T>
-__global__ void __launch_bounds__(64) cdbg_event_kernel(int64_t E, const double* __restrict__ mom,
-                                                       const int8_t* __restrict__ hel,
-                                                       const int8_t* __restrict__ col,
-                                                       const unsigned* __restrict__ list,
-                                                       const unsigned* __restrict__ count,
-                                                       unsigned* __restrict__ work,
-                                                       double* __restrict__ me2) {
-  using L = Lay<N, T>;
-  constexpr int M = N - 1;
-  constexpr int NS = L::NS;
-  extern __shared__ __align__(16) unsigned char bg_cdbg_lds[];
-  Sm<N, T> sm = carve<N, T>(bg_cdbg_lds);
-  const int lane = threadIdx.x;
-  const unsigned total = *count;
-  for (;;) {
-    unsigned idx = 0;
-    if (lane == 0) idx = atomicAdd(work, 1u);
-    idx = __shfl(idx, 0);
-    if (idx >= total) break;
-    const int64_t e = list[idx];
-
-    // ---- event set-up -------------------------------------------------
-    for (int x = lane; x < L::kJ; x += kWave) sm.J[x] = T(0);
-    for (int x = lane; x < L::kT; x += kWave) sm.Tt[x] = T(0);
-    if (lane < N) {
-      sm.ci[lane] = col[(int64_t)lane * E + e];
-      sm.cj[lane] = col[((int64_t)N + lane) * E + e];
-    }
-    __syncthreads();
-    // subset codes, momenta, 1/P^2 (FP64 sums)
-    for (int mask = lane + 1; mask < NS; mask += kWave) {
-      double q[4] = {0.0, 0.0, 0.0, 0.0};
-      int deg[3] = {0, 0, 0};
-      int par[3] = {0, 1, 2};
-      int touched = 0;
-      for (int k = 0; k < M; ++k) {
-        if (!(mask & (1 << k))) continue;
-#pragma unroll
-        for (int mu = 0; mu < 4; ++mu) q[mu] += mom[((int64_t)k * 4 + mu) * E + e];
-        const int ii = sm.ci[k], jj = sm.cj[k];
-        deg[jj] += 1;
-        deg[ii] -= 1;
-        touched |= (1 << ii) | (1 << jj);
-        int a = jj, b = ii;
-        while (par[a] != a) a = par[a];
-        while (par[b] != b) b = par[b];
-        if (a != b) par[a] = b;
-      }
-      bool conn = true;
-      int root = -1;
-      for (int v = 0; v < 3; ++v) {
-        if (!(touched & (1 << v))) continue;
-        int a = v;
-        while (par[a] != a) a = par[a];
-        if (root < 0) root = a;
-        else if (a != root) conn = false;
-      }
-      int code = 0;
-      if (conn) {
-        if (deg[0] == 0 && deg[1] == 0 && deg[2] == 0) {
-          code = 2 | (touched << 6);
-        } else {
-          int r = -1, c = -1, bad = 0;
-          for (int v = 0; v < 3; ++v) {
-            if (deg[v] == 1) r = v;
-            else if (deg[v] == -1) c = v;
-            else if (deg[v] != 0) bad = 1;
-          }
-          if (!bad && r >= 0 && c >= 0) code = 1 | (r << 2) | (c << 4);
-        }
-      }
-      sm.code[mask] = code;
-#pragma unroll
-      for (int mu = 0; mu < 4; ++mu) sm.P[mask * 4 + mu] = (T)q[mu];
-      const double p2 = q[0] * q[0] - q[1] * q[1] - q[2] * q[2] - q[3] * q[3];
-      sm.ip2[mask] = (T)(1.0 / p2);
-    }
-    // external currents of gluons 0..M-1 into their colour slot
-    if (lane < M) {
-      double p[4], er[4], ei[4];
-#pragma unroll
-      for (int mu = 0; mu < 4; ++mu) p[mu] = mom[((int64_t)lane * 4 + mu) * E + e];
-      polarization(p, (int)hel[(int64_t)lane * E + e], er, ei);
-      const int ii = sm.ci[lane], jj = sm.cj[lane];
-      const int slot = (ii == jj) ? jj : 0;
-      T* dst = sm.J + ((1 << lane) * 3 + slot) * 8;
-#pragma unroll
-      for (int mu = 0; mu < 4; ++mu) {
-        dst[mu] = (T)er[mu];
-        dst[4 + mu] = (T)ei[mu];
-      }
-    }
-    __syncthreads();
-
-    // ---- recursion by subset size ---------------------------------------
-    for (int size = 2; size <= M; ++size) {
-      const bool top = size == M;
-      // targets (mask, slot) of this size
-      int nitems = 0;
-      if (top) {
-        if (lane == 0) {
-          const int ii = sm.ci[M], jj = sm.cj[M];  // last gluon: entry (i_n, j_n)
-          sm.items[0] = (NS - 1) * 4 + (ii == jj ? ii : 0);
-        }
-        nitems = 1;
-      } else {
-        for (int base = 0; base < NS; base += kWave) {
-          const int mask = base + lane;
-          int code = 0;
-          if (mask > 0 && mask < NS && __popc(mask) == size) code = sm.code[mask];
-          for (int t = 0; t < 3; ++t) {
-            bool ok = false;
-            if ((code & 3) == 1) ok = (t == 0);
-            else if ((code & 3) == 2) ok = ((code >> 6) >> t) & 1;
-            const unsigned long long bal = __ballot(ok);
-            const unsigned long long below = lane ? (bal & ((~0ull) >> (64 - lane))) : 0ull;
-            if (ok) sm.items[nitems + __popcll(below)] = mask * 4 + t;
-            nitems += __popcll(bal);
-          }
-        }
-      }
-      __syncthreads();
-      // lanes per target
-      int q = 1;
-      while (q * 2 * nitems <= kWave && q < 32) q *= 2;
-      const int per_round = kWave / q;
-      for (int r0 = 0; r0 < nitems; r0 += per_round) {
-        const int it = r0 + lane / q;
-        const int sub = lane % q;
-        T gre[4] = {0, 0, 0, 0}, gim[4] = {0, 0, 0, 0};
-        T tre[6] = {0, 0, 0, 0, 0, 0}, tim[6] = {0, 0, 0, 0, 0, 0};
-        int S = 0, t = 0;
-        if (it < nitems) {
-          const int item = sm.items[it];
-          S = item >> 2;
-          t = item & 3;
-          int k = 0;
-          for (int m1 = (S - 1) & S; m1; m1 = (m1 - 1) & S, ++k) {
-            if ((k % q) != sub) continue;
-            const int m2 = S ^ m1;
-            int s1, s2;
-            if (!split_slots(sm.code[m1], sm.code[m2], t, s1, s2)) continue;
-            split_contrib<N, T>(sm, m1, m2, s1, s2, !top, gre, gim, tre, tim);
-          }
-        }
-        // fixed-order reduction over the q lanes of a target
-        T* mine = sm.part + lane * 20;
-#pragma unroll
-        for (int x = 0; x < 4; ++x) {
-          mine[x] = gre[x];
-          mine[4 + x] = gim[x];
-        }
-#pragma unroll
-        for (int x = 0; x < 6; ++x) {
-          mine[8 + x] = tre[x];
-          mine[14 + x] = tim[x];
-        }
-        __syncthreads();
-        if (it < nitems && sub == 0) {
-          for (int o = 1; o < q; ++o) {
-            const T* other = sm.part + (lane + o) * 20;
-#pragma unroll
-            for (int x = 0; x < 4; ++x) {
-              gre[x] += other[x];
-              gim[x] += other[4 + x];
-            }
-#pragma unroll
-            for (int x = 0; x < 6; ++x) {
-              tre[x] += other[8 + x];
-              tim[x] += other[14 + x];
-            }
-          }
-          if (top) {
-            double p[4], er[4], ei[4];
-#pragma unroll
-            for (int mu = 0; mu < 4; ++mu) p[mu] = mom[((int64_t)M * 4 + mu) * E + e];
-            polarization(p, (int)hel[(int64_t)M * E + e], er, ei);
-            double ar = 0.0, ai = 0.0;
-#pragma unroll
-            for (int mu = 0; mu < 4; ++mu) {
-              const double sg = mu == 0 ? 1.0 : -1.0;
-              ar += sg * (er[mu] * (double)gre[mu] - ei[mu] * (double)gim[mu]);
-              ai += sg * (er[mu] * (double)gim[mu] + ei[mu] * (double)gre[mu]);
-            }
-            double scale = 1.0;
-#pragma unroll
-            for (int i = 0; i < N - 2; ++i) scale *= kGsOverSqrt2;
-            ar *= scale;
-            ai *= scale;
-            me2[e] = ar * ar + ai * ai;
-          } else {
-            const T ip = sm.ip2[S];
-            T* dj = sm.J + (S * 3 + t) * 8;
-            T* dt = sm.Tt + (S * 3 + t) * 12;
-#pragma unroll
-            for (int x = 0; x < 4; ++x) {
-              dj[x] = gre[x] * ip;
-              dj[4 + x] = gim[x] * ip;
-            }
-#pragma unroll
-            for (int x = 0; x < 6; ++x) {
-              dt[x] = tre[x];
-              dt[6 + x] = tim[x];
-            }
-          }
-        }
-        __syncthreads();
-      }
-    }
-  }
-}
 
 __global__ void zero_u32_kernel(unsigned* p, int n) {
   if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;

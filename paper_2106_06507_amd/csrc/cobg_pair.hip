@@ -1,295 +1,9 @@
-// Colour-ordered Berends-Giele recursion (Section 2.3, eqs. cobg and
-// cobg_full_amplitude) for all (n-2)! orderings A(1, sigma, n) of the adjoint
-// basis (Section 2.2, eq. color_decomposition_adjoint), one event per lane
-// PAIR.
-//
-// Layout.  Lanes 2p and 2p+1 of a wave hold event p of the block's 32 events.
-// Lane half h = lane & 1 owns Lorentz components 2h and 2h+1 of every current
-// and momentum, so the per-lane register and LDS state is half that of one
-// event per lane.  A Minkowski product is the sum of the two halves'
-// partials, exchanged between partners with one DPP quad_perm [1,0,3,2]
-// move (a + b and b + a are the same IEEE result, so both lanes hold
-// bit-identical scalars).  The metric sign of the lane's first component is a
-// per-lane constant g0 (+1 for h = 0, -1 for h = 1); the second is always -1.
-//
-// Walk.  Orderings are visited depth first in lexicographic order; position d
-// of (1, sigma_2, .., sigma_{n-1}) is a template level and the gluon placed
-// there a wave-uniform loop variable.  Entering level d builds the ranges
-// (a..d), a = d-1 .. 0; the shallower columns stay live in VGPRs and are
-// shared by every ordering with the same prefix.
-//
-// Per range R = (a..b) (couplings factored out, see bg_device.h):
-//   Jhat(R) = sum_k [ d_k (P_L - P_R) + c1_k J_R - c2_k J_L ]
-//           + sum_{j<k} [ 2 (X.Z) J_Y - (Y.Z) J_X - (X.Y) J_Z ],
-// L = (a..k), R = (k+1..b), X = (a..j), Y = (j+1..k), Z = (k+1..b),
-// d_k = J_L.J_R, c1_k = (2P_R + P_L).J_L, c2_k = (2P_L + P_R).J_R.  This is
-// V3 summed over splits plus V4 summed over triples with the coefficients of
-// each sub-current collected.  X.Y and Y.Z are the d's of ranges (a..k) and
-// (j+1..b), kept in a table when those ranges are built, so a V4 needs one new
-// product.  J(R) = Jhat(R) / P_R^2 with 1/P^2 taken from a per-event table
-// formed in FP64 from the FP64 momenta (rounded once for T = float); the full
-// range is amputated and contracted with eps_n.  Range momenta are
-// differences of FP64 prefix sums, rounded once to T.
-#include <stdint.h>
-
-#include <utility>
-
-#include "bg_device.h"
-#include "bg_kernels.h"
-#include "bg_pair.h"
+// Launchers of the lane-pair colour-ordered recursion (templates in
+// cobg_pair_impl.h).
+#include "cobg_pair_impl.h"
 
 namespace bg {
 namespace pairk {
-
-// LDS map per 64-lane block (32 events):
-//   T region, [slot][lane]: gluon g in 1..N-2 has eps half (4) and p half (2)
-//     at slots 6 (g-1) .. 6 (g-1) + 5;
-//   T region, [mask][pair]: 1/P_S^2 for subsets S of gluons 0..N-2;
-//   double region, [2 (g-1) + c][lane]: FP64 momentum halves of gluons 1..N-2.
-template <int N>
-struct Lds {
-  static constexpr int kLanes = 64;
-  static constexpr int kPairs = 32;
-  static constexpr int kGluonSlots = 6 * (N - 2);
-  static constexpr int kTabEntries = 1 << (N - 1);
-  template <typename T>
-  static constexpr size_t bytes() {
-    return sizeof(T) * ((size_t)kGluonSlots * kLanes + (size_t)kTabEntries * kPairs) +
-           sizeof(double) * (size_t)(2 * (N - 2)) * kLanes;
-  }
-};
-
-template <int N, typename T>
-struct Ctx {
-  T* gl_slots;      // [slot][lane]
-  T* tab;           // [mask][pair]
-  double* p64;      // [2 (g-1) + c][lane]
-  int lane, pair;
-  T g0;
-  H<T> epsN;
-  double* amp;
-  int64_t E, e;
-  int sigma;
-  int h;
-};
-
-template <int N, typename T>
-struct State {
-  static constexpr int M = N - 1;
-  H<T> J[M][M];
-  Cx<T> Dt[M][M][M];  // [a][b][k] = J(a..k).J(k+1..b)
-  HR<double> P0[M];   // prefix momenta P(0..b), FP64 halves
-  HR<T> Pg[M];        // momentum half of the gluon at each position
-  int gl[M];          // gluon at each position (wave-uniform)
-};
-
-template <int N, typename T, int A, int B>
-__device__ __forceinline__ HR<T> range_mom(const State<N, T>& s) {
-  HR<T> r;
-  if constexpr (A == B) {
-    r = s.Pg[A];
-  } else if constexpr (A == 0) {
-#pragma unroll
-    for (int m = 0; m < 2; ++m) r.v[m] = (T)s.P0[B].v[m];
-  } else {
-#pragma unroll
-    for (int m = 0; m < 2; ++m) r.v[m] = (T)(s.P0[B].v[m] - s.P0[A - 1].v[m]);
-  }
-  return r;
-}
-
-template <int N, typename T, int D, int A>
-__device__ __forceinline__ void build_range(State<N, T>& s, const Ctx<N, T>& c, int mask,
-                                            Cx<T>& top) {
-  constexpr int M = N - 1;
-  constexpr bool kTop = (A == 0 && D == M - 1);
-  constexpr int NS = D - A;
-  Cx<T> coefL[NS], coefR[NS];
-  H<T> acc;
-#pragma unroll
-  for (int m = 0; m < 2; ++m) {
-    acc.re[m] = T(0);
-    acc.im[m] = T(0);
-  }
-  // splits: three-gluon vertices
-  [&]<int... Ks>(std::integer_sequence<int, Ks...>) {
-    (
-        [&] {
-          constexpr int k = A + Ks;
-          const HR<T> PL = range_mom<N, T, A, k>(s);
-          const HR<T> PR = range_mom<N, T, k + 1, D>(s);
-          const Cx<T> d = hdot(s.J[A][k], s.J[k + 1][D], c.g0);
-          if constexpr (!kTop) s.Dt[A][D][k] = d;
-          HR<T> q2p, p2q, dif;
-#pragma unroll
-          for (int m = 0; m < 2; ++m) {
-            q2p.v[m] = T(2) * PR.v[m] + PL.v[m];
-            p2q.v[m] = T(2) * PL.v[m] + PR.v[m];
-            dif.v[m] = PL.v[m] - PR.v[m];
-          }
-          coefR[Ks] = hrdot(q2p, s.J[A][k], c.g0);
-          const Cx<T> c2 = hrdot(p2q, s.J[k + 1][D], c.g0);
-          coefL[Ks] = Cx<T>{-c2.re, -c2.im};
-          craxpy(acc, d, dif);
-        }(),
-        ...);
-  }(std::make_integer_sequence<int, NS>{});
-  // triples: four-gluon vertices
-#pragma unroll
-  for (int j = A; j < D; ++j) {
-#pragma unroll
-    for (int k = j + 1; k < D; ++k) {
-      const Cx<T> xy = s.Dt[A][k][j];
-      const Cx<T> yz = s.Dt[j + 1][D][k];
-      const Cx<T> xz = hdot(s.J[A][j], s.J[k + 1][D], c.g0);
-      coefL[j - A].re -= yz.re;
-      coefL[j - A].im -= yz.im;
-      coefR[k - A].re -= xy.re;
-      coefR[k - A].im -= xy.im;
-      caxpy(acc, Cx<T>{T(2) * xz.re, T(2) * xz.im}, s.J[j + 1][k]);
-    }
-  }
-#pragma unroll
-  for (int k = A; k < D; ++k) {
-    caxpy(acc, coefL[k - A], s.J[A][k]);
-    caxpy(acc, coefR[k - A], s.J[k + 1][D]);
-  }
-  if constexpr (kTop) {
-    top = hdot(c.epsN, acc, c.g0);
-  } else {
-    const T ip2 = c.tab[mask * Lds<N>::kPairs + c.pair];
-#pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      s.J[A][D].re[m] = acc.re[m] * ip2;
-      s.J[A][D].im[m] = acc.im[m] * ip2;
-    }
-  }
-}
-
-template <int N, typename T, int D, int A>
-__device__ __forceinline__ void build_column(State<N, T>& s, const Ctx<N, T>& c, int mask,
-                                             Cx<T>& top) {
-  if constexpr (A >= 0) {
-    mask |= 1 << s.gl[A];
-    build_range<N, T, D, A>(s, c, mask, top);
-    build_column<N, T, D, A - 1>(s, c, mask, top);
-  }
-}
-
-template <int N, typename T, int D>
-__device__ __forceinline__ void level(State<N, T>& s, Ctx<N, T>& c, int used) {
-  constexpr int M = N - 1;
-  for (int g = 1; g <= N - 2; ++g) {  // wave-uniform
-    if (used & (1 << g)) continue;
-    s.gl[D] = g;
-    const int base = 6 * (g - 1);
-#pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      s.J[D][D].re[m] = c.gl_slots[(base + m) * Lds<N>::kLanes + c.lane];
-      s.J[D][D].im[m] = c.gl_slots[(base + 2 + m) * Lds<N>::kLanes + c.lane];
-      s.Pg[D].v[m] = c.gl_slots[(base + 4 + m) * Lds<N>::kLanes + c.lane];
-      s.P0[D].v[m] = s.P0[D - 1].v[m] + c.p64[(2 * (g - 1) + m) * Lds<N>::kLanes + c.lane];
-    }
-    Cx<T> top;
-    build_column<N, T, D, D - 1>(s, c, 1 << g, top);
-    if constexpr (D == M - 1) {
-      double scale = 1.0;
-#pragma unroll
-      for (int i = 0; i < N - 2; ++i) scale *= kGsOverSqrt2;
-      constexpr int64_t K = Factorial<N - 2>::value;
-      const double v = (double)(c.h == 0 ? top.re : top.im) * scale;
-      c.amp[((int64_t)c.h * K + c.sigma) * c.E + c.e] = v;
-      ++c.sigma;
-    } else {
-      level<N, T, D + 1>(s, c, used | (1 << g));
-    }
-  }
-}
-
-template <int N, typename T>
-__global__ void __launch_bounds__(64) cobg_pair_kernel(int64_t E, const double* __restrict__ mom,
-                                                      const int8_t* __restrict__ hel, int hconf,
-                                                      double* __restrict__ amp) {
-  extern __shared__ __align__(16) unsigned char bg_pair_lds[];
-  constexpr int M = N - 1;
-  const int lane = threadIdx.x;
-  const int pair = lane >> 1;
-  const int h = lane & 1;
-  const int64_t e = (int64_t)blockIdx.x * Lds<N>::kPairs + pair;
-  if (e >= E) return;  // both lanes of a pair leave together
-
-  Ctx<N, T> c;
-  c.gl_slots = reinterpret_cast<T*>(bg_pair_lds);
-  c.tab = c.gl_slots + (size_t)Lds<N>::kGluonSlots * Lds<N>::kLanes;
-  c.p64 = reinterpret_cast<double*>(c.tab + (size_t)Lds<N>::kTabEntries * Lds<N>::kPairs);
-  c.lane = lane;
-  c.pair = pair;
-  c.h = h;
-  c.g0 = h == 0 ? T(1) : T(-1);
-  c.amp = amp;
-  c.E = E;
-  c.e = e;
-  c.sigma = 0;
-
-  double p[N][4];
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int m = 0; m < 4; ++m) p[i][m] = mom[((int64_t)i * 4 + m) * E + e];
-
-  State<N, T> s;
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    double er[4], ei[4];
-    const int hh = hel ? (int)hel[(int64_t)i * E + e] : (((hconf >> (N - 1 - i)) & 1) ? -1 : 1);
-    polarization(p[i], hh, er, ei);
-    // select this lane's two components as values (no indexed stack array)
-    const bool hi = h != 0;
-    H<T> cur;
-    cur.re[0] = (T)(hi ? er[2] : er[0]);
-    cur.re[1] = (T)(hi ? er[3] : er[1]);
-    cur.im[0] = (T)(hi ? ei[2] : ei[0]);
-    cur.im[1] = (T)(hi ? ei[3] : ei[1]);
-    double ph[2];
-    ph[0] = hi ? p[i][2] : p[i][0];
-    ph[1] = hi ? p[i][3] : p[i][1];
-    if (i == 0) {
-      s.J[0][0] = cur;
-#pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        s.Pg[0].v[m] = (T)ph[m];
-        s.P0[0].v[m] = ph[m];
-      }
-    } else if (i == N - 1) {
-      c.epsN = cur;
-    } else {
-      const int base = 6 * (i - 1);
-#pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        c.gl_slots[(base + m) * Lds<N>::kLanes + lane] = cur.re[m];
-        c.gl_slots[(base + 2 + m) * Lds<N>::kLanes + lane] = cur.im[m];
-        c.gl_slots[(base + 4 + m) * Lds<N>::kLanes + lane] = (T)ph[m];
-        c.p64[(2 * (i - 1) + m) * Lds<N>::kLanes + lane] = ph[m];
-      }
-    }
-  }
-  // 1/P_S^2 table: the two lanes of a pair fill alternate subsets
-  for (int mask = h; mask < (1 << M); mask += 2) {
-    double q[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int i = 0; i < M; ++i) {
-      if (mask & (1 << i)) {
-#pragma unroll
-        for (int m = 0; m < 4; ++m) q[m] += p[i][m];
-      }
-    }
-    const double p2 = q[0] * q[0] - q[1] * q[1] - q[2] * q[2] - q[3] * q[3];
-    c.tab[mask * Lds<N>::kPairs + pair] = (T)(1.0 / p2);
-  }
-  __syncthreads();
-  s.gl[0] = 0;
-  level<N, T, 1>(s, c, 1);
-}
 
 template <int N, typename T>
 int launch(int64_t E, const double* mom, const int8_t* hel, int hconf, double* amp,
