@@ -1,15 +1,23 @@
 """Benchmark: colour-summed |M|^2 events/s for gg -> 4g (n = 6 gluons).
 
-Workload: 2^20 RAMBO points at sqrt(s) = 1 TeV with p_T > 20 GeV and
+Headline workload: 2^20 RAMBO points at sqrt(s) = 1 TeV with p_T > 20 GeV and
 Delta R > 0.4, one uniformly sampled helicity configuration per event,
-colour-ordered recursion over the 24 orderings plus the 24 x 24 colour-matrix
-contraction (matrix cores).  One step = one bg_me2 call over the whole batch
-with inputs resident in HBM.  The headline path is FP32 complex currents with
-FP64 invariants and FP64 contraction; the plain FP64 path is timed beside it.
+colour-ordered recursion over the 24 orderings and the 24 x 24 colour sum.
+One step = one bg_me2 call over the whole batch with inputs resident in HBM;
+bg_me2 runs the recursion and the colour sum in one fused kernel.  The
+headline path is FP32 complex currents with FP64 invariants and FP64 colour
+sum; the plain FP64 path is timed beside it.
 
-Prints one JSON line (rank 0).  Only one GPU is used: --gpus above 1 exits.
+Further rows (same JSON line): the two-stage path with amplitudes through
+memory and the matrix-core contraction, the colour-dressed gg -> 6g workload
+(n = 8, sampled colour flows), the adjoint d|M|^2/dp for gg -> 4g (2^18
+events), and the mixed-multiplicity batch (n = 4..9) in one persistent launch
+replayed from a recorded graph.
+
+Prints one JSON line.  Only one GPU is used: --gpus above 1 exits.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -20,9 +28,24 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+CSRC = os.path.join(ROOT, "paper_2106_06507_amd", "csrc")
+# sources whose change invalidates the committed HBM counter readings of the
+# fused colour-ordered kernel
+FUSED_SOURCES = ["bg_device.h", "bg_pair.h", "cobg_pair_impl.h", "cdbg_impl.h", "fused_impl.h",
+                 "batch.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def fused_source_hash():
+    h = hashlib.sha256()
+    for f in FUSED_SOURCES:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def nonvanishing(hel):
@@ -33,22 +56,225 @@ def nonvanishing(hel):
 
 def rel_err_stats(got, ref):
     rel = np.abs(got - ref) / np.abs(ref)
-    return {"median": float(np.median(rel)), "p99": float(np.percentile(rel, 99)), "max": float(rel.max())}
+    return {"median": float(np.median(rel)), "p99": float(np.percentile(rel, 99)),
+            "max": float(rel.max())}
 
 
-def time_calls(fn, steps, warmup):
+def time_events(fn, steps, warmup):
+    """Average ms per call from HIP events recorded on the current stream
+    (the stream every entry point is given)."""
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
-    start.record()
+    start.record(s)
     for _ in range(steps):
         fn()
-    stop.record()
+    stop.record(s)
     torch.cuda.synchronize()
-    return start.elapsed_time(stop) / steps  # ms
+    return start.elapsed_time(stop) / steps
+
+
+def section_headline(args, api, wm, torch):
+    from bg_inputs import workload
+    n = 6
+    log(f"gg->4g inputs: {args.events} events")
+    ev = workload("gg_4g_n6", n_events=args.events)
+    E = ev["mom"].shape[2]
+    mom = torch.from_numpy(ev["mom"]).cuda()
+    hel = torch.from_numpy(ev["hel"]).cuda()
+    out = torch.empty(E, dtype=torch.float64, device="cuda")
+    ctx = api.default_context()
+
+    def step32():
+        api.me2(mom, hel, precision="fp32", out=out, ctx=ctx)
+
+    def step64():
+        api.me2(mom, hel, precision="fp64", out=out, ctx=ctx)
+
+    log("timing the fused FP32-recursion path (headline)")
+    for _ in range(args.warmup):
+        step32()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step32()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall * 1e3 / args.steps
+    # the step is one kernel launch: its average duration from HIP events
+    kms32 = time_events(step32, args.steps, 1)
+    me2_32 = out.cpu().numpy().copy()
+    log("timing the fused FP64 path")
+    kms64 = time_events(step64, max(3, args.steps // 2), 1)
+    me2_64 = out.cpu().numpy().copy()
+
+    log("timing the two-stage path (amplitudes through memory, matrix-core contraction)")
+    amp = torch.empty((2, 24, E), dtype=torch.float64, device="cuda")
+    import ctypes
+    from paper_2106_06507_amd._lib import check, lib
+
+    def rec32():
+        check(lib().bg_currents(ctx.handle, n, E, ctypes.c_void_p(mom.data_ptr()),
+                                ctypes.c_void_p(hel.data_ptr()), 1, ctypes.c_void_p(amp.data_ptr()),
+                                ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)),
+              "bg_currents")
+
+    rms32 = time_events(rec32, args.steps, 1)
+    amp_t = amp.clone()
+    cms = time_events(lambda: api.color_contract(amp_t, n, out=out, ctx=ctx), args.steps, 1)
+    two_stage = out.cpu().numpy().copy()
+
+    from oracle.me2 import me2_cobg
+    idx = np.sort(np.random.default_rng(7).choice(E, min(E, 256), replace=False))
+    ref = me2_cobg(ev["mom"][:, :, idx], ev["hel"][:, idx])
+    scale = me2_cobg(ev["mom"][:, :, idx], None) / 2 ** n  # helicity-averaged |M|^2
+    nz = nonvanishing(ev["hel"][:, idx])
+    err32 = rel_err_stats(me2_32[idx][nz], ref[nz])
+    err64 = rel_err_stats(me2_64[idx][nz], ref[nz])
+    err32["scale_relative_max"] = float((np.abs(me2_32[idx] - ref) / scale)[nz].max())
+    err64["scale_relative_max"] = float((np.abs(me2_64[idx] - ref) / scale)[nz].max())
+    nz_all = nonvanishing(ev["hel"])
+    err32_vs64 = rel_err_stats(me2_32[nz_all], me2_64[nz_all])
+    two_vs_fused = rel_err_stats(two_stage[nz_all], me2_32[nz_all])
+
+    rec_flops = wm.cobg_flops_per_event(n)
+    col_flops = wm.colour_sum_flops_per_event(n)
+    eq32 = rec_flops + 2 * col_flops  # FP32-equivalent: an FP64 flop costs two
+    achieved32 = eq32 * E / (kms32 * 1e-3) / 1e12
+    achieved64 = (rec_flops + col_flops) * E / (kms64 * 1e-3) / 1e12
+    cflop = wm.contraction_flops_per_event(n) * E / (cms * 1e-3) / 1e12
+
+    traffic = None
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+        k = t.get("cobg_fused_kernel<6,float,false>")
+        if k and k.get("source_hash") == fused_source_hash() and k.get("events") == E:
+            traffic = k["fetch_bytes"] + k["write_bytes"]
+    except (OSError, ValueError, KeyError):
+        traffic = None
+
+    row = {
+        "value": E / (ms_step * 1e-3), "ms_per_step": ms_step, "wall_s": wall,
+        "events": E, "kernel_ms": kms32,
+        "fp64_path": {"value": E / (kms64 * 1e-3), "kernel_ms": kms64},
+        "two_stage_fp32": {"value": E / ((rms32 + cms) * 1e-3), "recursion_ms": rms32,
+                           "contraction_mfma_ms": cms,
+                           "rel_diff_vs_fused_nonvanishing": two_vs_fused},
+        "rel_err_vs_oracle": {
+            "events": int(nz.sum()), "fp32_mixed": err32, "fp64": err64,
+            "fp32_vs_fp64_all_nonvanishing": err32_vs64,
+            "note": "per-event |d|/|ref| and scale-relative |d|/S_e with S_e the "
+                    "helicity-averaged |M|^2 of the event; configurations with a "
+                    "vanishing tree amplitude excluded"},
+        "roofline": {"bound": "alu", "kernel": "cobg_fused_kernel<6,float,false>",
+                     "achieved": achieved32, "peak": wm.PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved32 / wm.PEAK_FP32_VALU_TFLOPS, "traffic": traffic,
+                     "flops_per_event": eq32,
+                     "note": "FP32 recursion flops + 2 x FP64 colour-sum flops per event "
+                             "(FP64 vector rate is half the FP32 rate)"},
+        "roofline_fp64": {"bound": "alu", "kernel": "cobg_fused_kernel<6,double,false>",
+                          "achieved": achieved64, "peak": wm.PEAK_FP64_VALU_TFLOPS,
+                          "unit": "TFLOP/s", "frac": achieved64 / wm.PEAK_FP64_VALU_TFLOPS},
+        "roofline_contraction": {
+            "bound": "mfma", "kernel": "contract_mfma_kernel<32>", "achieved": cflop,
+            "peak": wm.PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+            "frac": cflop / wm.PEAK_FP64_MFMA_TFLOPS,
+            "hbm_GBs": wm.contraction_bytes_per_event(n) * E / (cms * 1e-3) / 1e9,
+            "hbm_frac": wm.contraction_bytes_per_event(n) * E / (cms * 1e-3) / 1e9 / wm.PEAK_HBM_GBS},
+    }
+    return row, ev
+
+
+def section_cdbg(args, api, torch):
+    from bg_inputs import workload
+    from oracle import cdbg as ocdbg
+    n = 8
+    log("gg->6g colour-dressed inputs")
+    ev = workload("gg_6g_n8_colour", n_events=args.events)
+    E = ev["mom"].shape[2]
+    mom, hel, col = (torch.from_numpy(ev[k]).cuda() for k in ("mom", "hel", "col"))
+    out = torch.empty(E, dtype=torch.float64, device="cuda")
+    steps = max(2, args.steps // 4)
+    ms = {}
+    res = {}
+    for p in ("fp32", "fp64"):
+        log(f"timing colour-dressed {p}")
+        ms[p] = time_events(lambda: api.me2(mom, hel, col, mode="cdbg", precision=p, out=out),
+                            steps, 1)
+        res[p] = out.cpu().numpy().copy()
+    valid = res["fp64"] != 0.0
+    idx = np.nonzero(valid & nonvanishing(ev["hel"]))[0]
+    idx = np.sort(np.random.default_rng(13).choice(idx, min(6, idx.size), replace=False))
+    ref = np.abs(ocdbg.flow_amplitude(ev["mom"][:, :, idx], ev["hel"][:, idx],
+                                      ev["col"][:, :, idx])) ** 2
+    return {
+        "workload": "gg->6g n=8 colour-dressed, sampled helicities and colour flows",
+        "events": E, "valid_fraction": float(valid.mean()),
+        "fp32": {"value": E / (ms["fp32"] * 1e-3), "ms": ms["fp32"],
+                 "valid_events_per_s": valid.sum() / (ms["fp32"] * 1e-3),
+                 "rel_err_vs_oracle": rel_err_stats(res["fp32"][idx], ref)},
+        "fp64": {"value": E / (ms["fp64"] * 1e-3), "ms": ms["fp64"],
+                 "rel_err_vs_oracle": rel_err_stats(res["fp64"][idx], ref)},
+    }
+
+
+def section_adjoint(args, api, torch):
+    from bg_inputs import workload
+    log("gg->4g adjoint inputs")
+    ev = workload("gg_4g_n6_adjoint")
+    E = ev["mom"].shape[2]
+    mom, hel = torch.from_numpy(ev["mom"]).cuda(), torch.from_numpy(ev["hel"]).cuda()
+    steps = max(2, args.steps // 4)
+    row = {"workload": "gg->4g n=6, d|M|^2/dp for every momentum component", "events": E}
+    for p in ("fp32", "fp64"):
+        log(f"timing adjoint {p}")
+        ms = time_events(lambda: api.me2_grad(mom, hel, precision=p), steps, 1)
+        row[p] = {"value": E / (ms * 1e-3), "ms": ms,
+                  "note": "one call = recursion, FP64 colour vector C A, reverse sweep"}
+    return row
+
+
+def section_batch(args, api, torch):
+    from bg_inputs import mixed_workload
+    log("mixed batch inputs (n = 4..9)")
+    ev = mixed_workload()
+    segs = []
+    for n, e in sorted(ev.items()):
+        segs.append({"mom": torch.from_numpy(e["mom"]).cuda(), "hel": torch.from_numpy(e["hel"]).cuda(),
+                     "col": torch.from_numpy(e["col"]).cuda() if n >= 8 else None, "mode": "auto"})
+    total = sum(s["mom"].shape[2] for s in segs)
+    log("autotuning the batch kernel")
+    cfg, tune_ms = api.batch_tune(segs, "fp32")
+    g = api.BatchGraph(segs, "fp32")
+    steps = max(2, args.steps // 4)
+    log("timing graph replays")
+    ms = time_events(g.replay, steps, 1)
+    single = []
+    for s in segs:
+        single.append(time_events(lambda s=s: api.me2(s["mom"], s["hel"], s["col"], mode="auto",
+                                                      precision="fp32"), steps, 1))
+    return {"workload": "mixed n=4..9, log-uniform counts in [2^10, 2^20], COBG n<=7, CDBG n>=8, FP32",
+            "counts": {str(n): int(e["mom"].shape[2]) for n, e in sorted(ev.items())},
+            "events": total, "value": total / (ms * 1e-3), "ms": ms, "tuned_config": cfg,
+            "tune_best_ms": tune_ms, "single_requests_ms": dict(zip([str(n) for n in sorted(ev)], single)),
+            "single_requests_total_ms": float(sum(single))}
+
+
+def cpu_baseline(args, ev):
+    from oracle.me2 import me2_cobg
+    E = ev["mom"].shape[2]
+    S = min(args.cpu_sample, E)
+    log(f"timing the oracle on {S} events (1 thread)")
+    t0 = time.perf_counter()
+    me2_cobg(ev["mom"][:, :, :S], ev["hel"][:, :S])
+    dt = time.perf_counter() - t0
+    return {"value": S / dt, "unit": "events/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {S} of the {E} gg->4g events, numpy FP64 oracle, single thread"}
 
 
 def main():
@@ -57,8 +283,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--events", type=int, default=1 << 20)
+    ap.add_argument("--sections", default="cdbg,adjoint,batch",
+                    help="extra rows beside the headline: any of cdbg, adjoint, batch, or none")
     ap.add_argument("--cpu-sample", type=int, default=32768,
-                    help="events of the same workload timed on the oracle")
+                    help="events of the headline workload timed on the oracle")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (HBM counter calibration)")
@@ -73,129 +301,50 @@ def main():
         nbytes = args.copy_probe << 20
         src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
-        ms = time_calls(lambda: dst.copy_(src), max(1, args.steps), 1)
+        ms = time_events(lambda: dst.copy_(src), max(1, args.steps), 1)
         print(json.dumps({"copy_probe_bytes": nbytes, "ms": ms,
                           "GBs": 2 * nbytes / (ms * 1e-3) / 1e9}), flush=True)
         return
-    from bg_inputs import workload
     from paper_2106_06507_amd import api, workmodel as wm
 
-    n = 6
-    log(f"generating gg -> 4g inputs: {args.events} events")
-    ev = workload("gg_4g_n6", n_events=args.events)
-    E = ev["mom"].shape[2]
-    mom = torch.from_numpy(ev["mom"]).cuda()
-    hel = torch.from_numpy(ev["hel"]).cuda()
-    out = torch.empty(E, dtype=torch.float64, device="cuda")
-    ctx = api.default_context()
+    head, ev = section_headline(args, api, wm, torch)
+    sections = [s for s in args.sections.split(",") if s and s != "none"]
+    extra = {}
+    if "cdbg" in sections:
+        extra["cdbg_gg_6g"] = section_cdbg(args, api, torch)
+    if "adjoint" in sections:
+        extra["adjoint_gg_4g"] = section_adjoint(args, api, torch)
+    if "batch" in sections:
+        extra["mixed_batch"] = section_batch(args, api, torch)
+    cpu = None if args.no_cpu else cpu_baseline(args, ev)
 
-    def step32():
-        api.me2(mom, hel, precision="fp32", out=out, ctx=ctx)
-
-    def step64():
-        api.me2(mom, hel, precision="fp64", out=out, ctx=ctx)
-
-    # headline: FP32-recursion / FP64-contraction path, K timed steps
-    log("timing fp32/mixed path")
-    step32()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ms32 = time_calls(step32, args.steps, args.warmup)
-    wall = time.perf_counter() - t0
-    me2_32 = out.cpu().numpy().copy()
-    log("timing fp64 path")
-    ms64 = time_calls(step64, max(3, args.steps // 2), 1)
-    me2_64 = out.cpu().numpy().copy()
-
-    # dominant kernel (recursion) alone, same launch shape, on the current stream
-    amp = torch.empty((2, 24, E), dtype=torch.float64, device="cuda")
-    from paper_2106_06507_amd._lib import lib, check
-    import ctypes
-
-    def rec32():
-        check(lib().bg_currents(ctx.handle, n, E, ctypes.c_void_p(mom.data_ptr()),
-                                ctypes.c_void_p(hel.data_ptr()), 1, ctypes.c_void_p(amp.data_ptr()),
-                                ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)), "bg_currents")
-
-    def rec64():
-        check(lib().bg_currents(ctx.handle, n, E, ctypes.c_void_p(mom.data_ptr()),
-                                ctypes.c_void_p(hel.data_ptr()), 0, ctypes.c_void_p(amp.data_ptr()),
-                                ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)), "bg_currents")
-
-    kms32 = time_calls(rec32, args.steps, 1)
-    kms64 = time_calls(rec64, max(3, args.steps // 2), 1)
-    amp_t = amp.clone()
-
-    def contr():
-        api.color_contract(amp_t, n, out=out, ctx=ctx)
-
-    cms = time_calls(contr, args.steps, 1)
-
-    # accuracy against the FP64 oracle on a sample of events
-    from oracle.me2 import me2_cobg
-    idx = np.sort(np.random.default_rng(7).choice(E, min(E, 256), replace=False))
-    ref = me2_cobg(ev["mom"][:, :, idx], ev["hel"][:, idx])
-    scale = me2_cobg(ev["mom"][:, :, idx], None) / 2 ** n  # helicity-averaged |M|^2
-    nz = nonvanishing(ev["hel"][:, idx])
-    err32 = rel_err_stats(me2_32[idx][nz], ref[nz])
-    err64 = rel_err_stats(me2_64[idx][nz], ref[nz])
-    err32["scale_relative_max"] = float((np.abs(me2_32[idx] - ref) / scale)[nz].max())
-    err64["scale_relative_max"] = float((np.abs(me2_64[idx] - ref) / scale)[nz].max())
-    nz_all = nonvanishing(ev["hel"])
-    err32_vs64 = rel_err_stats(me2_32[nz_all], me2_64[nz_all])
-
-    flop_ev = wm.cobg_flops_per_event(n)
-    achieved32 = flop_ev * E / (kms32 * 1e-3) / 1e12
-    achieved64 = flop_ev * E / (kms64 * 1e-3) / 1e12
-    cflop = wm.contraction_flops_per_event(n) * E / (cms * 1e-3) / 1e12
-
-    cpu = None
-    if not args.no_cpu:
-        S = min(args.cpu_sample, E)
-        log(f"timing the oracle on {S} events (1 thread)")
-        t0 = time.perf_counter()
-        me2_cobg(ev["mom"][:, :, :S], ev["hel"][:, :S])
-        dt = time.perf_counter() - t0
-        cpu = {"value": S / dt, "unit": "events/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {S} of the {E} gg->4g events, numpy FP64 oracle, single thread"}
-
-    value = E / (ms32 * 1e-3)
     rec = {
         "metric": "|M|^2 events/sec per n-gluon multiplicity at stated rel. error vs FP64; % roofline",
-        "value": value,
+        "value": head["value"],
         "unit": "events/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms32,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 recursion + f64 contraction",
+        "dtype": "f32 recursion + f64 colour sum",
         "data": "synthetic: seeded RAMBO + cuts, sampled helicities",
-        "config": {"workload": "gg->4g n=6 COBG 24 orderings + 24x24 colour matrix (MFMA)",
-                   "n": n, "events": E, "sqrt_s_GeV": 1000.0, "cuts": "pT>20 GeV, dR>0.4",
-                   "helicity": "sampled", "parallelism": "single GPU"},
-        "rel_err_vs_oracle": {"events": int(nz.sum()), "fp32_mixed": err32, "fp64": err64,
-                              "fp32_vs_fp64_all_nonvanishing": err32_vs64,
-                              "note": "per-event |d|/|ref| and scale-relative |d|/S_e with S_e the "
-                                      "helicity-averaged |M|^2 of the event; configurations with a "
-                                      "vanishing tree amplitude excluded"},
-        "fp64_path": {"value": E / (ms64 * 1e-3), "ms_per_step": ms64},
-        "kernels_ms": {"recursion_fp32": kms32, "recursion_fp64": kms64, "contraction_mfma": cms},
-        "roofline": {"bound": "alu", "kernel": "cobg_amp_kernel<6,float>", "achieved": achieved32,
-                     "peak": wm.PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved32 / wm.PEAK_FP32_VALU_TFLOPS, "traffic": None,
-                     "flops_per_event": flop_ev},
-        "roofline_fp64": {"bound": "alu", "kernel": "cobg_amp_kernel<6,double>", "achieved": achieved64,
-                          "peak": wm.PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
-                          "frac": achieved64 / wm.PEAK_FP64_VALU_TFLOPS},
-        "roofline_contraction": {"bound": "mfma", "achieved": cflop, "peak": wm.PEAK_FP64_MFMA_TFLOPS,
-                                 "unit": "TFLOP/s", "frac": cflop / wm.PEAK_FP64_MFMA_TFLOPS,
-                                 "hbm_GBs": wm.contraction_bytes_per_event(n) * E / (cms * 1e-3) / 1e9},
+        "config": {"workload": "gg->4g n=6 COBG 24 orderings + 24x24 colour sum, fused kernel",
+                   "n": 6, "events": head["events"], "sqrt_s_GeV": 1000.0,
+                   "cuts": "pT>20 GeV, dR>0.4", "helicity": "sampled", "parallelism": "single GPU"},
+        "kernel_ms": head["kernel_ms"],
+        "fp64_path": head["fp64_path"],
+        "two_stage_fp32": head["two_stage_fp32"],
+        "rel_err_vs_oracle": head["rel_err_vs_oracle"],
+        "roofline": head["roofline"],
+        "roofline_fp64": head["roofline_fp64"],
+        "roofline_contraction": head["roofline_contraction"],
         "cpu_baseline": cpu,
-        "timed_wall_s": wall,
+        "timed_wall_s": head["wall_s"],
     }
+    rec.update(extra)
     print(json.dumps(rec), flush=True)
 
 

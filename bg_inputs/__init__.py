@@ -13,6 +13,7 @@ from .rambo import (
     passes_cuts,
     workload,
     mixed_counts,
+    mixed_workload,
 )
 
 __all__ = [
@@ -24,4 +25,5 @@ __all__ = [
     "passes_cuts",
     "workload",
     "mixed_counts",
+    "mixed_workload",
 ]

@@ -148,6 +148,20 @@ _WORKLOADS = {
 }
 
 
+def mixed_workload(seed=None, ns=(4, 5, 6, 7, 8, 9), scale=1.0):
+    """Mixed-multiplicity batch: for each n, floor(scale * count) events with
+    counts log-uniform in [2^10, 2^20] (mixed_counts), RAMBO at 1 TeV with the
+    pT/dR cuts, sampled helicities, and sampled colour flows for n >= 8."""
+    s = BASE_SEED + 4 if seed is None else seed
+    counts = mixed_counts(s, ns)
+    out = {}
+    for k, n in enumerate(ns):
+        E = max(1, int(math.floor(counts[n] * scale)))
+        out[n] = make_events(n, E, seed=s + 100 * (k + 1), cuts=True, sample_hel=True,
+                             sample_col=n >= 8)
+    return out
+
+
 def workload(name, n_events=None, seed=None):
     """Events of one named workload; n_events/seed override the defaults."""
     w = dict(_WORKLOADS[name])

@@ -114,10 +114,14 @@ typedef struct bg_request {
 } bg_request;
 
 /* |M|^2 per event.  COBG: colour-summed (eq. color_summed_analytic), for one
- * helicity per event or summed over helicities (hel NULL).  CDBG: |A|^2 of the
+ * helicity per event or summed over helicities (hel NULL); the recursion and
+ * the colour sum run in one kernel and the partial amplitudes never reach
+ * device memory outside a small per-block scratch (FP64 colour sum in VALU;
+ * bg_currents + bg_color_contract give the same quantity through the
+ * matrix-core contraction with the amplitudes exposed).  CDBG: |A|^2 of the
  * colour-flow amplitude of the given assignment (eq. color_decomposition_colorflow
  * via eq. color_dressed_currents); assignments without a closed colour chain
- * give exactly 0. */
+ * give exactly 0.  May allocate context workspace on first use of a size. */
 int bg_me2(bg_context* ctx, const bg_request* req, void* stream);
 
 /* Gradient of the COBG colour-summed |M|^2 with respect to every momentum
@@ -130,10 +134,52 @@ int bg_me2(bg_context* ctx, const bg_request* req, void* stream);
 int bg_me2_grad(bg_context* ctx, const bg_request* req, const double* grad_me2,
                 double* grad_mom, void* stream);
 
-/* Several requests (mixed multiplicities, uneven event counts) in one
- * persistent launch; mode BG_MODE_AUTO picks COBG for n <= 7 and CDBG for
- * n >= 8 per segment.  All segments share one precision. */
+/* Several requests (mixed multiplicities, uneven event counts) in ONE
+ * persistent kernel launch.  Mode BG_MODE_AUTO picks COBG for n <= 7 and CDBG
+ * for n >= 8 per segment; explicit modes are honoured (COBG needs n <= 7).
+ * Every segment must have the same precision, hel non-NULL, me2 non-NULL when
+ * its n_events > 0, and col for CDBG; at most BG_BATCH_MAX_SEGS segments.
+ * Results are identical, bit for bit, to bg_me2 on each segment alone (the
+ * same device routines evaluate every event; only the scheduling differs).
+ * The events are cut into tiles (config below), the tiles are ordered by
+ * decreasing estimated cost and the blocks of the persistent grid take them
+ * from an atomic queue.
+ * The tile table depends only on the segments' (n, mode, n_events), the
+ * precision and the config; it is built on the first call with that shape
+ * (synchronous host-to-device upload) and cached in the context (at most
+ * BG_BATCH_MAX_PLANS shapes; older ones are evicted after a device
+ * synchronisation).  A call whose shape is cached allocates nothing, copies
+ * nothing and only enqueues two kernels on `stream`, so it may be recorded
+ * into a HIP graph; such a graph remains valid while its shape stays cached
+ * and the context lives.  Recording a call whose shape is not cached returns
+ * BG_EINVAL.  Calls on one context must not overlap in time (they share the
+ * context's scratch memory). */
+#define BG_BATCH_MAX_SEGS 32
+#define BG_BATCH_MAX_PLANS 64
 int bg_me2_batch(bg_context* ctx, const bg_request* segs, int n_segs, void* stream);
+
+/* Tile and grid shape of the batch kernel, per precision. */
+typedef struct bg_batch_config {
+    int blocks_per_cu;      /* persistent one-wave blocks per compute unit; 0 = as many
+                               as registers and LDS allow */
+    int cobg_tile_events;   /* events per colour-ordered tile, multiple of 32, <= 4096 */
+    int cdbg_tile_events;   /* events per colour-dressed tile, multiple of 64, <= 4096 */
+    int reserved;           /* must be 0 */
+} bg_batch_config;
+
+/* Current batch config of `precision` (defaults: 0, 64, 256) into *out (host). */
+int bg_batch_config_get(bg_context* ctx, int precision, bg_batch_config* out);
+/* Set it; BG_EINVAL for values outside the ranges above. */
+int bg_batch_config_set(bg_context* ctx, int precision, const bg_batch_config* cfg);
+
+/* Autotuner: times bg_me2_batch on the given segments (their outputs are
+ * written) for candidate configs -- blocks per CU, then colour-ordered tile,
+ * then colour-dressed tile, each stage keeping the best -- with HIP events on
+ * `stream`, and installs the fastest config for the segments' precision.
+ * Synchronous; writes the chosen config and its time in milliseconds to
+ * *best and *best_ms when non-NULL.  Must not be called during graph capture. */
+int bg_me2_batch_tune(bg_context* ctx, const bg_request* segs, int n_segs,
+                      bg_batch_config* best, double* best_ms, void* stream);
 
 /* Self-test of the matrix-core operand layout used by bg_color_contract:
  * runs one v_mfma_f64_16x16x4f64 with lane l supplying A[l%16][l/16] =

@@ -37,6 +37,17 @@ class bg_request(ctypes.Structure):
     ]
 
 
+class bg_batch_config(ctypes.Structure):
+    _fields_ = [
+        ("blocks_per_cu", ctypes.c_int),
+        ("cobg_tile_events", ctypes.c_int),
+        ("cdbg_tile_events", ctypes.c_int),
+        ("reserved", ctypes.c_int),
+    ]
+
+
+BATCH_MAX_SEGS = 32
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int
 _I64 = ctypes.c_int64
@@ -52,6 +63,10 @@ _SIGNATURES = {
     "bg_me2": (_I, [_P, ctypes.POINTER(bg_request), _P]),
     "bg_me2_grad": (_I, [_P, ctypes.POINTER(bg_request), _P, _P, _P]),
     "bg_me2_batch": (_I, [_P, ctypes.POINTER(bg_request), _I, _P]),
+    "bg_batch_config_get": (_I, [_P, _I, ctypes.POINTER(bg_batch_config)]),
+    "bg_batch_config_set": (_I, [_P, _I, ctypes.POINTER(bg_batch_config)]),
+    "bg_me2_batch_tune": (_I, [_P, ctypes.POINTER(bg_request), _I, ctypes.POINTER(bg_batch_config),
+                               ctypes.POINTER(ctypes.c_double), _P]),
     "bg_mfma_layout_probe": (_I, [_P, _P]),
 }
 

@@ -11,7 +11,7 @@ import threading
 import torch
 
 from . import _lib
-from ._lib import bg_request, check, lib
+from ._lib import bg_batch_config, bg_request, check, lib
 
 _PREC = {"fp64": _lib.PREC_FP64, "fp32": _lib.PREC_FP32_MIXED, "mixed": _lib.PREC_FP32_MIXED}
 _MODE = {"cobg": _lib.MODE_COBG, "cdbg": _lib.MODE_CDBG, "auto": _lib.MODE_AUTO}
@@ -178,3 +178,95 @@ class ME2(torch.autograd.Function):
         _, g = me2_grad(mom, hel, grad_me2=grad_out.contiguous(), precision=ctx.precision,
                         want_me2=False)
         return g, None, None
+
+
+# ---------------------------------------------------------------- batches
+
+
+def _segment(seg):
+    """(mom, hel, col, mode) from a dict with keys mom, hel, col (optional), mode
+    (optional, default "auto") or from such a tuple."""
+    if isinstance(seg, dict):
+        return seg["mom"], seg["hel"], seg.get("col"), seg.get("mode", "auto")
+    mom, hel = seg[0], seg[1]
+    col = seg[2] if len(seg) > 2 else None
+    mode = seg[3] if len(seg) > 3 else "auto"
+    return mom, hel, col, mode
+
+
+def _batch_requests(segments, precision, outs):
+    segs = [_segment(s) for s in segments]
+    if len(segs) > _lib.BATCH_MAX_SEGS:
+        raise ValueError(f"at most {_lib.BATCH_MAX_SEGS} segments per batch")
+    if outs is None:
+        outs = [torch.empty(m.shape[2], dtype=torch.float64, device=m.device) for m, _, _, _ in segs]
+    arr = (bg_request * max(1, len(segs)))()
+    for i, ((mom, hel, col, mode), out) in enumerate(zip(segs, outs)):
+        if hel is None:
+            raise ValueError("batch segments need helicities")
+        arr[i] = _request(mom, hel, col, mode, precision, out)
+    return arr, outs
+
+
+def me2_batch(segments, precision="fp32", outs=None, ctx=None):
+    """|M|^2 of several segments (mixed n, uneven sizes) in one persistent
+    launch; returns one float64 [E_i] tensor per segment."""
+    if not segments:
+        return []
+    dev = _segment(segments[0])[0].device
+    ctx = ctx or default_context(dev.index)
+    arr, outs = _batch_requests(segments, precision, outs)
+    check(lib().bg_me2_batch(ctx.handle, arr, len(outs), _stream(dev)), "bg_me2_batch")
+    return outs
+
+
+def batch_config(precision="fp32", ctx=None):
+    ctx = ctx or default_context()
+    c = bg_batch_config()
+    check(lib().bg_batch_config_get(ctx.handle, _PREC[precision], ctypes.byref(c)), "bg_batch_config_get")
+    return {"blocks_per_cu": c.blocks_per_cu, "cobg_tile_events": c.cobg_tile_events,
+            "cdbg_tile_events": c.cdbg_tile_events}
+
+
+def set_batch_config(precision="fp32", ctx=None, **cfg):
+    ctx = ctx or default_context()
+    cur = batch_config(precision, ctx)
+    cur.update(cfg)
+    c = bg_batch_config(cur["blocks_per_cu"], cur["cobg_tile_events"], cur["cdbg_tile_events"], 0)
+    check(lib().bg_batch_config_set(ctx.handle, _PREC[precision], ctypes.byref(c)), "bg_batch_config_set")
+
+
+def batch_tune(segments, precision="fp32", ctx=None):
+    """Run the library's autotuner on these segments; returns (config, ms)."""
+    dev = _segment(segments[0])[0].device
+    ctx = ctx or default_context(dev.index)
+    arr, outs = _batch_requests(segments, precision, None)
+    c = bg_batch_config()
+    ms = ctypes.c_double()
+    check(lib().bg_me2_batch_tune(ctx.handle, arr, len(outs), ctypes.byref(c), ctypes.byref(ms),
+                                  _stream(dev)), "bg_me2_batch_tune")
+    return {"blocks_per_cu": c.blocks_per_cu, "cobg_tile_events": c.cobg_tile_events,
+            "cdbg_tile_events": c.cdbg_tile_events}, ms.value
+
+
+class BatchGraph:
+    """One bg_me2_batch launch recorded into a torch.cuda.CUDAGraph.
+
+    The call is made once eagerly first, which builds the tile table and the
+    workspace, so the recorded call only enqueues kernels.  replay() re-runs
+    the batch on the same input tensors and writes the same output tensors
+    (self.outs)."""
+
+    def __init__(self, segments, precision="fp32", ctx=None):
+        self.segments = list(segments)
+        dev = _segment(self.segments[0])[0].device
+        self.ctx = ctx or default_context(dev.index)
+        self.outs = me2_batch(self.segments, precision, ctx=self.ctx)
+        torch.cuda.synchronize(dev)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            me2_batch(self.segments, precision, outs=self.outs, ctx=self.ctx)
+
+    def replay(self):
+        self.graph.replay()
+        return self.outs

@@ -7,6 +7,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
+#include <new>
 #include <utility>
 #include <vector>
 
@@ -16,19 +18,43 @@ namespace bg {
 int64_t colour_matrix(int n, double* C);
 }
 
+namespace {
+
+// Cached tile table of one batch shape (segment kinds and sizes, precision,
+// config).
+struct BatchPlan {
+  std::vector<int64_t> key;
+  bg::BatchTile* tiles = nullptr;
+  unsigned n_tiles = 0;
+  uint64_t last_use = 0;
+};
+
+}  // namespace
+
 struct bg_context {
-  int device;
-  int num_cus;
-  size_t lds_per_cu;
-  size_t lds_per_block;
-  unsigned* cws;                   // colour-dressed workspace (counters + event list)
-  size_t cws_bytes;
-  double* C_dev[BG_N_MAX + 1];     // K x K colour matrix per n (lazy)
-  double* Cpad_dev[BG_N_MAX + 1];  // KP x KP zero-padded copy for the matrix-core path
-  int KP[BG_N_MAX + 1];
-  double* ws;                      // workspace (partial amplitudes)
-  size_t ws_bytes;
-  uint8_t* perms_dev[BG_N_MAX + 1];  // [K][n-2] middle gluons of each ordering (gradient)
+  int device = 0;
+  int num_cus = 0;
+  size_t lds_per_cu = 0;
+  size_t lds_per_block = 0;
+  unsigned* cws = nullptr;                   // colour-dressed workspace (counters + event list)
+  size_t cws_bytes = 0;
+  double* C_dev[BG_N_MAX + 1] = {};          // K x K colour matrix per n (lazy)
+  double* Cpad_dev[BG_N_MAX + 1] = {};       // KP x KP zero-padded copy for the matrix-core path
+  double* Cb_dev[BG_N_MAX + 1] = {};         // doubled lower triangle in row blocks (fused path)
+  int KP[BG_N_MAX + 1] = {};
+  double* ws = nullptr;                      // workspace (partial amplitudes)
+  size_t ws_bytes = 0;
+  uint8_t* perms_dev[BG_N_MAX + 1] = {};     // [K][n-2] middle gluons of each ordering (gradient)
+  double* scratch = nullptr;                 // per-block scratch of the fused and batch kernels
+  size_t scratch_bytes = 0;
+  std::vector<void*> retired;                // outgrown scratch buffers, freed on destroy
+  unsigned* counter = nullptr;               // batch tile-queue head
+  bg_batch_config bcfg[2] = {{0, 64, 256, 0}, {0, 64, 256, 0}};
+  std::vector<BatchPlan> plans;
+  uint64_t clock = 0;
+  int occ_fused[BG_N_MAX + 1][2][2] = {};    // blocks per CU of the fused kernel, 0 = unknown
+  int occ_batch[2] = {};                     // of the batch kernel at its last LDS size
+  size_t occ_batch_lds[2] = {};
 };
 
 namespace {
@@ -75,11 +101,44 @@ struct DeviceGuard {
   }
 };
 
+// Symmetric C as its doubled lower triangle, row blocks of RB rows: for each
+// block and each column j below the block's end, the RB entries of the block's
+// rows are contiguous (the layout the fused colour sum reads).
+std::vector<double> row_blocked_lower(const std::vector<double>& C, int K) {
+  const int RB = K < 8 ? K : 8;
+  std::vector<double> out;
+  for (int ib = 0; ib < K; ib += RB)
+    for (int j = 0; j < ib + RB; ++j)
+      for (int r = 0; r < RB; ++r) {
+        const int i = ib + r;
+        const double c = C[(size_t)i * K + j];
+        out.push_back(j < i ? 2.0 * c : (j == i ? c : 0.0));
+      }
+  return out;
+}
+
+int upload(const std::vector<double>& v, double** out, const char* what) {
+  double* d = nullptr;
+  int st = hip_status(hipMalloc(&d, sizeof(double) * v.size()), what);
+  if (st) return st;
+  st = hip_status(hipMemcpy(d, v.data(), sizeof(double) * v.size(), hipMemcpyHostToDevice), what);
+  if (st) {
+    (void)hipFree(d);
+    return st;
+  }
+  *out = d;
+  return BG_OK;
+}
+
 int ensure_colour(bg_context* ctx, int n) {
   if (ctx->C_dev[n]) return BG_OK;
   const int64_t K = bg::factorial(n - 2);
   std::vector<double> C((size_t)(K * K));
   bg::colour_matrix(n, C.data());
+  if (!ctx->Cb_dev[n]) {
+    int st = upload(row_blocked_lower(C, (int)K), &ctx->Cb_dev[n], "colour matrix (row blocks)");
+    if (st) return st;
+  }
   int KP = (int)((K + 15) / 16 * 16);
   std::vector<double> Cp((size_t)KP * KP, 0.0);
   for (int64_t i = 0; i < K; ++i)
@@ -127,6 +186,21 @@ int ensure_ws(bg_context* ctx, size_t bytes) {
 }
 
 bool valid_n(int n) { return n >= BG_N_MIN && n <= BG_N_MAX; }
+
+// Grows the per-block scratch.  An outgrown buffer is kept until the context
+// is destroyed, since a recorded graph may still refer to it.
+int ensure_scratch(bg_context* ctx, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (ctx->scratch_bytes >= bytes) return BG_OK;
+  size_t want = std::max(bytes, 2 * ctx->scratch_bytes);
+  double* d = nullptr;
+  int st = hip_status(hipMalloc(&d, want), "hipMalloc(scratch)");
+  if (st) return st;
+  if (ctx->scratch) ctx->retired.push_back(ctx->scratch);
+  ctx->scratch = d;
+  ctx->scratch_bytes = want;
+  return BG_OK;
+}
 
 // Lexicographic orderings of the middle gluons 1..n-2, as bytes [K][n-2].
 int ensure_perms(bg_context* ctx, int n) {
@@ -215,7 +289,7 @@ int bg_context_create(bg_context** out, int device) {
     BG_LOG("device %d is %s, not gfx950", device, prop.gcnArchName);
     return BG_ENODEV;
   }
-  bg_context* ctx = (bg_context*)calloc(1, sizeof(bg_context));
+  bg_context* ctx = new (std::nothrow) bg_context();
   if (!ctx) return BG_ENOMEM;
   ctx->device = device;
   ctx->num_cus = prop.multiProcessorCount;
@@ -232,11 +306,17 @@ void bg_context_destroy(bg_context* ctx) {
   for (int n = 0; n <= BG_N_MAX; ++n) {
     if (ctx->C_dev[n]) (void)hipFree(ctx->C_dev[n]);
     if (ctx->Cpad_dev[n]) (void)hipFree(ctx->Cpad_dev[n]);
+    if (ctx->Cb_dev[n]) (void)hipFree(ctx->Cb_dev[n]);
     if (ctx->perms_dev[n]) (void)hipFree(ctx->perms_dev[n]);
   }
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->cws) (void)hipFree(ctx->cws);
-  free(ctx);
+  if (ctx->scratch) (void)hipFree(ctx->scratch);
+  for (void* p : ctx->retired) (void)hipFree(p);
+  if (ctx->counter) (void)hipFree(ctx->counter);
+  for (BatchPlan& pl : ctx->plans)
+    if (pl.tiles) (void)hipFree(pl.tiles);
+  delete ctx;
 }
 
 int bg_currents(bg_context* ctx, int n, int64_t E, const double* mom, const int8_t* hel,
@@ -265,28 +345,28 @@ int bg_color_contract(bg_context* ctx, int n, int64_t E, const double* amp, doub
   return contract_dispatch(ctx, n, E, amp, me2, accumulate, (hipStream_t)stream);
 }
 
+static int fused_occupancy(bg_context* ctx, int n, bool fp32, bool hsum) {
+  int& occ = ctx->occ_fused[n][fp32 ? 1 : 0][hsum ? 1 : 0];
+  if (occ <= 0) occ = bg::cobg_fused_blocks_per_cu(n, fp32, hsum);
+  return occ;
+}
+
 static int me2_cobg(bg_context* ctx, const bg_request* r, hipStream_t stream) {
   const int n = r->n;
   if (n > 7) return BG_EUNSUPPORTED;
-  const int64_t K = bg::factorial(n - 2);
   const int64_t E = r->n_events;
   int st = ensure_colour(ctx, n);
   if (st) return st;
-  st = ensure_ws(ctx, sizeof(double) * 2 * K * E);
-  if (st) return st;
   const bool fp32 = r->precision == BG_PREC_FP32_MIXED;
-  if (r->hel) {
-    st = launch_status(bg::cobg_amplitudes(n, fp32, E, r->mom, r->hel, 0, ctx->ws, stream));
-    if (st) return st;
-    return contract_dispatch(ctx, n, E, ctx->ws, r->me2, 0, stream);
-  }
-  for (int h = 0; h < (1 << n); ++h) {
-    st = launch_status(bg::cobg_amplitudes(n, fp32, E, r->mom, nullptr, h, ctx->ws, stream));
-    if (st) return st;
-    st = contract_dispatch(ctx, n, E, ctx->ws, r->me2, h > 0, stream);
-    if (st) return st;
-  }
-  return BG_OK;
+  const bool hsum = r->hel == nullptr;
+  const int occ = fused_occupancy(ctx, n, fp32, hsum);
+  if (occ <= 0) return BG_EDEVICE;
+  const int64_t tiles = (E + 31) / 32;
+  const int64_t grid = std::min<int64_t>(tiles, (int64_t)ctx->num_cus * occ);
+  st = ensure_scratch(ctx, sizeof(double) * (size_t)grid * bg::cobg_fused_scratch_doubles(n));
+  if (st) return st;
+  return launch_status(bg::cobg_fused_me2(n, fp32, E, r->mom, r->hel, ctx->Cb_dev[n], ctx->scratch,
+                                          (int)grid, r->me2, stream));
 }
 
 static int me2_cdbg(bg_context* ctx, const bg_request* r, hipStream_t stream) {
@@ -376,14 +456,319 @@ int bg_me2_grad(bg_context* ctx, const bg_request* r, const double* grad_me2, do
   return st;
 }
 
-int bg_me2_batch(bg_context* ctx, const bg_request* segs, int n_segs, void* stream) {
-  (void)stream;
-  if (!ctx || n_segs < 0 || (n_segs > 0 && !segs)) return BG_EINVAL;
-  for (int i = 0; i < n_segs; ++i) {
-    int st = validate_request(&segs[i]);
-    if (st) return st;
+}  // extern "C"
+
+namespace {
+
+int resolved_mode(const bg_request* r) {
+  return r->mode == BG_MODE_AUTO ? (r->n <= 7 ? BG_MODE_COBG : BG_MODE_CDBG) : r->mode;
+}
+
+// Estimated cost of one event in wave-time units (FP32 flops of one lane),
+// used only to order the tiles.  Colour-ordered: the recursion's vertex counts
+// (prefix sharing of the depth-first walk) over 64 lanes (32 events, each
+// split over two lanes) plus the FP64 colour sum.  Colour-dressed: a valid
+// event occupies the whole wave for ~3x its flops / 64; about 5% of uniformly
+// sampled colour assignments are valid.
+double event_cost(int n, bool cdbg, bool fp32) {
+  const double prec = fp32 ? 1.0 : 2.0;
+  if (!cdbg) {
+    const int M = n - 1;
+    double v3 = 0, v4 = 0;
+    for (int d = 1; d < M; ++d) {
+      const double times = (double)bg::factorial(n - 2) / (double)bg::factorial(n - 2 - d);
+      for (int a = d - 1; a >= 0; --a) {
+        const int L = d - a + 1;
+        v3 += times * (L - 1);
+        v4 += times * ((L - 1) * (L - 2) / 2);
+      }
+    }
+    const double K = (double)bg::factorial(n - 2);
+    return (166.0 * v3 + 188.0 * v4) * prec / 64.0 + 2.0 * (K * K / 2.0 + 8.0 * K);
   }
-  return BG_EUNSUPPORTED;
+  const int M = n - 1;
+  double splits = 1.0;
+  for (int i = 0; i < M; ++i) splits *= 3.0;
+  splits -= 2.0 * (double)(1 << M) - 1.0;
+  return 20.0 * n + 0.05 * 3.0 * splits * 450.0 * prec / 64.0;
+}
+
+int validate_batch(bg_context* ctx, const bg_request* segs, int n_segs) {
+  if (!ctx || n_segs < 0 || (n_segs > 0 && !segs)) return BG_EINVAL;
+  if (n_segs > BG_BATCH_MAX_SEGS) return BG_ERANGE;
+  for (int i = 0; i < n_segs; ++i) {
+    const bg_request* r = &segs[i];
+    int st = validate_request(r);
+    if (st) return st;
+    if (r->precision != segs[0].precision) return BG_EINVAL;
+    if (r->n_events == 0) continue;
+    if (!r->me2 || !r->hel) return BG_EINVAL;
+    const int mode = resolved_mode(r);
+    if (mode == BG_MODE_COBG && r->n > 7) return BG_EUNSUPPORTED;
+    const bool fp32 = r->precision == BG_PREC_FP32_MIXED;
+    const size_t lds =
+        mode == BG_MODE_COBG ? bg::cobg_lds_bytes(r->n, fp32) : bg::cdbg_lds_bytes(r->n, fp32);
+    if (lds == 0 || lds > ctx->lds_per_block) return BG_EUNSUPPORTED;
+  }
+  return BG_OK;
+}
+
+bool stream_capturing(hipStream_t stream) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return false;
+  return cs == hipStreamCaptureStatusActive;
+}
+
+// Finds or builds the tile table of this batch shape.  Building allocates
+// and uploads synchronously, so it is refused while the stream records.
+int batch_plan(bg_context* ctx, const bg_request* segs, int n_segs, const bg_batch_config& cfg,
+               bool capturing, BatchPlan** out) {
+  const int prec = segs[0].precision;
+  const bool fp32 = prec == BG_PREC_FP32_MIXED;
+  std::vector<int64_t> key = {prec, cfg.cobg_tile_events, cfg.cdbg_tile_events};
+  for (int i = 0; i < n_segs; ++i) {
+    key.push_back(segs[i].n * 2 + (resolved_mode(&segs[i]) == BG_MODE_CDBG ? 1 : 0));
+    key.push_back(segs[i].n_events);
+  }
+  for (BatchPlan& pl : ctx->plans) {
+    if (pl.key == key) {
+      pl.last_use = ++ctx->clock;
+      *out = &pl;
+      return BG_OK;
+    }
+  }
+  if (capturing) {
+    BG_LOG("bg_me2_batch: shape not prepared before graph capture");
+    return BG_EINVAL;
+  }
+  struct Item {
+    double cost;
+    bg::BatchTile t;
+  };
+  std::vector<Item> items;
+  for (int i = 0; i < n_segs; ++i) {
+    const bg_request* r = &segs[i];
+    if (r->n_events == 0) continue;
+    const bool cd = resolved_mode(r) == BG_MODE_CDBG;
+    const int64_t step = cd ? cfg.cdbg_tile_events : cfg.cobg_tile_events;
+    const double c = event_cost(r->n, cd, fp32);
+    for (int64_t f = 0; f < r->n_events; f += step) {
+      const int cnt = (int)std::min<int64_t>(step, r->n_events - f);
+      items.push_back(Item{c * cnt, bg::BatchTile{f, i, cnt}});
+    }
+  }
+  if (items.size() > 0x7fffffffu) return BG_ERANGE;
+  std::stable_sort(items.begin(), items.end(),
+                   [](const Item& a, const Item& b) { return a.cost > b.cost; });
+  std::vector<bg::BatchTile> tiles(items.size());
+  for (size_t i = 0; i < items.size(); ++i) tiles[i] = items[i].t;
+  BatchPlan pl;
+  pl.key = key;
+  pl.n_tiles = (unsigned)tiles.size();
+  if (!tiles.empty()) {
+    int st = hip_status(hipMalloc(&pl.tiles, sizeof(bg::BatchTile) * tiles.size()),
+                        "hipMalloc(tiles)");
+    if (st) return st;
+    st = hip_status(hipMemcpy(pl.tiles, tiles.data(), sizeof(bg::BatchTile) * tiles.size(),
+                              hipMemcpyHostToDevice),
+                    "hipMemcpy(tiles)");
+    if (st) {
+      (void)hipFree(pl.tiles);
+      return st;
+    }
+  }
+  if (ctx->plans.size() >= BG_BATCH_MAX_PLANS) {
+    auto lru = std::min_element(ctx->plans.begin(), ctx->plans.end(),
+                                [](const BatchPlan& a, const BatchPlan& b) {
+                                  return a.last_use < b.last_use;
+                                });
+    int st = hip_status(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    if (st) {
+      if (pl.tiles) (void)hipFree(pl.tiles);
+      return st;
+    }
+    if (lru->tiles) (void)hipFree(lru->tiles);
+    ctx->plans.erase(lru);
+  }
+  pl.last_use = ++ctx->clock;
+  ctx->plans.push_back(std::move(pl));
+  *out = &ctx->plans.back();
+  BG_LOG("batch plan: %u tiles, %d segments", ctx->plans.back().n_tiles, n_segs);
+  return BG_OK;
+}
+
+int batch_run(bg_context* ctx, const bg_request* segs, int n_segs, const bg_batch_config& cfg,
+              hipStream_t stream) {
+  const bool capturing = stream_capturing(stream);
+  const bool fp32 = segs[0].precision == BG_PREC_FP32_MIXED;
+  bg::BatchSegTable tab;
+  memset(&tab, 0, sizeof(tab));
+  size_t lds = 0;
+  int64_t stride = 0;
+  for (int i = 0; i < n_segs; ++i) {
+    const bg_request* r = &segs[i];
+    const bool cd = resolved_mode(r) == BG_MODE_CDBG;
+    bg::BatchSeg& b = tab.s[i];
+    b.mom = r->mom;
+    b.hel = r->hel;
+    b.col = r->col;
+    b.me2 = r->me2;
+    b.E = r->n_events;
+    b.kind = (cd ? bg::kBatchCdbg : bg::kBatchCobg) + r->n;
+    if (r->n_events == 0) continue;
+    if (!cd) {
+      if (!ctx->Cb_dev[r->n]) {
+        if (capturing) return BG_EINVAL;
+        int st = ensure_colour(ctx, r->n);
+        if (st) return st;
+      }
+      b.Cl = ctx->Cb_dev[r->n];
+      stride = std::max<int64_t>(stride, bg::cobg_fused_scratch_doubles(r->n));
+      lds = std::max(lds, bg::cobg_lds_bytes(r->n, fp32));
+    } else {
+      lds = std::max(lds, bg::cdbg_lds_bytes(r->n, fp32));
+    }
+  }
+  BatchPlan* pl = nullptr;
+  int st = batch_plan(ctx, segs, n_segs, cfg, capturing, &pl);
+  if (st) return st;
+  if (pl->n_tiles == 0) return BG_OK;
+  const int fi = fp32 ? 1 : 0;
+  if (ctx->occ_batch[fi] <= 0 || ctx->occ_batch_lds[fi] != lds) {
+    ctx->occ_batch[fi] = bg::batch_blocks_per_cu(fp32, lds);
+    ctx->occ_batch_lds[fi] = lds;
+  }
+  const int occ = ctx->occ_batch[fi];
+  if (occ <= 0) return BG_EUNSUPPORTED;
+  const int bpc = cfg.blocks_per_cu > 0 ? std::min(cfg.blocks_per_cu, occ) : occ;
+  const int64_t grid = std::min<int64_t>((int64_t)ctx->num_cus * bpc, pl->n_tiles);
+  const size_t need = sizeof(double) * (size_t)grid * (size_t)stride;
+  if (ctx->scratch_bytes < std::max<size_t>(need, 256) || !ctx->counter) {
+    if (capturing) {
+      BG_LOG("bg_me2_batch: workspace not prepared before graph capture");
+      return BG_EINVAL;
+    }
+    st = ensure_scratch(ctx, need);
+    if (st) return st;
+    if (!ctx->counter) {
+      st = hip_status(hipMalloc(&ctx->counter, 256), "hipMalloc(counter)");
+      if (st) return st;
+    }
+  }
+  return launch_status(bg::batch_launch(fp32, tab, pl->tiles, pl->n_tiles, ctx->counter,
+                                        ctx->scratch, stride, (int)grid, lds, stream));
+}
+
+bool valid_config(const bg_batch_config* c) {
+  return c && c->blocks_per_cu >= 0 && c->blocks_per_cu <= 64 && c->cobg_tile_events >= 32 &&
+         c->cobg_tile_events <= 4096 && c->cobg_tile_events % 32 == 0 &&
+         c->cdbg_tile_events >= 64 && c->cdbg_tile_events <= 4096 &&
+         c->cdbg_tile_events % 64 == 0 && c->reserved == 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bg_me2_batch(bg_context* ctx, const bg_request* segs, int n_segs, void* stream) {
+  int st = validate_batch(ctx, segs, n_segs);
+  if (st) return st;
+  if (n_segs == 0) return BG_OK;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return BG_EDEVICE;
+  const int fi = segs[0].precision == BG_PREC_FP32_MIXED ? 1 : 0;
+  return batch_run(ctx, segs, n_segs, ctx->bcfg[fi], (hipStream_t)stream);
+}
+
+int bg_batch_config_get(bg_context* ctx, int precision, bg_batch_config* out) {
+  if (!ctx || !out) return BG_EINVAL;
+  if (precision != BG_PREC_FP64 && precision != BG_PREC_FP32_MIXED) return BG_EINVAL;
+  *out = ctx->bcfg[precision == BG_PREC_FP32_MIXED ? 1 : 0];
+  return BG_OK;
+}
+
+int bg_batch_config_set(bg_context* ctx, int precision, const bg_batch_config* cfg) {
+  if (!ctx || !valid_config(cfg)) return BG_EINVAL;
+  if (precision != BG_PREC_FP64 && precision != BG_PREC_FP32_MIXED) return BG_EINVAL;
+  ctx->bcfg[precision == BG_PREC_FP32_MIXED ? 1 : 0] = *cfg;
+  return BG_OK;
+}
+
+int bg_me2_batch_tune(bg_context* ctx, const bg_request* segs, int n_segs, bg_batch_config* best,
+                      double* best_ms, void* stream) {
+  int st = validate_batch(ctx, segs, n_segs);
+  if (st) return st;
+  if (n_segs == 0) return BG_EINVAL;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return BG_EDEVICE;
+  hipStream_t s = (hipStream_t)stream;
+  if (stream_capturing(s)) return BG_EINVAL;
+  const int fi = segs[0].precision == BG_PREC_FP32_MIXED ? 1 : 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  st = hip_status(hipEventCreate(&e0), "hipEventCreate");
+  if (!st) st = hip_status(hipEventCreate(&e1), "hipEventCreate");
+  bg_batch_config cur = {0, 64, 256, 0};
+  double cur_ms = 1e300;
+  auto time_cfg = [&](const bg_batch_config& c, double* ms) -> int {
+    int r = batch_run(ctx, segs, n_segs, c, s);  // warm-up, builds the plan
+    if (r) return r;
+    double bestt = 1e300;
+    for (int rep = 0; rep < 2; ++rep) {
+      r = hip_status(hipEventRecord(e0, s), "hipEventRecord");
+      if (!r) r = batch_run(ctx, segs, n_segs, c, s);
+      if (!r) r = hip_status(hipEventRecord(e1, s), "hipEventRecord");
+      if (!r) r = hip_status(hipEventSynchronize(e1), "hipEventSynchronize");
+      float t = 0.f;
+      if (!r) r = hip_status(hipEventElapsedTime(&t, e0, e1), "hipEventElapsedTime");
+      if (r) return r;
+      bestt = std::min(bestt, (double)t);
+    }
+    *ms = bestt;
+    return BG_OK;
+  };
+  auto try_cfg = [&](const bg_batch_config& c) -> int {
+    double ms = 0.0;
+    int r = time_cfg(c, &ms);
+    if (r) return r;
+    BG_LOG("tune: blocks/CU %d cobg tile %d cdbg tile %d -> %.3f ms", c.blocks_per_cu,
+           c.cobg_tile_events, c.cdbg_tile_events, ms);
+    if (ms < cur_ms) {
+      cur_ms = ms;
+      cur = c;
+    }
+    return BG_OK;
+  };
+  if (!st) {
+    const bg_batch_config base = cur;
+    for (int b : {0, 1, 2, 3, 4, 6, 8}) {
+      bg_batch_config c = base;
+      c.blocks_per_cu = b;
+      if ((st = try_cfg(c))) break;
+    }
+  }
+  if (!st) {
+    const bg_batch_config base = cur;
+    for (int t : {32, 64, 128, 256}) {
+      bg_batch_config c = base;
+      c.cobg_tile_events = t;
+      if ((st = try_cfg(c))) break;
+    }
+  }
+  if (!st) {
+    const bg_batch_config base = cur;
+    for (int t : {64, 128, 256, 512}) {
+      bg_batch_config c = base;
+      c.cdbg_tile_events = t;
+      if ((st = try_cfg(c))) break;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (st) return st;
+  ctx->bcfg[fi] = cur;
+  if (best) *best = cur;
+  if (best_ms) *best_ms = cur_ms;
+  return BG_OK;
 }
 
 int bg_mfma_layout_probe(bg_context* ctx, double* out) {

@@ -54,4 +54,48 @@ int mfma_probe(double* out_dev, hipStream_t stream);
 int contract_mfma(int K, int64_t E, const double* amp, const double* C_pad, int KP, double* me2,
                   int accumulate, hipStream_t stream);
 
+// Fused colour-ordered |M|^2: recursion and colour sum in one persistent
+// grid-stride kernel.  Cl is the colour matrix as doubled lower triangle
+// [K][K]; scratch holds grid * cobg_fused_scratch_doubles(n) doubles.
+int cobg_fused_me2(int n, bool fp32, int64_t E, const double* mom, const int8_t* hel,
+                   const double* Cl, double* scratch, int grid, double* me2, hipStream_t stream);
+int cobg_fused_scratch_doubles(int n);
+int cobg_fused_blocks_per_cu(int n, bool fp32, bool hsum);
+size_t cobg_lds_bytes(int n, bool fp32);
+
+// Mixed-multiplicity batch.  kind = kBatchCobg + n or kBatchCdbg + n.
+constexpr int kBatchCobg = 0;
+constexpr int kBatchCdbg = 16;
+
+struct BatchSeg {
+  const double* mom;   // [n][4][E]
+  const int8_t* hel;   // [n][E]
+  const int8_t* col;   // [2][n][E] (colour-dressed only)
+  double* me2;         // [E]
+  const double* Cl;    // doubled lower-triangle colour matrix (colour-ordered only)
+  int64_t E;
+  int kind;
+  int pad;
+};
+
+struct BatchTile {
+  int64_t first;  // first event of the tile within its segment
+  int seg;
+  int count;      // events in the tile
+};
+
+constexpr int kBatchMaxSegs = 32;
+
+// Passed by value as a kernel argument, so that a launch (or a recorded graph
+// node) carries the caller's pointers without any device-side table.
+struct BatchSegTable {
+  BatchSeg s[kBatchMaxSegs];
+};
+
+int batch_blocks_per_cu(bool fp32, size_t lds);
+// Enqueues the counter reset and the persistent kernel on stream.
+int batch_launch(bool fp32, const BatchSegTable& segs, const BatchTile* tiles, unsigned n_tiles,
+                 unsigned* counter, double* scratch, int64_t scratch_stride, int grid, size_t lds,
+                 hipStream_t stream);
+
 }  // namespace bg

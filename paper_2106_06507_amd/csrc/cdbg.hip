@@ -4,6 +4,30 @@
 namespace bg {
 namespace cdbgk {
 
+// Valid-flow classification and compaction.  Invalid events get me2 = 0.
+__global__ void __launch_bounds__(256) cdbg_classify_kernel(int n, int64_t E,
+                                                           const int8_t* __restrict__ col,
+                                                           double* __restrict__ me2,
+                                                           unsigned* __restrict__ list,
+                                                           unsigned* __restrict__ count) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool valid = false;
+  if (e < E) {
+    valid = flow_valid(n, E, col, e);
+    if (!valid) me2[e] = 0.0;
+  }
+  // one atomic per wave
+  const unsigned long long bal = __ballot(valid);
+  const int lane = threadIdx.x & 63;
+  unsigned base = 0;
+  if (lane == 0 && bal) base = atomicAdd(count, (unsigned)__popcll(bal));
+  base = __shfl(base, 0);
+  if (valid) {
+    const unsigned long long below = lane ? (bal & ((~0ull) >> (64 - lane))) : 0ull;
+    list[base + __popcll(below)] = (unsigned)e;
+  }
+}
+
 __global__ void zero_u32_kernel(unsigned* p, int n) {
   if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
 }

@@ -228,58 +228,41 @@ __device__ __forceinline__ void split_contrib(const Sm<N, T>& sm, int m1, int m2
   }
 }
 
-// Valid-flow classification and compaction: edges j_k -> i_k must be
-// balanced and connected.  Invalid events get me2 = 0.
-__global__ void __launch_bounds__(256) cdbg_classify_kernel(int n, int64_t E,
-                                                           const int8_t* __restrict__ col,
-                                                           double* __restrict__ me2,
-                                                           unsigned* __restrict__ list,
-                                                           unsigned* __restrict__ count) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool valid = false;
-  if (e < E) {
-    int deg[3] = {0, 0, 0};
-    int par[3] = {0, 1, 2};
-    int touched = 0;
-    bool in_range = true;
-    for (int k = 0; k < n; ++k) {
-      int ii = col[(int64_t)k * E + e];
-      int jj = col[((int64_t)n + k) * E + e];
-      if (ii < 0 || ii > 2 || jj < 0 || jj > 2) {  // not a colour: the event is invalid
-        in_range = false;
-        ii = 0;
-        jj = 0;
-      }
-      deg[jj] += 1;
-      deg[ii] -= 1;
-      touched |= (1 << ii) | (1 << jj);
-      int a = jj, b = ii;
-      while (par[a] != a) a = par[a];
-      while (par[b] != b) b = par[b];
-      if (a != b) par[a] = b;
+// True if the colour-flow edges j_k -> i_k of event e are balanced (in =
+// out degree at every colour) and connected, i.e. form one closed circuit.
+// Indices outside 0..2 make the event invalid.
+__device__ __forceinline__ bool flow_valid(int n, int64_t E, const int8_t* __restrict__ col,
+                                           int64_t e) {
+  int deg[3] = {0, 0, 0};
+  int par[3] = {0, 1, 2};
+  int touched = 0;
+  bool in_range = true;
+  for (int k = 0; k < n; ++k) {
+    int ii = col[(int64_t)k * E + e];
+    int jj = col[((int64_t)n + k) * E + e];
+    if (ii < 0 || ii > 2 || jj < 0 || jj > 2) {
+      in_range = false;
+      ii = 0;
+      jj = 0;
     }
-    bool conn = true;
-    int root = -1;
-    for (int v = 0; v < 3; ++v) {
-      if (!(touched & (1 << v))) continue;
-      int a = v;
-      while (par[a] != a) a = par[a];
-      if (root < 0) root = a;
-      else if (a != root) conn = false;
-    }
-    valid = in_range && conn && deg[0] == 0 && deg[1] == 0 && deg[2] == 0;
-    if (!valid) me2[e] = 0.0;
+    deg[jj] += 1;
+    deg[ii] -= 1;
+    touched |= (1 << ii) | (1 << jj);
+    int a = jj, b = ii;
+    while (par[a] != a) a = par[a];
+    while (par[b] != b) b = par[b];
+    if (a != b) par[a] = b;
   }
-  // one atomic per wave
-  const unsigned long long bal = __ballot(valid);
-  const int lane = threadIdx.x & 63;
-  unsigned base = 0;
-  if (lane == 0 && bal) base = atomicAdd(count, (unsigned)__popcll(bal));
-  base = __shfl(base, 0);
-  if (valid) {
-    const unsigned long long below = lane ? (bal & ((~0ull) >> (64 - lane))) : 0ull;
-    list[base + __popcll(below)] = (unsigned)e;
+  bool conn = true;
+  int root = -1;
+  for (int v = 0; v < 3; ++v) {
+    if (!(touched & (1 << v))) continue;
+    int a = v;
+    while (par[a] != a) a = par[a];
+    if (root < 0) root = a;
+    else if (a != root) conn = false;
   }
+  return in_range && conn && deg[0] == 0 && deg[1] == 0 && deg[2] == 0;
 }
 
 // One valid event (colour flow closes into a circuit) on this 64-lane wave.

@@ -1,0 +1,135 @@
+// Tile routines shared by the fused colour-ordered kernel and the persistent
+// mixed-multiplicity batch kernel.
+//
+// Colour-ordered tile (n <= 7): 32 events on one 64-lane wave (lane pairs, as
+// in cobg_pair_impl.h).  The (n-2)! partial amplitudes of the tile go to a
+// block-private scratch [2][K][32] (real and imaginary planes), which stays in
+// L2 because the same block reuses it for every tile it processes; then each
+// lane forms the colour sum (eq. color_summed_analytic) of its plane,
+//   q_h = a_h^T C a_h,  a_0 = Re A, a_1 = Im A,   |M|^2 = q_0 + q_1,
+// with C given as its lower triangle with doubled off-diagonal entries (the
+// same quadratic form for symmetric C at half the products), stored in row
+// blocks (see lower_quadform).  A lane reads
+// back only the amplitudes it wrote itself, so no cross-lane exchange of
+// amplitudes is needed; the pair partner adds the other plane with one DPP
+// move.  Without helicities the tile loops over all 2^n configurations and
+// sums.
+//
+// Colour-dressed chunk (n >= 8 in the batch): up to 64 consecutive events are
+// classified one per lane (closed colour circuit, as in cdbg_impl.h); invalid
+// ones get exactly 0 and the valid ones are evaluated one at a time by the
+// whole wave.
+#pragma once
+
+#include <stdint.h>
+
+#include "cdbg_impl.h"
+#include "cobg_pair_impl.h"
+
+namespace bg {
+namespace fusedk {
+
+constexpr int kTileEvents = 32;  // events per colour-ordered sub-tile (one per lane pair)
+
+template <int N>
+struct Cobg {
+  static constexpr int K = (int)Factorial<N - 2>::value;
+  static constexpr int kScratch = 2 * K * kTileEvents;  // doubles per block
+};
+
+// Row block of the colour quadratic form (divides K = (n-2)!).
+template <int K>
+struct RowBlock {
+  static constexpr int value = K < 8 ? K : 8;
+};
+
+// a^T C a for symmetric C given as its doubled lower triangle in row blocks:
+// for row block b (rows b RB .. b RB + RB - 1) and every column
+// j < (b + 1) RB the RB entries L[b RB + r][j], r = 0..RB-1, are contiguous,
+// where L = 2 C below the diagonal, C on it and 0 above.  One scalar load of
+// RB entries then serves the RB products of one loaded a_j.  a[j] is read at
+// a[j * stride].
+template <int K>
+__device__ __forceinline__ double lower_quadform(const double* __restrict__ Cb, const double* a,
+                                                 int stride) {
+  constexpr int RB = RowBlock<K>::value;
+  static_assert(K % RB == 0, "row block must divide K");
+  double q = 0.0;
+  const double* cb = Cb;
+#pragma unroll 1
+  for (int ib = 0; ib < K; ib += RB) {
+    double y[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) y[r] = 0.0;
+    const int jend = ib + RB;
+#pragma unroll 2
+    for (int j = 0; j < jend; ++j) {
+      const double aj = a[j * stride];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) y[r] += cb[j * RB + r] * aj;
+    }
+    cb += jend * RB;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) q += a[(ib + r) * stride] * y[r];
+  }
+  return q;
+}
+
+// Colour-summed |M|^2 of events [first, first + count) (count <= 32) of an
+// [n][4][E] input.  HSUM: sum over all 2^n helicity configurations (hel is
+// ignored); otherwise one configuration per event from hel.
+template <int N, typename T, bool HSUM>
+__device__ __forceinline__ void cobg_tile(unsigned char* lds, int64_t E,
+                                          const double* __restrict__ mom,
+                                          const int8_t* __restrict__ hel,
+                                          const double* __restrict__ Cl, double* blk,
+                                          double* __restrict__ me2, int64_t first, int count) {
+  constexpr int K = Cobg<N>::K;
+  const int lane = threadIdx.x;
+  const int pair = lane >> 1;
+  const int h = lane & 1;
+  const bool live = pair < count;
+  int64_t e = first + (live ? pair : count - 1);
+  double q = 0.0;
+  if constexpr (HSUM) {
+    for (int hc = 0; hc < (1 << N); ++hc) {
+      // keep the momentum loads inside the loop: hoisting them would hold
+      // 4n FP64 values live through the whole recursion
+      asm volatile("" : "+v"(e));
+      pairk::cobg_pair_body<N, T>(lds, E, mom, nullptr, hc, e, true, blk, kTileEvents, pair);
+      q += lower_quadform<K>(Cl, blk + (size_t)h * K * kTileEvents + pair, kTileEvents);
+      __syncthreads();  // the next configuration rewrites LDS and scratch
+    }
+  } else {
+    pairk::cobg_pair_body<N, T>(lds, E, mom, hel, 0, e, true, blk, kTileEvents, pair);
+    q = lower_quadform<K>(Cl, blk + (size_t)h * K * kTileEvents + pair, kTileEvents);
+    __syncthreads();
+  }
+  const double tot = pairk::pair_sum(q);
+  if (live && h == 0) me2[e] = tot;
+}
+
+// Colour-dressed |A|^2 of events [first, first + count), count <= 64.
+template <int N, typename T>
+__device__ __forceinline__ void cdbg_chunk(unsigned char* lds, int64_t E,
+                                           const double* __restrict__ mom,
+                                           const int8_t* __restrict__ hel,
+                                           const int8_t* __restrict__ col,
+                                           double* __restrict__ me2, int64_t first, int count) {
+  const cdbgk::Sm<N, T> sm = cdbgk::carve<N, T>(lds);
+  const int lane = threadIdx.x;
+  bool valid = false;
+  if (lane < count) {
+    valid = cdbgk::flow_valid(N, E, col, first + lane);
+    if (!valid) me2[first + lane] = 0.0;
+  }
+  uint64_t m = __ballot(valid);
+  while (m) {
+    const int l = __builtin_ctzll(m);
+    m &= m - 1;
+    cdbgk::cdbg_one_event<N, T>(sm, E, mom, hel, col, first + l, me2);
+  }
+}
+
+}  // namespace fusedk
+}  // namespace bg

@@ -8,6 +8,7 @@ as written (a fused multiply-add counts 2, a complex product 6 = 4 mul + 2 add):
   range momentum (four additions)                                 4
   final contraction with the last polarization (+ coupling)      32
 Colour contraction x^T C x + y^T C y with K orderings:     4K^2 + 4K
+  (the fused kernel uses the symmetry of C: 2K(K+1) + 4K)
 The colour-ordered recursion walks the orderings depth first and shares
 prefixes: column d (ranges ending at position d) is evaluated once per
 distinct prefix of length d+1, i.e. (n-2)!/(n-2-d)! times.
@@ -47,6 +48,14 @@ def cobg_flops_per_event(n):
 def contraction_flops_per_event(n):
     K = math.factorial(n - 2)
     return 4 * K * K + 4 * K
+
+
+def colour_sum_flops_per_event(n):
+    """FP64 flops of the fused colour sum x^T C x + y^T C y using the symmetry
+    of C: K(K+1)/2 multiply-adds for the triangle and K for the outer
+    products, per plane."""
+    K = math.factorial(n - 2)
+    return 2 * 2 * (K * (K + 1) // 2 + K)
 
 
 def cobg_bytes_per_event(n, amp_out=True):

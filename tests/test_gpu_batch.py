@@ -1,0 +1,227 @@
+"""Persistent mixed-multiplicity batch on the GPU.
+
+The batch kernel evaluates every event with the same device routines as the
+single-request entry point (fused colour-ordered tiles for n <= 7,
+colour-dressed chunks for n >= 8).  In FP64 its output equals bg_me2 on each
+segment alone bit for bit; in FP32 the two kernels may contract multiply-adds
+differently, so they agree to the recursion's rounding.  Within the batch
+kernel the result does not depend on tile or grid shape (bit for bit).  A few
+events of each segment are also checked against the oracle directly.
+"""
+import numpy as np
+import pytest
+
+from bg_inputs import make_events, mixed_workload
+from oracle import cdbg as ocdbg
+from oracle import me2 as ome2
+from tests.helpers import nonvanishing
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_06507_amd import api as a
+    return a
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _segments(events):
+    segs = []
+    for n, ev in sorted(events.items()):
+        col = _dev(ev["col"]) if n >= 8 else None
+        segs.append({"n": n, "mom": _dev(ev["mom"]), "hel": _dev(ev["hel"]), "col": col,
+                     "mode": "auto"})
+    return segs
+
+
+def _single(api, segs, precision):
+    return [api.me2(s["mom"], s["hel"], s["col"], mode="auto", precision=precision) for s in segs]
+
+
+def _same(segs, got, ref, precision, label=""):
+    """FP64: bit-identical.  FP32: the two kernels may contract multiply-adds
+    differently, so the recursion's rounding differs; per-event relative
+    difference median <= 1e-6 and max <= 1e-2 (the conditioning tail of the
+    FP32 parity tests) on events with a non-vanishing tree amplitude; for the
+    colour-dressed segments the zeros (invalid colour flows) coincide."""
+    for s, g, r in zip(segs, got, ref):
+        g, r = g.cpu().numpy(), r.cpu().numpy()
+        if precision == "fp64":
+            assert np.array_equal(g, r), f"{label} n={s['n']}"
+            continue
+        keep = nonvanishing(s["hel"].cpu().numpy())
+        if s["n"] >= 8:
+            assert np.array_equal(g == 0.0, r == 0.0), f"{label} n={s['n']}"
+            keep &= r != 0.0
+        rel = np.abs(g - r)[keep] / np.abs(r[keep])
+        _say(f"  {label} n={s['n']}: events differing {(g != r).sum()} of {g.size}, "
+             f"rel diff median {np.median(rel):.1e} max {rel.max():.1e}")
+        assert np.median(rel) <= 1e-6 and rel.max() <= 1e-2, f"{label} n={s['n']}"
+
+
+def _small_mix():
+    sizes = {4: 300, 5: 257, 6: 130, 7: 40, 8: 700, 9: 260}
+    return {n: make_events(n, E, seed=7000 + n, cuts=True, sample_col=n >= 8)
+            for n, E in sizes.items()}
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batch_equals_single_requests(api, precision):
+    segs = _segments(_small_mix())
+    _say(f"bg_me2_batch small mix {precision}: " + ", ".join(f"n={s['n']} E={s['mom'].shape[2]}" for s in segs))
+    got = api.me2_batch(segs, precision)
+    ref = _single(api, segs, precision)
+    torch.cuda.synchronize()
+    _same(segs, got, ref, precision, "batch vs single")
+
+
+def test_batch_spot_checks_against_oracle(api):
+    ev = _small_mix()
+    segs = _segments(ev)
+    got = [g.cpu().numpy() for g in api.me2_batch(segs, "fp64")]
+    for s, g in zip(segs, got):
+        n = s["n"]
+        e = ev[n]
+        if n <= 7:
+            idx = np.nonzero(nonvanishing(e["hel"]))[0][:4]
+            ref = ome2.me2_cobg(e["mom"][:, :, idx], e["hel"][:, idx])
+        else:
+            valid = ocdbg.is_valid_flow(e["col"])
+            assert np.all(g[~valid] == 0.0)
+            idx = np.nonzero(valid & nonvanishing(e["hel"]))[0][:3]
+            ref = np.abs(ocdbg.flow_amplitude(e["mom"][:, :, idx], e["hel"][:, idx],
+                                              e["col"][:, :, idx])) ** 2
+        rel = np.abs(g[idx] - ref) / np.abs(ref)
+        _say(f"  n={n} oracle spot check max rel {rel.max():.2e}")
+        assert rel.max() < 1e-9
+
+
+@pytest.mark.parametrize("cfg", [
+    dict(blocks_per_cu=1, cobg_tile_events=32, cdbg_tile_events=64),
+    dict(blocks_per_cu=2, cobg_tile_events=128, cdbg_tile_events=512),
+    dict(blocks_per_cu=0, cobg_tile_events=4096, cdbg_tile_events=4096),
+])
+def test_batch_result_independent_of_config(api, cfg):
+    """Same kernel, other tiles and grid: bit-identical results."""
+    segs = _segments(_small_mix())
+    ref = [r.clone() for r in api.me2_batch(segs, "fp32")]
+    old = api.batch_config("fp32")
+    try:
+        api.set_batch_config("fp32", **cfg)
+        _say(f"bg_me2_batch config {cfg}")
+        got = api.me2_batch(segs, "fp32")
+        torch.cuda.synchronize()
+    finally:
+        api.set_batch_config("fp32", **old)
+    for g, r in zip(got, ref):
+        assert torch.equal(g, r)
+
+
+def test_batch_rejects_bad_requests(api):
+    from paper_2106_06507_amd._lib import BGError
+    segs = _segments(_small_mix())
+    with pytest.raises(ValueError):
+        api.me2_batch([{"mom": segs[0]["mom"], "hel": None}], "fp32")
+    with pytest.raises(BGError):  # colour-ordered mode above n = 7
+        api.me2_batch([dict(segs[4], mode="cobg")], "fp32")
+    with pytest.raises(BGError):  # colour-dressed without colours
+        api.me2_batch([dict(segs[4], col=None, mode="cdbg")], "fp32")
+    with pytest.raises(BGError):
+        api.set_batch_config("fp32", cobg_tile_events=48)
+    assert api.me2_batch([], "fp32") == []
+
+
+def test_batch_fp32_against_oracle(api):
+    """FP32 recursion in the batch kernel against the FP64 oracle on a few
+    events per segment (per-event relative error, non-vanishing helicities)."""
+    ev = _small_mix()
+    segs = _segments(ev)
+    got = [g.cpu().numpy() for g in api.me2_batch(segs, "fp32")]
+    for s, g in zip(segs, got):
+        n = s["n"]
+        e = ev[n]
+        if n <= 7:
+            idx = np.nonzero(nonvanishing(e["hel"]))[0][:8]
+            ref = ome2.me2_cobg(e["mom"][:, :, idx], e["hel"][:, idx])
+        else:
+            idx = np.nonzero(ocdbg.is_valid_flow(e["col"]) & nonvanishing(e["hel"]))[0][:3]
+            ref = np.abs(ocdbg.flow_amplitude(e["mom"][:, :, idx], e["hel"][:, idx],
+                                              e["col"][:, :, idx])) ** 2
+        rel = np.abs(g[idx] - ref) / np.abs(ref)
+        _say(f"  n={n} fp32 oracle spot check median {np.median(rel):.1e} max {rel.max():.1e}")
+        assert np.median(rel) < 1e-5 and rel.max() < 1e-2
+
+
+def test_batch_empty_and_tiny_segments(api):
+    ev = {4: make_events(4, 1, seed=7100), 8: make_events(8, 3, seed=7101, sample_col=True),
+          6: make_events(6, 33, seed=7102)}
+    segs = _segments(ev)
+    empty = {"n": 5, "mom": torch.empty((5, 4, 0), dtype=torch.float64, device="cuda"),
+             "hel": torch.empty((5, 0), dtype=torch.int8, device="cuda"), "col": None}
+    got = api.me2_batch(segs + [empty], "fp64")
+    ref = _single(api, segs, "fp64")
+    _same(segs, got, ref, "fp64", "tiny")
+    assert got[-1].numel() == 0
+
+
+def test_batch_graph_replays(api):
+    """Recorded launch replayed several times, with eager work and
+    synchronisation between replays; every replay equals the eager result."""
+    segs = _segments(_small_mix())
+    ref = [r.clone() for r in api.me2_batch(segs, "fp32")]
+    single = api.me2(segs[2]["mom"], segs[2]["hel"], precision="fp32").clone()
+    g = api.BatchGraph(segs, "fp32")
+    for k in range(4):
+        for o in g.outs:
+            o.fill_(-1.0)
+        outs = g.replay()
+        torch.cuda.synchronize()
+        for o, r in zip(outs, ref):
+            assert torch.equal(o, r), f"replay {k}"
+        # unrelated eager work between replays
+        other = api.me2(segs[2]["mom"], segs[2]["hel"], precision="fp32")
+        torch.cuda.synchronize()
+        assert torch.equal(other, single)
+
+
+def test_batch_autotune(api):
+    segs = _segments(_small_mix())
+    ref = [r.clone() for r in api.me2_batch(segs, "fp32")]
+    old = api.batch_config("fp32")
+    try:
+        cfg, ms = api.batch_tune(segs, "fp32")
+        _say(f"  tuned {cfg} {ms:.3f} ms")
+        assert ms > 0
+        assert api.batch_config("fp32") == cfg
+        got = api.me2_batch(segs, "fp32")
+        torch.cuda.synchronize()
+    finally:
+        api.set_batch_config("fp32", **old)
+    for g, r in zip(got, ref):
+        assert torch.equal(g, r)
+
+
+def test_full_size_mixed_batch(api):
+    """The mixed workload at full size (n = 4..9, log-uniform counts in
+    [2^10, 2^20]) in one launch, FP32 recursion: equal to the single-request
+    results on every event."""
+    ev = mixed_workload()
+    segs = _segments(ev)
+    _say("bg_me2_batch full mix: " + ", ".join(f"n={s['n']} E={s['mom'].shape[2]}" for s in segs))
+    got = api.me2_batch(segs, "fp32")
+    ref = _single(api, segs, "fp32")
+    torch.cuda.synchronize()
+    for g in got:
+        assert torch.isfinite(g).all()
+    _same(segs, got, ref, "fp32", "full mix")

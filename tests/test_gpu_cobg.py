@@ -104,6 +104,35 @@ def test_helicity_sum_gg_gg(api):
 
 
 @pytest.mark.parametrize("n", [5, 6])
+def test_helicity_sum_fused(api, n):
+    """Helicity-summed |M|^2 (all 2^n configurations inside the fused kernel)."""
+    E = 40 if n == 5 else 12
+    mom, _ = _events(n, E, 3150 + n)
+    _say(f"bg_me2 helicity sum n={n} E={E}")
+    got = api.me2(_dev(mom), None).cpu().numpy()
+    ref = ome2.me2_cobg(mom, None)
+    assert np.max(np.abs(got - ref) / ref) < FP64_ME2_RTOL
+
+
+@pytest.mark.parametrize("n", [4, 5, 6, 7])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fused_equals_two_stage(api, n, precision):
+    """bg_me2 (recursion and colour sum in one kernel) against bg_currents
+    followed by bg_color_contract (amplitudes through memory, matrix cores at
+    n = 6): same amplitudes, colour sums in a different order."""
+    E = 1000 if n < 7 else 200
+    mom, hel = _events(n, E, 3180 + n)
+    dm, dh = _dev(mom), _dev(hel)
+    _say(f"fused vs two-stage {precision} n={n} E={E}")
+    fused = api.me2(dm, dh, precision=precision).cpu().numpy()
+    two = api.color_contract(api.currents(dm, dh, precision), n).cpu().numpy()
+    nz = nonvanishing(hel)
+    rel = np.abs(fused - two)[nz] / np.abs(two[nz])
+    _say(f"  max rel {rel.max():.2e}")
+    assert rel.max() < 1e-12
+
+
+@pytest.mark.parametrize("n", [5, 6])
 def test_contraction_matches_oracle(api, n):
     """bg_color_contract on oracle amplitudes (matrix cores at n = 6)."""
     E = 300

@@ -69,6 +69,10 @@ def test_entry_points_validate_before_launch():
     assert L.bg_me2(None, ctypes.byref(req), None) == _lib.BG_EINVAL
     assert L.bg_me2_grad(None, ctypes.byref(req), None, None, None) == _lib.BG_EINVAL
     assert L.bg_me2_batch(None, ctypes.byref(req), 1, None) == _lib.BG_EINVAL
+    assert L.bg_me2_batch_tune(None, ctypes.byref(req), 1, None, None, None) == _lib.BG_EINVAL
+    cfg = _lib.bg_batch_config(0, 64, 256, 0)
+    assert L.bg_batch_config_get(None, 0, ctypes.byref(cfg)) == _lib.BG_EINVAL
+    assert L.bg_batch_config_set(None, 0, ctypes.byref(cfg)) == _lib.BG_EINVAL
     L.bg_context_destroy(None)  # no-op
 
 
