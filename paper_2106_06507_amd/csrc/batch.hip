@@ -5,22 +5,42 @@
 namespace bg {
 namespace fusedk {
 
-// Grid-stride over 32-event tiles; each block owns one scratch slice, reused
-// for every tile it processes.
+// n <= 6: one 32-event tile per block, amplitudes in LDS; the hardware
+// dispatcher balances the blocks.
 template <int N, typename T, bool HSUM>
 __global__ void __launch_bounds__(64) cobg_fused_kernel(int64_t E, const double* __restrict__ mom,
                                                        const int8_t* __restrict__ hel,
-                                                       const double* __restrict__ Cl,
-                                                       double* __restrict__ scratch,
+                                                       const double* __restrict__ Cb,
                                                        double* __restrict__ me2) {
   extern __shared__ __align__(16) unsigned char bg_fused_lds[];
-  double* blk = scratch + (size_t)blockIdx.x * Cobg<N>::kScratch;
-  const int64_t tiles = (E + kTileEvents - 1) / kTileEvents;
-  for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
-    const int64_t first = t * kTileEvents;
+  const int64_t first = (int64_t)blockIdx.x * kTileEvents;
+  const int64_t left = E - first;
+  cobg_tile<N, T, HSUM>(bg_fused_lds, E, mom, hel, Cb, nullptr, me2, first,
+                        (int)(left < kTileEvents ? left : kTileEvents));
+}
+
+// n = 7: persistent blocks, each with its own scratch slice, take tiles from
+// an atomic queue (reset by zero_counter_kernel before the launch).
+template <typename T, bool HSUM>
+__global__ void __launch_bounds__(64) cobg_fused_queue_kernel(int64_t E,
+                                                             const double* __restrict__ mom,
+                                                             const int8_t* __restrict__ hel,
+                                                             const double* __restrict__ Cb,
+                                                             double* __restrict__ scratch,
+                                                             unsigned* __restrict__ counter,
+                                                             double* __restrict__ me2) {
+  extern __shared__ __align__(16) unsigned char bg_fused_lds[];
+  double* blk = scratch + (size_t)blockIdx.x * Cobg<7>::kScratch;
+  const unsigned tiles = (unsigned)((E + kTileEvents - 1) / kTileEvents);
+  for (;;) {
+    unsigned t = 0;
+    if (threadIdx.x == 0) t = atomicAdd(counter, 1u);
+    t = (unsigned)__builtin_amdgcn_readfirstlane((int)__shfl(t, 0));
+    if (t >= tiles) break;
+    const int64_t first = (int64_t)t * kTileEvents;
     const int64_t left = E - first;
-    cobg_tile<N, T, HSUM>(bg_fused_lds, E, mom, hel, Cl, blk, me2, first,
-                    (int)(left < kTileEvents ? left : kTileEvents));
+    cobg_tile<7, T, HSUM>(bg_fused_lds, E, mom, hel, Cb, blk, me2, first,
+                          (int)(left < kTileEvents ? left : kTileEvents));
   }
 }
 
@@ -82,24 +102,40 @@ __global__ void __launch_bounds__(64) batch_kernel(const BatchSegTable segs,
 }
 
 template <int N, typename T>
-int fused_launch(int64_t E, const double* mom, const int8_t* hel, const double* Cl,
-                 double* scratch, int grid, double* me2, hipStream_t stream) {
-  if (hel)
-    hipLaunchKernelGGL((cobg_fused_kernel<N, T, false>), dim3(grid), dim3(64),
-                       (pairk::Lds<N>::template bytes<T>()), stream, E, mom, hel, Cl, scratch, me2);
-  else
-    hipLaunchKernelGGL((cobg_fused_kernel<N, T, true>), dim3(grid), dim3(64),
-                       (pairk::Lds<N>::template bytes<T>()), stream, E, mom, hel, Cl, scratch, me2);
+int fused_launch(int64_t E, const double* mom, const int8_t* hel, const double* Cb,
+                 double* scratch, unsigned* counter, int grid, double* me2, hipStream_t stream) {
+  const size_t lds = Cobg<N>::template lds_bytes<T>();
+  if constexpr (Cobg<N>::kLdsAmp) {
+    (void)scratch;
+    (void)counter;
+    (void)grid;
+    const unsigned tiles = (unsigned)((E + kTileEvents - 1) / kTileEvents);
+    if (hel)
+      hipLaunchKernelGGL((cobg_fused_kernel<N, T, false>), dim3(tiles), dim3(64), lds, stream, E,
+                         mom, hel, Cb, me2);
+    else
+      hipLaunchKernelGGL((cobg_fused_kernel<N, T, true>), dim3(tiles), dim3(64), lds, stream, E,
+                         mom, hel, Cb, me2);
+  } else {
+    hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, stream, counter);
+    if (hel)
+      hipLaunchKernelGGL((cobg_fused_queue_kernel<T, false>), dim3(grid), dim3(64), lds, stream,
+                         E, mom, hel, Cb, scratch, counter, me2);
+    else
+      hipLaunchKernelGGL((cobg_fused_queue_kernel<T, true>), dim3(grid), dim3(64), lds, stream,
+                         E, mom, hel, Cb, scratch, counter, me2);
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template <int N, typename T>
+// Blocks per CU of the persistent (n = 7) kernel.
+template <typename T>
 int fused_occupancy(bool hsum) {
   int nb = 0;
-  const size_t lds = pairk::Lds<N>::template bytes<T>();
+  const size_t lds = Cobg<7>::template lds_bytes<T>();
   const hipError_t e =
-      hsum ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cobg_fused_kernel<N, T, true>, 64, lds)
-           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cobg_fused_kernel<N, T, false>, 64, lds);
+      hsum ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cobg_fused_queue_kernel<T, true>, 64, lds)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cobg_fused_queue_kernel<T, false>, 64, lds);
   return e == hipSuccess ? nb : -1;
 }
 
@@ -117,32 +153,29 @@ int cobg_fused_scratch_doubles(int n) {
 
 size_t cobg_lds_bytes(int n, bool fp32) {
   switch (n) {
-    case 4: return fp32 ? pairk::Lds<4>::bytes<float>() : pairk::Lds<4>::bytes<double>();
-    case 5: return fp32 ? pairk::Lds<5>::bytes<float>() : pairk::Lds<5>::bytes<double>();
-    case 6: return fp32 ? pairk::Lds<6>::bytes<float>() : pairk::Lds<6>::bytes<double>();
-    case 7: return fp32 ? pairk::Lds<7>::bytes<float>() : pairk::Lds<7>::bytes<double>();
+    case 4: return fp32 ? fusedk::Cobg<4>::lds_bytes<float>() : fusedk::Cobg<4>::lds_bytes<double>();
+    case 5: return fp32 ? fusedk::Cobg<5>::lds_bytes<float>() : fusedk::Cobg<5>::lds_bytes<double>();
+    case 6: return fp32 ? fusedk::Cobg<6>::lds_bytes<float>() : fusedk::Cobg<6>::lds_bytes<double>();
+    case 7: return fp32 ? fusedk::Cobg<7>::lds_bytes<float>() : fusedk::Cobg<7>::lds_bytes<double>();
     default: return 0;
   }
 }
 
-int cobg_fused_blocks_per_cu(int n, bool fp32, bool hsum) {
-  switch (n) {
-    case 4: return fp32 ? fusedk::fused_occupancy<4, float>(hsum) : fusedk::fused_occupancy<4, double>(hsum);
-    case 5: return fp32 ? fusedk::fused_occupancy<5, float>(hsum) : fusedk::fused_occupancy<5, double>(hsum);
-    case 6: return fp32 ? fusedk::fused_occupancy<6, float>(hsum) : fusedk::fused_occupancy<6, double>(hsum);
-    case 7: return fp32 ? fusedk::fused_occupancy<7, float>(hsum) : fusedk::fused_occupancy<7, double>(hsum);
-    default: return -2;
-  }
+int cobg_fused_persistent_blocks_per_cu(bool fp32, bool hsum) {
+  return fp32 ? fusedk::fused_occupancy<float>(hsum) : fusedk::fused_occupancy<double>(hsum);
 }
 
 int cobg_fused_me2(int n, bool fp32, int64_t E, const double* mom, const int8_t* hel,
-                   const double* Cl, double* scratch, int grid, double* me2, hipStream_t stream) {
+                   const double* Cb, double* scratch, unsigned* counter, int grid, double* me2,
+                   hipStream_t stream) {
   if (E <= 0) return 0;
   switch (n) {
 #define BG_CASE(NN)                                                                              \
   case NN:                                                                                       \
-    return fp32 ? fusedk::fused_launch<NN, float>(E, mom, hel, Cl, scratch, grid, me2, stream)   \
-                : fusedk::fused_launch<NN, double>(E, mom, hel, Cl, scratch, grid, me2, stream);
+    return fp32 ? fusedk::fused_launch<NN, float>(E, mom, hel, Cb, scratch, counter, grid, me2,  \
+                                                  stream)                                        \
+                : fusedk::fused_launch<NN, double>(E, mom, hel, Cb, scratch, counter, grid, me2, \
+                                                   stream);
     BG_CASE(4)
     BG_CASE(5)
     BG_CASE(6)

@@ -48,11 +48,12 @@ struct bg_context {
   double* scratch = nullptr;                 // per-block scratch of the fused and batch kernels
   size_t scratch_bytes = 0;
   std::vector<void*> retired;                // outgrown scratch buffers, freed on destroy
-  unsigned* counter = nullptr;               // batch tile-queue head
+  unsigned* counter = nullptr;               // tile-queue heads: [0] batch, [1] fused n = 7
   bg_batch_config bcfg[2] = {{0, 64, 256, 0}, {0, 64, 256, 0}};
   std::vector<BatchPlan> plans;
   uint64_t clock = 0;
-  int occ_fused[BG_N_MAX + 1][2][2] = {};    // blocks per CU of the fused kernel, 0 = unknown
+  int occ_fused[2][2] = {};                  // blocks per CU of the persistent fused kernel
+                                             // [fp32][helicity sum], 0 = unknown
   int occ_batch[2] = {};                     // of the batch kernel at its last LDS size
   size_t occ_batch_lds[2] = {};
 };
@@ -345,10 +346,9 @@ int bg_color_contract(bg_context* ctx, int n, int64_t E, const double* amp, doub
   return contract_dispatch(ctx, n, E, amp, me2, accumulate, (hipStream_t)stream);
 }
 
-static int fused_occupancy(bg_context* ctx, int n, bool fp32, bool hsum) {
-  int& occ = ctx->occ_fused[n][fp32 ? 1 : 0][hsum ? 1 : 0];
-  if (occ <= 0) occ = bg::cobg_fused_blocks_per_cu(n, fp32, hsum);
-  return occ;
+static int ensure_counters(bg_context* ctx) {
+  if (ctx->counter) return BG_OK;
+  return hip_status(hipMalloc(&ctx->counter, 256), "hipMalloc(counters)");
 }
 
 static int me2_cobg(bg_context* ctx, const bg_request* r, hipStream_t stream) {
@@ -359,14 +359,19 @@ static int me2_cobg(bg_context* ctx, const bg_request* r, hipStream_t stream) {
   if (st) return st;
   const bool fp32 = r->precision == BG_PREC_FP32_MIXED;
   const bool hsum = r->hel == nullptr;
-  const int occ = fused_occupancy(ctx, n, fp32, hsum);
-  if (occ <= 0) return BG_EDEVICE;
-  const int64_t tiles = (E + 31) / 32;
-  const int64_t grid = std::min<int64_t>(tiles, (int64_t)ctx->num_cus * occ);
-  st = ensure_scratch(ctx, sizeof(double) * (size_t)grid * bg::cobg_fused_scratch_doubles(n));
-  if (st) return st;
+  int64_t grid = 0;
+  if (n == 7) {  // persistent kernel with per-block scratch
+    int& occ = ctx->occ_fused[fp32 ? 1 : 0][hsum ? 1 : 0];
+    if (occ <= 0) occ = bg::cobg_fused_persistent_blocks_per_cu(fp32, hsum);
+    if (occ <= 0) return BG_EDEVICE;
+    grid = std::min<int64_t>((E + 31) / 32, (int64_t)ctx->num_cus * occ);
+    st = ensure_scratch(ctx, sizeof(double) * (size_t)grid * bg::cobg_fused_scratch_doubles(n));
+    if (!st) st = ensure_counters(ctx);
+    if (st) return st;
+  }
   return launch_status(bg::cobg_fused_me2(n, fp32, E, r->mom, r->hel, ctx->Cb_dev[n], ctx->scratch,
-                                          (int)grid, r->me2, stream));
+                                          ctx->counter ? ctx->counter + 1 : nullptr, (int)grid,
+                                          r->me2, stream));
 }
 
 static int me2_cdbg(bg_context* ctx, const bg_request* r, hipStream_t stream) {
@@ -649,11 +654,8 @@ int batch_run(bg_context* ctx, const bg_request* segs, int n_segs, const bg_batc
       return BG_EINVAL;
     }
     st = ensure_scratch(ctx, need);
+    if (!st) st = ensure_counters(ctx);
     if (st) return st;
-    if (!ctx->counter) {
-      st = hip_status(hipMalloc(&ctx->counter, 256), "hipMalloc(counter)");
-      if (st) return st;
-    }
   }
   return launch_status(bg::batch_launch(fp32, tab, pl->tiles, pl->n_tiles, ctx->counter,
                                         ctx->scratch, stride, (int)grid, lds, stream));

@@ -54,13 +54,17 @@ int mfma_probe(double* out_dev, hipStream_t stream);
 int contract_mfma(int K, int64_t E, const double* amp, const double* C_pad, int KP, double* me2,
                   int accumulate, hipStream_t stream);
 
-// Fused colour-ordered |M|^2: recursion and colour sum in one persistent
-// grid-stride kernel.  Cl is the colour matrix as doubled lower triangle
-// [K][K]; scratch holds grid * cobg_fused_scratch_doubles(n) doubles.
+// Fused colour-ordered |M|^2: recursion and colour sum in one kernel.  Cb is
+// the colour matrix as doubled lower triangle in row blocks.  n <= 6: one
+// block per 32-event tile (scratch, counter and grid unused).  n = 7:
+// persistent grid of `grid` blocks over an atomic tile queue; scratch holds
+// grid * cobg_fused_scratch_doubles(7) doubles, counter one unsigned.
 int cobg_fused_me2(int n, bool fp32, int64_t E, const double* mom, const int8_t* hel,
-                   const double* Cl, double* scratch, int grid, double* me2, hipStream_t stream);
+                   const double* Cb, double* scratch, unsigned* counter, int grid, double* me2,
+                   hipStream_t stream);
 int cobg_fused_scratch_doubles(int n);
-int cobg_fused_blocks_per_cu(int n, bool fp32, bool hsum);
+int cobg_fused_persistent_blocks_per_cu(bool fp32, bool hsum);
+// LDS of a colour-ordered tile (recursion state plus staged amplitudes).
 size_t cobg_lds_bytes(int n, bool fp32);
 
 // Mixed-multiplicity batch.  kind = kBatchCobg + n or kBatchCdbg + n.

@@ -61,8 +61,12 @@ struct Lds {
   }
 };
 
-template <int N, typename T>
+// RAW: amplitudes go unscaled, in T, to amp_raw[(h K + sigma) 32 + pair]
+// (block-private LDS); otherwise scaled, in FP64, to
+// amp[(h K + sigma) astride + acol].
+template <int N, typename T, bool RAW>
 struct Ctx {
+  static constexpr bool kRaw = RAW;
   T* gl_slots;      // [slot][lane]
   T* tab;           // [mask][pair]
   double* p64;      // [2 (g-1) + c][lane]
@@ -70,6 +74,7 @@ struct Ctx {
   T g0;
   H<T> epsN;
   double* amp;
+  T* amp_raw;
   int64_t E, e;       // input stride and event index
   int64_t astride;    // amplitude array stride (events per plane row)
   int64_t acol;       // amplitude column of this event
@@ -103,8 +108,8 @@ __device__ __forceinline__ HR<T> range_mom(const State<N, T>& s) {
   return r;
 }
 
-template <int N, typename T, int D, int A>
-__device__ __forceinline__ void build_range(State<N, T>& s, const Ctx<N, T>& c, int mask,
+template <int N, typename T, int D, int A, class CtxT>
+__device__ __forceinline__ void build_range(State<N, T>& s, const CtxT& c, int mask,
                                             Cx<T>& top) {
   constexpr int M = N - 1;
   constexpr bool kTop = (A == 0 && D == M - 1);
@@ -171,8 +176,8 @@ __device__ __forceinline__ void build_range(State<N, T>& s, const Ctx<N, T>& c, 
   }
 }
 
-template <int N, typename T, int D, int A>
-__device__ __forceinline__ void build_column(State<N, T>& s, const Ctx<N, T>& c, int mask,
+template <int N, typename T, int D, int A, class CtxT>
+__device__ __forceinline__ void build_column(State<N, T>& s, const CtxT& c, int mask,
                                              Cx<T>& top) {
   if constexpr (A >= 0) {
     mask |= 1 << s.gl[A];
@@ -181,8 +186,8 @@ __device__ __forceinline__ void build_column(State<N, T>& s, const Ctx<N, T>& c,
   }
 }
 
-template <int N, typename T, int D>
-__device__ __forceinline__ void level(State<N, T>& s, Ctx<N, T>& c, int used) {
+template <int N, typename T, int D, class CtxT>
+__device__ __forceinline__ void level(State<N, T>& s, CtxT& c, int used) {
   constexpr int M = N - 1;
   for (int g = 1; g <= N - 2; ++g) {  // wave-uniform
     if (used & (1 << g)) continue;
@@ -198,12 +203,16 @@ __device__ __forceinline__ void level(State<N, T>& s, Ctx<N, T>& c, int used) {
     Cx<T> top;
     build_column<N, T, D, D - 1>(s, c, 1 << g, top);
     if constexpr (D == M - 1) {
-      double scale = 1.0;
-#pragma unroll
-      for (int i = 0; i < N - 2; ++i) scale *= kGsOverSqrt2;
       constexpr int64_t K = Factorial<N - 2>::value;
-      const double v = (double)(c.h == 0 ? top.re : top.im) * scale;
-      if (c.live) c.amp[((int64_t)c.h * K + c.sigma) * c.astride + c.acol] = v;
+      if constexpr (CtxT::kRaw) {
+        c.amp_raw[(c.h * (int)K + c.sigma) * Lds<N>::kPairs + c.pair] = c.h == 0 ? top.re : top.im;
+      } else {
+        double scale = 1.0;
+#pragma unroll
+        for (int i = 0; i < N - 2; ++i) scale *= kGsOverSqrt2;
+        const double v = (double)(c.h == 0 ? top.re : top.im) * scale;
+        if (c.live) c.amp[((int64_t)c.h * K + c.sigma) * c.astride + c.acol] = v;
+      }
       ++c.sigma;
     } else {
       level<N, T, D + 1>(s, c, used | (1 << g));
@@ -213,18 +222,20 @@ __device__ __forceinline__ void level(State<N, T>& s, Ctx<N, T>& c, int used) {
 
 // Amplitudes of the event pair of this lane (event e of an [n][4][E] input);
 // padding pairs (live = false) repeat a valid event and store nothing.  The
-// block must be one 64-lane wave; lds holds Lds<N>::bytes<T>().
-template <int N, typename T>
+// block must be one 64-lane wave; lds holds Lds<N>::bytes<T>().  RAW: the
+// unscaled amplitudes go to amp_raw (see Ctx), amp is unused.
+template <int N, typename T, bool RAW = false>
 __device__ __forceinline__ void cobg_pair_body(unsigned char* lds, int64_t E,
                                                const double* __restrict__ mom,
                                                const int8_t* __restrict__ hel, int hconf,
                                                int64_t e, bool live, double* __restrict__ amp,
-                                               int64_t astride, int64_t acol) {
+                                               int64_t astride, int64_t acol,
+                                               T* amp_raw = nullptr) {
   constexpr int M = N - 1;
   const int lane = threadIdx.x;
   const int pair = lane >> 1;
   const int h = lane & 1;
-  Ctx<N, T> c;
+  Ctx<N, T, RAW> c;
   c.gl_slots = reinterpret_cast<T*>(lds);
   c.tab = c.gl_slots + (size_t)Lds<N>::kGluonSlots * Lds<N>::kLanes;
   c.p64 = reinterpret_cast<double*>(c.tab + (size_t)Lds<N>::kTabEntries * Lds<N>::kPairs);
@@ -233,6 +244,7 @@ __device__ __forceinline__ void cobg_pair_body(unsigned char* lds, int64_t E,
   c.h = h;
   c.g0 = h == 0 ? T(1) : T(-1);
   c.amp = amp;
+  c.amp_raw = amp_raw;
   c.E = E;
   c.e = e;
   c.astride = astride;

@@ -2,10 +2,9 @@
 // mixed-multiplicity batch kernel.
 //
 // Colour-ordered tile (n <= 7): 32 events on one 64-lane wave (lane pairs, as
-// in cobg_pair_impl.h).  The (n-2)! partial amplitudes of the tile go to a
-// block-private scratch [2][K][32] (real and imaginary planes), which stays in
-// L2 because the same block reuses it for every tile it processes; then each
-// lane forms the colour sum (eq. color_summed_analytic) of its plane,
+// in cobg_pair_impl.h).  The (n-2)! partial amplitudes of the tile are staged
+// as [2][K][32] (real and imaginary planes; where, see Cobg); then each lane
+// forms the colour sum (eq. color_summed_analytic) of its plane,
 //   q_h = a_h^T C a_h,  a_0 = Re A, a_1 = Im A,   |M|^2 = q_0 + q_1,
 // with C given as its lower triangle with doubled off-diagonal entries (the
 // same quadratic form for symmetric C at half the products), stored in row
@@ -31,10 +30,20 @@ namespace fusedk {
 
 constexpr int kTileEvents = 32;  // events per colour-ordered sub-tile (one per lane pair)
 
+// Where a tile keeps its amplitudes: up to n = 6 in LDS, unscaled, in the
+// recursion's type (at most 12 KB); at n = 7 (K = 120) in a block-private
+// FP64 scratch slice of device memory, which stays in L2 because the block
+// reuses it for every tile it takes.
 template <int N>
 struct Cobg {
   static constexpr int K = (int)Factorial<N - 2>::value;
-  static constexpr int kScratch = 2 * K * kTileEvents;  // doubles per block
+  static constexpr bool kLdsAmp = N <= 6;
+  static constexpr int kScratch = kLdsAmp ? 0 : 2 * K * kTileEvents;  // doubles per block
+  template <typename T>
+  static constexpr size_t lds_bytes() {
+    return pairk::Lds<N>::template bytes<T>() +
+           (kLdsAmp ? sizeof(T) * 2 * (size_t)K * kTileEvents : 0);
+  }
 };
 
 // Row block of the colour quadratic form (divides K = (n-2)!).
@@ -49,8 +58,8 @@ struct RowBlock {
 // where L = 2 C below the diagonal, C on it and 0 above.  One scalar load of
 // RB entries then serves the RB products of one loaded a_j.  a[j] is read at
 // a[j * stride].
-template <int K>
-__device__ __forceinline__ double lower_quadform(const double* __restrict__ Cb, const double* a,
+template <int K, typename A>
+__device__ __forceinline__ double lower_quadform(const double* __restrict__ Cb, const A* a,
                                                  int stride) {
   constexpr int RB = RowBlock<K>::value;
   static_assert(K % RB == 0, "row block must divide K");
@@ -64,46 +73,62 @@ __device__ __forceinline__ double lower_quadform(const double* __restrict__ Cb, 
     const int jend = ib + RB;
 #pragma unroll 2
     for (int j = 0; j < jend; ++j) {
-      const double aj = a[j * stride];
+      const double aj = (double)a[j * stride];
 #pragma unroll
       for (int r = 0; r < RB; ++r) y[r] += cb[j * RB + r] * aj;
     }
     cb += jend * RB;
 #pragma unroll
-    for (int r = 0; r < RB; ++r) q += a[(ib + r) * stride] * y[r];
+    for (int r = 0; r < RB; ++r) q += (double)a[(ib + r) * stride] * y[r];
   }
   return q;
 }
 
 // Colour-summed |M|^2 of events [first, first + count) (count <= 32) of an
 // [n][4][E] input.  HSUM: sum over all 2^n helicity configurations (hel is
-// ignored); otherwise one configuration per event from hel.
+// ignored); otherwise one configuration per event from hel.  lds holds
+// Cobg<N>::lds_bytes<T>(); blk is the block's scratch slice (n = 7 only).
 template <int N, typename T, bool HSUM>
 __device__ __forceinline__ void cobg_tile(unsigned char* lds, int64_t E,
                                           const double* __restrict__ mom,
                                           const int8_t* __restrict__ hel,
-                                          const double* __restrict__ Cl, double* blk,
+                                          const double* __restrict__ Cb, double* blk,
                                           double* __restrict__ me2, int64_t first, int count) {
   constexpr int K = Cobg<N>::K;
+  constexpr bool kL = Cobg<N>::kLdsAmp;
+  T* amp_lds = reinterpret_cast<T*>(lds + pairk::Lds<N>::template bytes<T>());
   const int lane = threadIdx.x;
   const int pair = lane >> 1;
   const int h = lane & 1;
   const bool live = pair < count;
   int64_t e = first + (live ? pair : count - 1);
+  auto one = [&](const int8_t* hp, int hc) -> double {
+    if constexpr (kL) {
+      pairk::cobg_pair_body<N, T, true>(lds, E, mom, hp, hc, e, true, nullptr, 0, 0, amp_lds);
+      return lower_quadform<K>(Cb, amp_lds + (size_t)h * K * kTileEvents + pair, kTileEvents);
+    } else {
+      pairk::cobg_pair_body<N, T, false>(lds, E, mom, hp, hc, e, true, blk, kTileEvents, pair);
+      return lower_quadform<K>(Cb, blk + (size_t)h * K * kTileEvents + pair, kTileEvents);
+    }
+  };
   double q = 0.0;
   if constexpr (HSUM) {
     for (int hc = 0; hc < (1 << N); ++hc) {
       // keep the momentum loads inside the loop: hoisting them would hold
       // 4n FP64 values live through the whole recursion
       asm volatile("" : "+v"(e));
-      pairk::cobg_pair_body<N, T>(lds, E, mom, nullptr, hc, e, true, blk, kTileEvents, pair);
-      q += lower_quadform<K>(Cl, blk + (size_t)h * K * kTileEvents + pair, kTileEvents);
+      q += one(nullptr, hc);
       __syncthreads();  // the next configuration rewrites LDS and scratch
     }
   } else {
-    pairk::cobg_pair_body<N, T>(lds, E, mom, hel, 0, e, true, blk, kTileEvents, pair);
-    q = lower_quadform<K>(Cl, blk + (size_t)h * K * kTileEvents + pair, kTileEvents);
+    q = one(hel, 0);
     __syncthreads();
+  }
+  if constexpr (kL) {
+    double scale = 1.0;  // (g_s / sqrt2)^(n-2), squared: the amplitudes were stored unscaled
+#pragma unroll
+    for (int i = 0; i < N - 2; ++i) scale *= kGsOverSqrt2;
+    q *= scale * scale;
   }
   const double tot = pairk::pair_sum(q);
   if (live && h == 0) me2[e] = tot;
