@@ -72,5 +72,8 @@ def contraction_bytes_per_event(n):
 # Published MI355X peaks (dense, no sparsity)
 PEAK_FP64_VALU_TFLOPS = 78.6
 PEAK_FP32_VALU_TFLOPS = 157.3
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz: FP32 without packed
+# (two-wide) instructions, the same rate as FP64
+PEAK_FP32_VALU_NOPK_TFLOPS = 78.6
 PEAK_FP64_MFMA_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
