@@ -54,10 +54,9 @@ struct Lay {
   static constexpr int kT = NS * 3 * 12;     // tensors  [mask][slot][re6, im6]
   static constexpr int kP = NS * 4;          // momenta  [mask][mu]
   static constexpr int kI = NS;              // 1/P^2    [mask]
-  static constexpr int kPart = kWave * 20;   // partial sums [lane][8 + 12]
   static constexpr int kItems = NS * 3;      // target list of one size
   static constexpr size_t bytes() {
-    return sizeof(T) * (size_t)(kJ + kT + kP + kI + kPart) + sizeof(int) * (size_t)(NS + kItems + 2 * N + 4);
+    return sizeof(T) * (size_t)(kJ + kT + kP + kI) + sizeof(int) * (size_t)(NS + kItems + 2 * N + 4);
   }
 };
 
@@ -67,7 +66,6 @@ struct Sm {
   T* Tt;
   T* P;
   T* ip2;
-  T* part;
   int* code;   // per mask: 0 zero; 1 | r << 2 | c << 4 unbalanced; 2 | touched << 6 balanced
   int* items;
   int* ci;     // colours i_k
@@ -84,8 +82,7 @@ __device__ __forceinline__ Sm<N, T> carve(unsigned char* raw) {
   s.Tt = s.J + L::kJ;
   s.P = s.Tt + L::kT;
   s.ip2 = s.P + L::kP;
-  s.part = s.ip2 + L::kI;
-  int* ip = reinterpret_cast<int*>(s.part + L::kPart);
+  int* ip = reinterpret_cast<int*>(s.ip2 + L::kI);
   s.code = ip;
   s.items = s.code + L::NS;
   s.ci = s.items + L::kItems;
@@ -127,6 +124,25 @@ __device__ __forceinline__ void tdotj_acc(T* gre, T* gim, const T* tre, const T*
   BG_CM(tre[5], tim[5], jre[2], jim[2], r, i) sr += r; si += i;
   gre[3] += sgn * sr; gim[3] += sgn * si;
 #undef BG_CM
+}
+
+// The x-th subset of S in the order of the binary counter over S's bits
+// (bit b of x selects the b-th lowest member of S): x = 1 .. 2^|S| - 2 runs
+// over the non-empty proper subsets.
+__device__ __forceinline__ int subset_of(int x, int S) {
+  int r = 0;
+  for (int b = 0; S; ++b) {
+    const int low = S & -S;
+    if (x & (1 << b)) r |= low;
+    S ^= low;
+  }
+  return r;
+}
+
+// v from lane + off (own value where that lane does not exist).
+template <typename T>
+__device__ __forceinline__ T shfl_down_t(T v, int off) {
+  return __shfl_down(v, (unsigned)off, kWave);
 }
 
 // Operand slots of split (S1, S2) feeding target slot t of S; false if none.
@@ -228,14 +244,65 @@ __device__ __forceinline__ void split_contrib(const Sm<N, T>& sm, int m1, int m2
   }
 }
 
+// Degrees, touched colours and connectivity of a set of colour edges
+// j -> i over the three colours, kept in registers (packed union-find: two
+// bits of parent per colour).
+struct ColourGraph {
+  int d0 = 0, d1 = 0, d2 = 0;  // out - in degree per colour
+  int par = 0 | (1 << 2) | (2 << 4);
+  int touched = 0;
+
+  __device__ __forceinline__ int find(int a) const {
+    int p = (par >> (2 * a)) & 3;
+    while (p != a) {
+      a = p;
+      p = (par >> (2 * a)) & 3;
+    }
+    return a;
+  }
+  __device__ __forceinline__ void add(int jj, int ii) {
+    d0 += (jj == 0) - (ii == 0);
+    d1 += (jj == 1) - (ii == 1);
+    d2 += (jj == 2) - (ii == 2);
+    touched |= (1 << ii) | (1 << jj);
+    const int a = find(jj), b = find(ii);
+    if (a != b) par = (par & ~(3 << (2 * a))) | (b << (2 * a));
+  }
+  __device__ __forceinline__ bool connected() const {
+    int root = -1;
+    bool conn = true;
+    for (int v = 0; v < 3; ++v) {
+      if (!(touched & (1 << v))) continue;
+      const int a = find(v);
+      if (root < 0) root = a;
+      else if (a != root) conn = false;
+    }
+    return conn;
+  }
+  __device__ __forceinline__ bool balanced() const { return d0 == 0 && d1 == 0 && d2 == 0; }
+  // subset code: 0 zero current; 1 | r << 2 | c << 4 single trail r -> c;
+  // 2 | touched << 6 balanced
+  __device__ __forceinline__ int code() const {
+    if (!connected()) return 0;
+    if (balanced()) return 2 | (touched << 6);
+    const int dv[3] = {d0, d1, d2};
+    int r = -1, c = -1;
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      if (dv[v] == 1) r = v;
+      else if (dv[v] == -1) c = v;
+      else if (dv[v] != 0) return 0;
+    }
+    return (r >= 0 && c >= 0) ? (1 | (r << 2) | (c << 4)) : 0;
+  }
+};
+
 // True if the colour-flow edges j_k -> i_k of event e are balanced (in =
 // out degree at every colour) and connected, i.e. form one closed circuit.
 // Indices outside 0..2 make the event invalid.
 __device__ __forceinline__ bool flow_valid(int n, int64_t E, const int8_t* __restrict__ col,
                                            int64_t e) {
-  int deg[3] = {0, 0, 0};
-  int par[3] = {0, 1, 2};
-  int touched = 0;
+  ColourGraph g;
   bool in_range = true;
   for (int k = 0; k < n; ++k) {
     int ii = col[(int64_t)k * E + e];
@@ -245,24 +312,9 @@ __device__ __forceinline__ bool flow_valid(int n, int64_t E, const int8_t* __res
       ii = 0;
       jj = 0;
     }
-    deg[jj] += 1;
-    deg[ii] -= 1;
-    touched |= (1 << ii) | (1 << jj);
-    int a = jj, b = ii;
-    while (par[a] != a) a = par[a];
-    while (par[b] != b) b = par[b];
-    if (a != b) par[a] = b;
+    g.add(jj, ii);
   }
-  bool conn = true;
-  int root = -1;
-  for (int v = 0; v < 3; ++v) {
-    if (!(touched & (1 << v))) continue;
-    int a = v;
-    while (par[a] != a) a = par[a];
-    if (root < 0) root = a;
-    else if (a != root) conn = false;
-  }
-  return in_range && conn && deg[0] == 0 && deg[1] == 0 && deg[2] == 0;
+  return in_range && g.balanced() && g.connected();
 }
 
 // One valid event (colour flow closes into a circuit) on this 64-lane wave.
@@ -287,45 +339,14 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
   // subset codes, momenta, 1/P^2 (FP64 sums)
   for (int mask = lane + 1; mask < NS; mask += kWave) {
     double q[4] = {0.0, 0.0, 0.0, 0.0};
-    int deg[3] = {0, 0, 0};
-    int par[3] = {0, 1, 2};
-    int touched = 0;
+    ColourGraph g;
     for (int k = 0; k < M; ++k) {
       if (!(mask & (1 << k))) continue;
 #pragma unroll
       for (int mu = 0; mu < 4; ++mu) q[mu] += mom[((int64_t)k * 4 + mu) * E + e];
-      const int ii = sm.ci[k], jj = sm.cj[k];
-      deg[jj] += 1;
-      deg[ii] -= 1;
-      touched |= (1 << ii) | (1 << jj);
-      int a = jj, b = ii;
-      while (par[a] != a) a = par[a];
-      while (par[b] != b) b = par[b];
-      if (a != b) par[a] = b;
+      g.add(sm.cj[k], sm.ci[k]);
     }
-    bool conn = true;
-    int root = -1;
-    for (int v = 0; v < 3; ++v) {
-      if (!(touched & (1 << v))) continue;
-      int a = v;
-      while (par[a] != a) a = par[a];
-      if (root < 0) root = a;
-      else if (a != root) conn = false;
-    }
-    int code = 0;
-    if (conn) {
-      if (deg[0] == 0 && deg[1] == 0 && deg[2] == 0) {
-        code = 2 | (touched << 6);
-      } else {
-        int r = -1, c = -1, bad = 0;
-        for (int v = 0; v < 3; ++v) {
-          if (deg[v] == 1) r = v;
-          else if (deg[v] == -1) c = v;
-          else if (deg[v] != 0) bad = 1;
-        }
-        if (!bad && r >= 0 && c >= 0) code = 1 | (r << 2) | (c << 4);
-      }
-    }
+    const int code = g.code();
     sm.code[mask] = code;
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) sm.P[mask * 4 + mu] = (T)q[mu];
@@ -377,56 +398,53 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
       }
     }
     __syncthreads();
-    // lanes per target
-    int q = 1;
-    while (q * 2 * nitems <= kWave && q < 32) q *= 2;
+    // q adjacent lanes per target, each taking every q-th split directly
+    // (no lane walks the splits it does not evaluate)
+    const int q = (nitems >= kWave || nitems == 0) ? 1 : kWave / nitems;
     const int per_round = kWave / q;
+    const int nsplit = (1 << size) - 2;
     for (int r0 = 0; r0 < nitems; r0 += per_round) {
       const int it = r0 + lane / q;
       const int sub = lane % q;
       T gre[4] = {0, 0, 0, 0}, gim[4] = {0, 0, 0, 0};
       T tre[6] = {0, 0, 0, 0, 0, 0}, tim[6] = {0, 0, 0, 0, 0, 0};
       int S = 0, t = 0;
-      if (it < nitems) {
+      const bool active = lane < q * per_round && it < nitems;
+      if (active) {
         const int item = sm.items[it];
         S = item >> 2;
         t = item & 3;
-        int k = 0;
-        for (int m1 = (S - 1) & S; m1; m1 = (m1 - 1) & S, ++k) {
-          if ((k % q) != sub) continue;
+        for (int k = sub; k < nsplit; k += q) {
+          const int m1 = subset_of(k + 1, S);
           const int m2 = S ^ m1;
           int s1, s2;
           if (!split_slots(sm.code[m1], sm.code[m2], t, s1, s2)) continue;
           split_contrib<N, T>(sm, m1, m2, s1, s2, !top, gre, gim, tre, tim);
         }
       }
-      // fixed-order reduction over the q lanes of a target
-      T* mine = sm.part + lane * 20;
+      // fixed-order tree over the q lanes of a target (all lanes take part)
+      for (int off = 1; off < q; off *= 2) {
+        const bool take = (sub % (2 * off)) == 0 && sub + off < q;
 #pragma unroll
-      for (int x = 0; x < 4; ++x) {
-        mine[x] = gre[x];
-        mine[4 + x] = gim[x];
-      }
-#pragma unroll
-      for (int x = 0; x < 6; ++x) {
-        mine[8 + x] = tre[x];
-        mine[14 + x] = tim[x];
-      }
-      __syncthreads();
-      if (it < nitems && sub == 0) {
-        for (int o = 1; o < q; ++o) {
-          const T* other = sm.part + (lane + o) * 20;
-#pragma unroll
-          for (int x = 0; x < 4; ++x) {
-            gre[x] += other[x];
-            gim[x] += other[4 + x];
-          }
-#pragma unroll
-          for (int x = 0; x < 6; ++x) {
-            tre[x] += other[8 + x];
-            tim[x] += other[14 + x];
+        for (int x = 0; x < 4; ++x) {
+          const T a = shfl_down_t(gre[x], off), b = shfl_down_t(gim[x], off);
+          if (take) {
+            gre[x] += a;
+            gim[x] += b;
           }
         }
+        if (!top) {
+#pragma unroll
+          for (int x = 0; x < 6; ++x) {
+            const T a = shfl_down_t(tre[x], off), b = shfl_down_t(tim[x], off);
+            if (take) {
+              tre[x] += a;
+              tim[x] += b;
+            }
+          }
+        }
+      }
+      if (active && sub == 0) {
         if (top) {
           double p[4], er[4], ei[4];
 #pragma unroll

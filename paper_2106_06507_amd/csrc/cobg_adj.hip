@@ -32,25 +32,31 @@ using pairk::hdot;
 using pairk::hrdot;
 using pairk::pair_sum;
 
-// LDS per 64-lane block (32 events):
-//   T   [6 g + x][lane]     eps half (4) and p half (2) of every gluon g
-//   T   [mask][pair]        1/P_S^2
-//   f64 [mask][pair]        P_S^2
-//   f64 [2 g + c][lane]     FP64 momentum halves
-//   f64 [6 g + x][lane]     adjoint accumulators: eps_bar half (4), p_bar half (2)
-//   T   [4 r + x][lane]     forward current halves of range r = a M + b
-//   T   [2 r + x][lane]     range momentum halves
+// LDS per 64-lane block (32 events), all in the recursion type T:
+//   [6 g + x][lane]     eps half (4) and p half (2) of every gluon g
+//   [mask][pair]        1/P_S^2 (formed in FP64)
+//   [6 g + x][lane]     adjoint accumulators: eps_bar half (4), p_bar half (2)
+//   [4 r + x][lane]     forward current halves of range r = tri(a, b), a < b
+//   [2 r + x][lane]     range momentum halves of range r
+// Single-gluon ranges are read from the gluon slots.  FP64 momenta for the
+// range-momentum prefix sums are re-read from global memory (L1/L2 hits).
 template <int N>
 struct Lds {
   static constexpr int kLanes = 64, kPairs = 32;
   static constexpr int kTab = 1 << (N - 1);
-  static constexpr int kR = (N - 1) * (N - 1);
+  static constexpr int M = N - 1;
+  static constexpr int kR = M * (M - 1) / 2;  // ranges (a, b), a < b
   template <typename T>
   static constexpr size_t bytes() {
-    return sizeof(double) * ((size_t)kTab * kPairs + (size_t)2 * N * kLanes + (size_t)6 * N * kLanes) +
-           sizeof(T) * ((size_t)6 * N * kLanes + (size_t)kTab * kPairs + (size_t)6 * kR * kLanes);
+    return sizeof(T) * ((size_t)12 * N * kLanes + (size_t)kTab * kPairs + (size_t)6 * kR * kLanes);
   }
 };
+
+// index of range (a, b), a < b, among the ranges of positions 0..M-1
+template <int M>
+__device__ __forceinline__ constexpr int tri(int a, int b) {
+  return a * (2 * M - a - 1) / 2 + (b - a - 1);
+}
 
 template <int N, typename T>
 struct Ctx {
@@ -58,9 +64,7 @@ struct Ctx {
   T* pl;        // [2 r + x][lane]
   T* gsl;       // [6 g + x][lane]
   T* ip2;       // [mask][pair]
-  double* p2;   // [mask][pair]
-  double* p64;  // [2 g + c][lane]
-  double* acc;  // [6 g + x][lane]
+  T* acc;       // [6 g + x][lane]
   int lane, pair, h;
   T g0;
 };
@@ -239,20 +243,29 @@ struct St {
   int gl[M];
 };
 
+// current of range (a, b): a gluon slot for a == b, else the stored range
 template <int N, typename T>
-__device__ __forceinline__ H<T> ldJ(const Ctx<N, T>& c, int a, int b) {
-  const int r = a * (N - 1) + b;
+__device__ __forceinline__ H<T> ldJ(const Ctx<N, T>& c, const St<N, T>& s, int a, int b) {
   H<T> v;
-  v.re[0] = c.jl[(4 * r + 0) * 64 + c.lane];
-  v.re[1] = c.jl[(4 * r + 1) * 64 + c.lane];
-  v.im[0] = c.jl[(4 * r + 2) * 64 + c.lane];
-  v.im[1] = c.jl[(4 * r + 3) * 64 + c.lane];
+  if (a == b) {
+    const T* g = c.gsl + (size_t)6 * s.gl[a] * 64 + c.lane;
+    v.re[0] = g[0];
+    v.re[1] = g[64];
+    v.im[0] = g[128];
+    v.im[1] = g[192];
+  } else {
+    const int r = tri<N - 1>(a, b);
+    v.re[0] = c.jl[(4 * r + 0) * 64 + c.lane];
+    v.re[1] = c.jl[(4 * r + 1) * 64 + c.lane];
+    v.im[0] = c.jl[(4 * r + 2) * 64 + c.lane];
+    v.im[1] = c.jl[(4 * r + 3) * 64 + c.lane];
+  }
   return v;
 }
 
 template <int N, typename T>
 __device__ __forceinline__ void stJ(const Ctx<N, T>& c, int a, int b, const H<T>& v) {
-  const int r = a * (N - 1) + b;
+  const int r = tri<N - 1>(a, b);
   c.jl[(4 * r + 0) * 64 + c.lane] = v.re[0];
   c.jl[(4 * r + 1) * 64 + c.lane] = v.re[1];
   c.jl[(4 * r + 2) * 64 + c.lane] = v.im[0];
@@ -260,17 +273,23 @@ __device__ __forceinline__ void stJ(const Ctx<N, T>& c, int a, int b, const H<T>
 }
 
 template <int N, typename T>
-__device__ __forceinline__ HR<T> ldP(const Ctx<N, T>& c, int a, int b) {
-  const int r = a * (N - 1) + b;
+__device__ __forceinline__ HR<T> ldP(const Ctx<N, T>& c, const St<N, T>& s, int a, int b) {
   HR<T> v;
-  v.v[0] = c.pl[(2 * r + 0) * 64 + c.lane];
-  v.v[1] = c.pl[(2 * r + 1) * 64 + c.lane];
+  if (a == b) {
+    const T* g = c.gsl + (size_t)(6 * s.gl[a] + 4) * 64 + c.lane;
+    v.v[0] = g[0];
+    v.v[1] = g[64];
+  } else {
+    const int r = tri<N - 1>(a, b);
+    v.v[0] = c.pl[(2 * r + 0) * 64 + c.lane];
+    v.v[1] = c.pl[(2 * r + 1) * 64 + c.lane];
+  }
   return v;
 }
 
 template <int N, typename T>
 __device__ __forceinline__ void stP(const Ctx<N, T>& c, int a, int b, const HR<T>& v) {
-  const int r = a * (N - 1) + b;
+  const int r = tri<N - 1>(a, b);
   c.pl[(2 * r + 0) * 64 + c.lane] = v.v[0];
   c.pl[(2 * r + 1) * 64 + c.lane] = v.v[1];
 }
@@ -299,11 +318,9 @@ __global__ void __launch_bounds__(64) cobg_adj_kernel(int64_t E, const double* _
   const int64_t e = (int64_t)blockIdx.x * L::kPairs + pair;
   if (e >= E) return;
   Ctx<N, T> c;
-  c.p2 = reinterpret_cast<double*>(bg_adj_lds);
-  c.p64 = c.p2 + (size_t)L::kTab * L::kPairs;
-  c.acc = c.p64 + (size_t)2 * N * L::kLanes;
-  c.gsl = reinterpret_cast<T*>(c.acc + (size_t)6 * N * L::kLanes);
-  c.ip2 = c.gsl + (size_t)6 * N * L::kLanes;
+  c.gsl = reinterpret_cast<T*>(bg_adj_lds);
+  c.acc = c.gsl + (size_t)6 * N * L::kLanes;
+  c.ip2 = c.acc + (size_t)6 * N * L::kLanes;
   c.jl = c.ip2 + (size_t)L::kTab * L::kPairs;
   c.pl = c.jl + (size_t)4 * L::kR * L::kLanes;
   c.lane = lane;
@@ -333,10 +350,8 @@ __global__ void __launch_bounds__(64) cobg_adj_kernel(int64_t E, const double* _
     }
 #pragma unroll
     for (int x = 0; x < 6; ++x) c.gsl[(6 * i + x) * L::kLanes + lane] = (T)v[x];
-    c.p64[(2 * i + 0) * L::kLanes + lane] = v[4];
-    c.p64[(2 * i + 1) * L::kLanes + lane] = v[5];
 #pragma unroll
-    for (int x = 0; x < 6; ++x) c.acc[(6 * i + x) * L::kLanes + lane] = 0.0;
+    for (int x = 0; x < 6; ++x) c.acc[(6 * i + x) * L::kLanes + lane] = T(0);
   }
   for (int mask = h; mask < L::kTab; mask += 2) {
     double q[4] = {0.0, 0.0, 0.0, 0.0};
@@ -348,7 +363,6 @@ __global__ void __launch_bounds__(64) cobg_adj_kernel(int64_t E, const double* _
       }
     const double p2 = q[0] * q[0] - q[1] * q[1] - q[2] * q[2] - q[3] * q[3];
     c.ip2[mask * L::kPairs + pair] = (T)(1.0 / p2);
-    c.p2[mask * L::kPairs + pair] = p2;
   }
   __syncthreads();
 
@@ -373,24 +387,15 @@ __global__ void __launch_bounds__(64) cobg_adj_kernel(int64_t E, const double* _
     s.gl[0] = 0;
 #pragma unroll
     for (int k = 1; k < M; ++k) s.gl[k] = perms[sig * (N - 2) + (k - 1)];
-    // positions: external currents and range momenta (FP64 prefix differences)
+    // range momenta: FP64 prefix sums of the positions' momenta (re-read
+    // from global memory), differences rounded once to T
     HR<double> P0[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) {
       const int g = s.gl[k];
-      H<T> jk;
-      jk.re[0] = c.gsl[(6 * g + 0) * L::kLanes + lane];
-      jk.re[1] = c.gsl[(6 * g + 1) * L::kLanes + lane];
-      jk.im[0] = c.gsl[(6 * g + 2) * L::kLanes + lane];
-      jk.im[1] = c.gsl[(6 * g + 3) * L::kLanes + lane];
-      stJ(c, k, k, jk);
-      HR<T> pk;
-      pk.v[0] = c.gsl[(6 * g + 4) * L::kLanes + lane];
-      pk.v[1] = c.gsl[(6 * g + 5) * L::kLanes + lane];
-      stP(c, k, k, pk);
 #pragma unroll
       for (int m = 0; m < 2; ++m) {
-        const double pg = c.p64[(2 * g + m) * L::kLanes + lane];
+        const double pg = mom[((int64_t)g * 4 + 2 * h + m) * E + e];
         P0[k].v[m] = k == 0 ? pg : P0[k - 1].v[m] + pg;
       }
       s.pb[k].v[0] = 0.0;
@@ -400,6 +405,7 @@ __global__ void __launch_bounds__(64) cobg_adj_kernel(int64_t E, const double* _
     for (int a = 0; a < M; ++a)
 #pragma unroll
       for (int b = a + 1; b < M; ++b) {
+        if (a == 0 && b == M - 1) continue;  // the top range's momentum is not needed
         HR<T> pr;
 #pragma unroll
         for (int m = 0; m < 2; ++m)
@@ -417,12 +423,12 @@ __global__ void __launch_bounds__(64) cobg_adj_kernel(int64_t E, const double* _
         zero(acc);
 #pragma unroll
         for (int k = a; k < b; ++k)
-          v3(acc, ldP(c, a, k), ldP(c, k + 1, b), ldJ(c, a, k), ldJ(c, k + 1, b), c.g0);
+          v3(acc, ldP(c, s, a, k), ldP(c, s, k + 1, b), ldJ(c, s, a, k), ldJ(c, s, k + 1, b), c.g0);
 #pragma unroll
         for (int j = a; j < b; ++j)
 #pragma unroll
           for (int k = j + 1; k < b; ++k)
-            v4(acc, ldJ(c, a, j), ldJ(c, j + 1, k), ldJ(c, k + 1, b), c.g0);
+            v4(acc, ldJ(c, s, a, j), ldJ(c, s, j + 1, k), ldJ(c, s, k + 1, b), c.g0);
         if (len == M) {
           top = acc;
         } else {
@@ -470,14 +476,14 @@ __global__ void __launch_bounds__(64) cobg_adj_kernel(int64_t E, const double* _
             accb.re[m] = s.Jb[a][b].re[m] * ip;
             accb.im[m] = s.Jb[a][b].im[m] * ip;
           }
-          // ip2 = 1/(P.P): ipb = Re sum Jb.acc = Re sum Jb.J * P^2; Pbar += ipb (-2 g P) ip^2
-          const Cx<T> jj = psum(s.Jb[a][b], ldJ(c, a, b));
-          const HR<T> pab = ldP(c, a, b);
-          const double ipb = (double)jj.re * c.p2[mk * L::kPairs + pair];
-          const double ipd = 1.0 / c.p2[mk * L::kPairs + pair];
+          // J = acc ip, ip = 1/(P.P): ip_bar = Re sum Jb acc = Re(sum Jb J) P^2 and
+          // Pbar_m += ip_bar d ip / dP_m = Re(sum Jb J) (-2 g_m P_m) ip
+          const Cx<T> jj = psum(s.Jb[a][b], ldJ(c, s, a, b));
+          const HR<T> pab = ldP(c, s, a, b);
 #pragma unroll
           for (int m = 0; m < 2; ++m) {
-            const double v = ipb * (-2.0 * (double)gm(c.g0, m) * (double)pab.v[m]) * ipd * ipd;
+            const double v =
+                (double)jj.re * (-2.0 * (double)gm(c.g0, m) * (double)pab.v[m]) * (double)ip;
 #pragma unroll
             for (int i = a; i <= b; ++i) s.pb[i].v[m] += v;
           }
@@ -485,7 +491,7 @@ __global__ void __launch_bounds__(64) cobg_adj_kernel(int64_t E, const double* _
 #pragma unroll
         for (int k = a; k < b; ++k) {
           HR<double> PLb{{0.0, 0.0}}, PRb{{0.0, 0.0}};
-          v3_adj(accb, ldP(c, a, k), ldP(c, k + 1, b), ldJ(c, a, k), ldJ(c, k + 1, b), s.Jb[a][k],
+          v3_adj(accb, ldP(c, s, a, k), ldP(c, s, k + 1, b), ldJ(c, s, a, k), ldJ(c, s, k + 1, b), s.Jb[a][k],
                  s.Jb[k + 1][b], PLb, PRb, c.g0);
 #pragma unroll
           for (int m = 0; m < 2; ++m) {
@@ -499,36 +505,35 @@ __global__ void __launch_bounds__(64) cobg_adj_kernel(int64_t E, const double* _
         for (int j = a; j < b; ++j)
 #pragma unroll
           for (int k = j + 1; k < b; ++k)
-            v4_adj(accb, ldJ(c, a, j), ldJ(c, j + 1, k), ldJ(c, k + 1, b), s.Jb[a][j],
+            v4_adj(accb, ldJ(c, s, a, j), ldJ(c, s, j + 1, k), ldJ(c, s, k + 1, b), s.Jb[a][j],
                    s.Jb[j + 1][k], s.Jb[k + 1][b], c.g0);
       }
     }
-    // gluon accumulators (FP64)
+    // gluon accumulators (type T; the per-ordering momentum adjoints are
+    // summed in FP64 first)
 #pragma unroll
     for (int k = 0; k < M; ++k) {
       const int g = s.gl[k];
-      double* ac = c.acc + (size_t)6 * g * L::kLanes + lane;
-      ac[0 * L::kLanes] += (double)s.Jb[k][k].re[0];
-      ac[1 * L::kLanes] += (double)s.Jb[k][k].re[1];
-      ac[2 * L::kLanes] += (double)s.Jb[k][k].im[0];
-      ac[3 * L::kLanes] += (double)s.Jb[k][k].im[1];
-      ac[4 * L::kLanes] += s.pb[k].v[0];
-      ac[5 * L::kLanes] += s.pb[k].v[1];
+      T* ac = c.acc + (size_t)6 * g * L::kLanes + lane;
+      ac[0 * L::kLanes] += s.Jb[k][k].re[0];
+      ac[1 * L::kLanes] += s.Jb[k][k].re[1];
+      ac[2 * L::kLanes] += s.Jb[k][k].im[0];
+      ac[3 * L::kLanes] += s.Jb[k][k].im[1];
+      ac[4 * L::kLanes] += (T)s.pb[k].v[0];
+      ac[5 * L::kLanes] += (T)s.pb[k].v[1];
     }
-  }
-  {
-    double* ac = c.acc + (size_t)6 * (N - 1) * L::kLanes + lane;
-    ac[0 * L::kLanes] += epsNb.re[0];
-    ac[1 * L::kLanes] += epsNb.re[1];
-    ac[2 * L::kLanes] += epsNb.im[0];
-    ac[3 * L::kLanes] += epsNb.im[1];
   }
   // pull the external-current adjoints back to the momenta
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    const double* ac = c.acc + (size_t)6 * i * L::kLanes + lane;
-    const double ebr0 = ac[0], ebr1 = ac[L::kLanes], ebi0 = ac[2 * L::kLanes],
-                 ebi1 = ac[3 * L::kLanes];
+    const T* ac = c.acc + (size_t)6 * i * L::kLanes + lane;
+    double ebr0 = ac[0], ebr1 = ac[L::kLanes], ebi0 = ac[2 * L::kLanes], ebi1 = ac[3 * L::kLanes];
+    if (i == N - 1) {
+      ebr0 += epsNb.re[0];
+      ebr1 += epsNb.re[1];
+      ebi0 += epsNb.im[0];
+      ebi1 += epsNb.im[1];
+    }
     double dre[4][4], dim[4][4];
     polarization_jacobian(p[i], hv[i], dre, dim);
     // this lane's eps_bar as a full four-vector with zeros in the partner's slots
@@ -548,7 +553,7 @@ __global__ void __launch_bounds__(64) cobg_adj_kernel(int64_t E, const double* _
       for (int mu = 0; mu < 4; ++mu) t += ebr[mu] * dre[nu][mu] - ebi[mu] * dim[nu][mu];
       part[nu] = pair_sum(t);
     }
-    const double pb0 = ac[4 * L::kLanes], pb1 = ac[5 * L::kLanes];
+    const double pb0 = (double)ac[4 * L::kLanes], pb1 = (double)ac[5 * L::kLanes];
     if (hi) {
       grad[((int64_t)i * 4 + 2) * E + e] = pb0 + part[2];
       grad[((int64_t)i * 4 + 3) * E + e] = pb1 + part[3];

@@ -62,8 +62,12 @@ def _same(segs, got, ref, precision, label=""):
             continue
         keep = nonvanishing(s["hel"].cpu().numpy())
         if s["n"] >= 8:
-            assert np.array_equal(g == 0.0, r == 0.0), f"{label} n={s['n']}"
-            keep &= r != 0.0
+            # zeros of invalid colour flows coincide; flows whose amplitude
+            # cancels to rounding may give an exact 0 on one side only
+            typical = np.median(np.abs(r[r != 0.0])) if (r != 0.0).any() else 0.0
+            noise = (np.abs(r) < 1e-8 * typical) & (np.abs(g) < 1e-8 * typical)
+            assert np.array_equal((g == 0.0) | noise, (r == 0.0) | noise), f"{label} n={s['n']}"
+            keep &= np.abs(r) >= 1e-8 * typical
         rel = np.abs(g - r)[keep] / np.abs(r[keep])
         _say(f"  {label} n={s['n']}: events differing {(g != r).sum()} of {g.size}, "
              f"rel diff median {np.median(rel):.1e} max {rel.max():.1e}")

@@ -101,18 +101,23 @@ def test_full_size_gg_6g_sampled(api):
     dm, dh, dc = _dev(mom), _dev(hel), _dev(col)
     g64 = api.me2(dm, dh, dc, mode="cdbg", precision="fp64").cpu().numpy()
     g32 = api.me2(dm, dh, dc, mode="cdbg", precision="fp32").cpu().numpy()
-    nonzero = g64 != 0.0
-    frac = nonzero.mean()
+    frac = (g64 != 0.0).mean()
     _say(f"  non-zero fraction {frac:.4f}")
     assert 0.03 < frac < 0.06
-    assert np.array_equal(nonzero, g32 != 0.0)
+    # zero patterns of the two precisions agree, except flows whose amplitude
+    # cancels to rounding (one side may return an exact 0, the other noise)
+    typical = np.median(np.abs(g64[g64 != 0.0]))
+    noise = (np.abs(g64) < 1e-8 * typical) & (np.abs(g32) < 1e-8 * typical)
+    assert np.array_equal((g64 == 0.0) | noise, (g32 == 0.0) | noise)
+    # on a sample, against the oracle's classification: no closed colour
+    # circuit -> exactly 0 in both precisions; closed circuits non-zero
     rng = np.random.default_rng(9)
+    smp = np.sort(rng.choice(E, 20000, replace=False))
+    valid = ocdbg.is_valid_flow(col[:, :, smp])
+    assert np.all(g64[smp][~valid] == 0.0) and np.all(g32[smp][~valid] == 0.0)
+    assert (g64[smp][valid] != 0.0).mean() > 0.99
+    nonzero = g64 != 0.0
     idx = np.sort(rng.choice(np.nonzero(nonzero)[0], 10, replace=False))
-    sub = ocdbg.is_valid_flow(col[:, :, idx])
-    assert sub.all()
     ref = np.abs(ocdbg.flow_amplitude(mom[:, :, idx], hel[:, idx], col[:, :, idx])) ** 2
     _check(g64[idx], ref, hel[:, idx], "fp64", "full")
     _check(g32[idx], ref, hel[:, idx], "fp32", "full")
-    # invalid flows on a sample: exact zeros
-    zidx = np.sort(rng.choice(np.nonzero(~nonzero)[0], 200, replace=False))
-    assert not ocdbg.is_valid_flow(col[:, :, zidx]).any()
