@@ -160,21 +160,25 @@ int bg_me2_batch(bg_context* ctx, const bg_request* segs, int n_segs, void* stre
 
 /* Tile and grid shape of the batch kernel, per precision. */
 typedef struct bg_batch_config {
-    int blocks_per_cu;      /* persistent one-wave blocks per compute unit; 0 = as many
+    int blocks_per_cu;      /* persistent 256-lane blocks per compute unit; 0 = as many
                                as registers and LDS allow */
-    int cobg_tile_events;   /* events per colour-ordered tile, multiple of 32, <= 4096 */
-    int cdbg_tile_events;   /* events per colour-dressed tile, multiple of 64, <= 4096 */
-    int reserved;           /* must be 0 */
+    int cobg_tile_events;   /* events per colour-ordered tile, multiple of 128, <= 8192 */
+    int cdbg_tile_events;   /* events per colour-dressed tile, multiple of 256, <= 8192 */
+    int waves_per_simd;     /* register budget of the kernel: 1 = all registers the
+                               largest branch wants (one block per CU), 2 = at most 256
+                               per lane (two blocks per CU, some spilling at n = 7) */
 } bg_batch_config;
 
-/* Current batch config of `precision` (defaults: 0, 64, 256) into *out (host). */
+/* Current batch config of `precision` (defaults: 0, 128, 256, 2) into *out (host). */
 int bg_batch_config_get(bg_context* ctx, int precision, bg_batch_config* out);
 /* Set it; BG_EINVAL for values outside the ranges above. */
 int bg_batch_config_set(bg_context* ctx, int precision, const bg_batch_config* cfg);
 
 /* Autotuner: times bg_me2_batch on the given segments (their outputs are
- * written) for candidate configs -- blocks per CU, then colour-ordered tile,
- * then colour-dressed tile, each stage keeping the best -- with HIP events on
+ * written) for candidate configs -- register budget {2, 1} x blocks per CU
+ * {max, 1}, then
+ * colour-ordered tile {128, 256, 512, 1024}, then colour-dressed tile
+ * {256, 512, 1024}, each stage keeping the best -- with HIP events on
  * `stream`, and installs the fastest config for the segments' precision.
  * Synchronous; writes the chosen config and its time in milliseconds to
  * *best and *best_ms when non-NULL.  Must not be called during graph capture. */

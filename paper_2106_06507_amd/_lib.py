@@ -42,7 +42,7 @@ class bg_batch_config(ctypes.Structure):
         ("blocks_per_cu", ctypes.c_int),
         ("cobg_tile_events", ctypes.c_int),
         ("cdbg_tile_events", ctypes.c_int),
-        ("reserved", ctypes.c_int),
+        ("waves_per_simd", ctypes.c_int),
     ]
 
 

@@ -48,53 +48,89 @@ __global__ void zero_counter_kernel(unsigned* c) {
   if (threadIdx.x == 0) c[0] = 0u;
 }
 
+// Batch blocks: four waves.  A colour-ordered tile is split into 32-event
+// sub-tiles, wave w taking sub-tiles w, w + 4, ... with its own LDS region and
+// scratch slice; every wave runs the same number of rounds (a wave without a
+// sub-tile evaluates a stand-in event and stores nothing), because the tile
+// routine synchronises the block.  A colour-dressed tile is evaluated by all
+// 256 lanes, one valid event at a time.  LDS: a 64-byte header (validity
+// masks, tile broadcast) followed by the tile region.
+constexpr int kBatchWaves = 4;
+constexpr int kBatchLanes = 64 * kBatchWaves;
+constexpr size_t kBatchHeader = 64;
+
+// n >= 6 re-read FP64 momenta from global memory so that four waves of
+// colour-ordered tiles fit beside a colour-dressed n = 9 event's LDS.
+template <int N>
+struct BatchP64G {
+  static constexpr bool value = N >= 6;
+};
+
 template <int N, typename T>
 __device__ __forceinline__ void run_cobg(unsigned char* lds, const BatchSeg& s, double* blk,
                                          int64_t first, int count) {
-  for (int off = 0; off < count; off += kTileEvents) {
-    const int c = count - off < kTileEvents ? count - off : kTileEvents;
-    cobg_tile<N, T, false>(lds, s.E, s.mom, s.hel, s.Cl, blk, s.me2, first + off, c);
+  constexpr bool G = BatchP64G<N>::value;
+  const int w = threadIdx.x >> 6;
+  unsigned char* mine = lds + (size_t)w * Cobg<N>::template lds_bytes<T, G>();
+  double* myblk = blk + (size_t)w * Cobg<N>::kScratch;
+  const int nsub = (count + kTileEvents - 1) / kTileEvents;
+  for (int i = 0; i < nsub; i += kBatchWaves) {
+    const int j = i + w;
+    const int off = j * kTileEvents;
+    const int c = j < nsub ? (count - off < kTileEvents ? count - off : kTileEvents) : 0;
+    cobg_tile<N, T, false, G>(mine, s.E, s.mom, s.hel, s.Cl, myblk, s.me2,
+                              first + (j < nsub ? off : 0), c);
   }
 }
 
 template <int N, typename T>
-__device__ __forceinline__ void run_cdbg(unsigned char* lds, const BatchSeg& s, int64_t first,
-                                         int count) {
-  for (int off = 0; off < count; off += 64) {
-    const int c = count - off < 64 ? count - off : 64;
-    cdbg_chunk<N, T>(lds, s.E, s.mom, s.hel, s.col, s.me2, first + off, c);
+__device__ __forceinline__ void run_cdbg(unsigned char* lds, unsigned long long* vmask,
+                                         const BatchSeg& s, int64_t first, int count) {
+  for (int off = 0; off < count; off += kBatchLanes) {
+    const int c = count - off < kBatchLanes ? count - off : kBatchLanes;
+    cdbg_chunk<N, T, kBatchLanes>(lds, vmask, s.E, s.mom, s.hel, s.col, s.me2, first + off, c);
   }
 }
 
-// Persistent: each one-wave block pops tile indices from an atomic counter
-// until the queue is empty (every wave reaches the exit test).  Tiles are
-// ordered by decreasing estimated cost on the host.
-template <typename T>
-__global__ void __launch_bounds__(64) batch_kernel(const BatchSegTable segs,
-                                                  const BatchTile* __restrict__ tiles,
-                                                  unsigned n_tiles, unsigned* __restrict__ counter,
-                                                  double* __restrict__ scratch,
-                                                  int64_t scratch_stride) {
+// Persistent: each block pops tile indices from an atomic counter until the
+// queue is empty (every block reaches the exit test).  Tiles are ordered by
+// decreasing estimated cost on the host.
+// WAVES: minimum waves per SIMD the register allocation must allow.  1: the
+// largest branch (n = 7 colour-ordered) keeps all its registers and one
+// block fits on a CU; 2: at most 256 registers per lane, two blocks per CU
+// (the colour-dressed branches need ~130 and gain from the second block, the
+// n = 7 branch spills a little).  The autotuner picks one.
+template <typename T, int WAVES>
+__global__ void __launch_bounds__(kBatchLanes, WAVES) batch_kernel(const BatchSegTable segs,
+                                                           const BatchTile* __restrict__ tiles,
+                                                           unsigned n_tiles,
+                                                           unsigned* __restrict__ counter,
+                                                           double* __restrict__ scratch,
+                                                           int64_t scratch_stride) {
   extern __shared__ __align__(16) unsigned char bg_batch_lds[];
+  unsigned long long* vmask = reinterpret_cast<unsigned long long*>(bg_batch_lds);
+  unsigned* bcast = reinterpret_cast<unsigned*>(bg_batch_lds + 32);
+  unsigned char* lds = bg_batch_lds + kBatchHeader;
   double* blk = scratch + (size_t)blockIdx.x * (size_t)scratch_stride;
   for (;;) {
-    unsigned t = 0;
-    if (threadIdx.x == 0) t = atomicAdd(counter, 1u);
-    t = (unsigned)__builtin_amdgcn_readfirstlane((int)__shfl(t, 0));
+    if (threadIdx.x == 0) bcast[0] = atomicAdd(counter, 1u);
+    __syncthreads();
+    const unsigned t = (unsigned)__builtin_amdgcn_readfirstlane((int)bcast[0]);
+    __syncthreads();  // every lane has the index before the next pop
     if (t >= n_tiles) break;
     const BatchTile tile = tiles[t];
     const BatchSeg s = segs.s[tile.seg];
     switch (s.kind) {
-      case kBatchCobg + 4: run_cobg<4, T>(bg_batch_lds, s, blk, tile.first, tile.count); break;
-      case kBatchCobg + 5: run_cobg<5, T>(bg_batch_lds, s, blk, tile.first, tile.count); break;
-      case kBatchCobg + 6: run_cobg<6, T>(bg_batch_lds, s, blk, tile.first, tile.count); break;
-      case kBatchCobg + 7: run_cobg<7, T>(bg_batch_lds, s, blk, tile.first, tile.count); break;
-      case kBatchCdbg + 4: run_cdbg<4, T>(bg_batch_lds, s, tile.first, tile.count); break;
-      case kBatchCdbg + 5: run_cdbg<5, T>(bg_batch_lds, s, tile.first, tile.count); break;
-      case kBatchCdbg + 6: run_cdbg<6, T>(bg_batch_lds, s, tile.first, tile.count); break;
-      case kBatchCdbg + 7: run_cdbg<7, T>(bg_batch_lds, s, tile.first, tile.count); break;
-      case kBatchCdbg + 8: run_cdbg<8, T>(bg_batch_lds, s, tile.first, tile.count); break;
-      case kBatchCdbg + 9: run_cdbg<9, T>(bg_batch_lds, s, tile.first, tile.count); break;
+      case kBatchCobg + 4: run_cobg<4, T>(lds, s, blk, tile.first, tile.count); break;
+      case kBatchCobg + 5: run_cobg<5, T>(lds, s, blk, tile.first, tile.count); break;
+      case kBatchCobg + 6: run_cobg<6, T>(lds, s, blk, tile.first, tile.count); break;
+      case kBatchCobg + 7: run_cobg<7, T>(lds, s, blk, tile.first, tile.count); break;
+      case kBatchCdbg + 4: run_cdbg<4, T>(lds, vmask, s, tile.first, tile.count); break;
+      case kBatchCdbg + 5: run_cdbg<5, T>(lds, vmask, s, tile.first, tile.count); break;
+      case kBatchCdbg + 6: run_cdbg<6, T>(lds, vmask, s, tile.first, tile.count); break;
+      case kBatchCdbg + 7: run_cdbg<7, T>(lds, vmask, s, tile.first, tile.count); break;
+      case kBatchCdbg + 8: run_cdbg<8, T>(lds, vmask, s, tile.first, tile.count); break;
+      case kBatchCdbg + 9: run_cdbg<9, T>(lds, vmask, s, tile.first, tile.count); break;
       default: break;
     }
     __syncthreads();  // the next tile rewrites LDS
@@ -186,25 +222,70 @@ int cobg_fused_me2(int n, bool fp32, int64_t E, const double* mom, const int8_t*
   }
 }
 
-int batch_blocks_per_cu(bool fp32, size_t lds) {
+// LDS of the batch kernel for one segment kind (header included).
+size_t batch_lds_bytes(int kind, int n, bool fp32) {
+  if (kind == kBatchCobg) {
+    size_t per_wave = 0;
+    switch (n) {
+#define BG_CASE(NN)                                                                          \
+  case NN:                                                                                   \
+    per_wave = fp32 ? fusedk::Cobg<NN>::lds_bytes<float, fusedk::BatchP64G<NN>::value>()     \
+                    : fusedk::Cobg<NN>::lds_bytes<double, fusedk::BatchP64G<NN>::value>();   \
+    break;
+      BG_CASE(4)
+      BG_CASE(5)
+      BG_CASE(6)
+      BG_CASE(7)
+#undef BG_CASE
+      default:
+        return 0;
+    }
+    return fusedk::kBatchHeader + fusedk::kBatchWaves * per_wave;
+  }
+  const size_t c = cdbg_lds_bytes(n, fp32);
+  return c ? fusedk::kBatchHeader + c : 0;
+}
+
+int batch_scratch_doubles(int n) { return fusedk::kBatchWaves * cobg_fused_scratch_doubles(n); }
+
+int batch_blocks_per_cu(bool fp32, int waves, size_t lds) {
   int nb = 0;
-  hipError_t e = fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                            &nb, fusedk::batch_kernel<float>, 64, lds)
-                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                            &nb, fusedk::batch_kernel<double>, 64, lds);
+  const int L = fusedk::kBatchLanes;
+  hipError_t e;
+  if (fp32)
+    e = waves == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fusedk::batch_kernel<float, 2>, L, lds)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fusedk::batch_kernel<float, 1>, L, lds);
+  else
+    e = waves == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fusedk::batch_kernel<double, 2>, L, lds)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fusedk::batch_kernel<double, 1>, L, lds);
   return e == hipSuccess ? nb : -1;
 }
 
-int batch_launch(bool fp32, const BatchSegTable& segs, const BatchTile* tiles, unsigned n_tiles,
-                 unsigned* counter, double* scratch, int64_t scratch_stride, int grid, size_t lds,
-                 hipStream_t stream) {
+namespace fusedk {
+template <typename T, int WAVES>
+void launch_batch(const BatchSegTable& segs, const BatchTile* tiles, unsigned n_tiles,
+                  unsigned* counter, double* scratch, int64_t scratch_stride, int grid, size_t lds,
+                  hipStream_t stream) {
+  hipLaunchKernelGGL((batch_kernel<T, WAVES>), dim3(grid), dim3(kBatchLanes), lds, stream, segs,
+                     tiles, n_tiles, counter, scratch, scratch_stride);
+}
+}  // namespace fusedk
+
+int batch_launch(bool fp32, int waves, const BatchSegTable& segs, const BatchTile* tiles,
+                 unsigned n_tiles, unsigned* counter, double* scratch, int64_t scratch_stride,
+                 int grid, size_t lds, hipStream_t stream) {
   hipLaunchKernelGGL(fusedk::zero_counter_kernel, dim3(1), dim3(64), 0, stream, counter);
-  if (fp32)
-    hipLaunchKernelGGL(fusedk::batch_kernel<float>, dim3(grid), dim3(64), lds, stream, segs, tiles,
-                       n_tiles, counter, scratch, scratch_stride);
-  else
-    hipLaunchKernelGGL(fusedk::batch_kernel<double>, dim3(grid), dim3(64), lds, stream, segs,
-                       tiles, n_tiles, counter, scratch, scratch_stride);
+  if (fp32) {
+    if (waves == 2)
+      fusedk::launch_batch<float, 2>(segs, tiles, n_tiles, counter, scratch, scratch_stride, grid, lds, stream);
+    else
+      fusedk::launch_batch<float, 1>(segs, tiles, n_tiles, counter, scratch, scratch_stride, grid, lds, stream);
+  } else {
+    if (waves == 2)
+      fusedk::launch_batch<double, 2>(segs, tiles, n_tiles, counter, scratch, scratch_stride, grid, lds, stream);
+    else
+      fusedk::launch_batch<double, 1>(segs, tiles, n_tiles, counter, scratch, scratch_stride, grid, lds, stream);
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

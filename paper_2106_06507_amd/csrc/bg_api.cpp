@@ -49,13 +49,15 @@ struct bg_context {
   size_t scratch_bytes = 0;
   std::vector<void*> retired;                // outgrown scratch buffers, freed on destroy
   unsigned* counter = nullptr;               // tile-queue heads: [0] batch, [1] fused n = 7
-  bg_batch_config bcfg[2] = {{0, 64, 256, 0}, {0, 64, 256, 0}};
+  bg_batch_config bcfg[2] = {{0, 128, 256, 2}, {0, 128, 256, 2}};
   std::vector<BatchPlan> plans;
   uint64_t clock = 0;
   int occ_fused[2][2] = {};                  // blocks per CU of the persistent fused kernel
                                              // [fp32][helicity sum], 0 = unknown
-  int occ_batch[2] = {};                     // of the batch kernel at its last LDS size
-  size_t occ_batch_lds[2] = {};
+  int occ_batch[2][2] = {};                  // of the batch kernel [fp32][variant] at its
+                                             // last LDS size
+  int occ_cdbg[BG_N_MAX + 1][2] = {};        // of the colour-dressed event kernel
+  size_t occ_batch_lds[2][2] = {};
 };
 
 namespace {
@@ -392,9 +394,9 @@ static int me2_cdbg(bg_context* ctx, const bg_request* r, hipStream_t stream) {
     if (st) return st;
     ctx->cws_bytes = need;
   }
-  size_t per_cu = ctx->lds_per_cu ? ctx->lds_per_cu / lds : 1;
-  if (per_cu < 1) per_cu = 1;
-  if (per_cu > 8) per_cu = 8;
+  int& per_cu = ctx->occ_cdbg[n][fp32 ? 1 : 0];
+  if (per_cu <= 0) per_cu = bg::cdbg_blocks_per_cu(n, fp32);
+  if (per_cu <= 0) return BG_EUNSUPPORTED;
   int64_t grid = (int64_t)ctx->num_cus * (int64_t)per_cu;
   if (grid > r->n_events) grid = r->n_events;
   if (grid < 1) grid = 1;
@@ -511,8 +513,8 @@ int validate_batch(bg_context* ctx, const bg_request* segs, int n_segs) {
     const int mode = resolved_mode(r);
     if (mode == BG_MODE_COBG && r->n > 7) return BG_EUNSUPPORTED;
     const bool fp32 = r->precision == BG_PREC_FP32_MIXED;
-    const size_t lds =
-        mode == BG_MODE_COBG ? bg::cobg_lds_bytes(r->n, fp32) : bg::cdbg_lds_bytes(r->n, fp32);
+    const size_t lds = bg::batch_lds_bytes(mode == BG_MODE_COBG ? bg::kBatchCobg : bg::kBatchCdbg,
+                                           r->n, fp32);
     if (lds == 0 || lds > ctx->lds_per_block) return BG_EUNSUPPORTED;
   }
   return BG_OK;
@@ -555,7 +557,15 @@ int batch_plan(bg_context* ctx, const bg_request* segs, int n_segs, const bg_bat
     const bg_request* r = &segs[i];
     if (r->n_events == 0) continue;
     const bool cd = resolved_mode(r) == BG_MODE_CDBG;
-    const int64_t step = cd ? cfg.cdbg_tile_events : cfg.cobg_tile_events;
+    int64_t step = cd ? cfg.cdbg_tile_events : cfg.cobg_tile_events;
+    if (cd) {
+      // a colour-dressed tile costs about its number of valid events (~5 %)
+      // times one event on the whole block: small segments get small tiles
+      // (multiples of 16 raw events) so that ~4 tiles per block exist
+      const int64_t want = (int64_t)ctx->num_cus * 2 * 4;
+      const int64_t t = ((r->n_events + want - 1) / want + 15) / 16 * 16;
+      step = std::max<int64_t>(16, std::min<int64_t>(step, t));
+    }
     const double c = event_cost(r->n, cd, fp32);
     for (int64_t f = 0; f < r->n_events; f += step) {
       const int cnt = (int)std::min<int64_t>(step, r->n_events - f);
@@ -628,10 +638,10 @@ int batch_run(bg_context* ctx, const bg_request* segs, int n_segs, const bg_batc
         if (st) return st;
       }
       b.Cl = ctx->Cb_dev[r->n];
-      stride = std::max<int64_t>(stride, bg::cobg_fused_scratch_doubles(r->n));
-      lds = std::max(lds, bg::cobg_lds_bytes(r->n, fp32));
+      stride = std::max<int64_t>(stride, bg::batch_scratch_doubles(r->n));
+      lds = std::max(lds, bg::batch_lds_bytes(bg::kBatchCobg, r->n, fp32));
     } else {
-      lds = std::max(lds, bg::cdbg_lds_bytes(r->n, fp32));
+      lds = std::max(lds, bg::batch_lds_bytes(bg::kBatchCdbg, r->n, fp32));
     }
   }
   BatchPlan* pl = nullptr;
@@ -639,11 +649,14 @@ int batch_run(bg_context* ctx, const bg_request* segs, int n_segs, const bg_batc
   if (st) return st;
   if (pl->n_tiles == 0) return BG_OK;
   const int fi = fp32 ? 1 : 0;
-  if (ctx->occ_batch[fi] <= 0 || ctx->occ_batch_lds[fi] != lds) {
-    ctx->occ_batch[fi] = bg::batch_blocks_per_cu(fp32, lds);
-    ctx->occ_batch_lds[fi] = lds;
+  const int waves = cfg.waves_per_simd == 1 ? 1 : 2;
+  const int wi = waves - 1;
+  if (ctx->occ_batch[fi][wi] <= 0 || ctx->occ_batch_lds[fi][wi] != lds) {
+    if (capturing) return BG_EINVAL;
+    ctx->occ_batch[fi][wi] = bg::batch_blocks_per_cu(fp32, waves, lds);
+    ctx->occ_batch_lds[fi][wi] = lds;
   }
-  const int occ = ctx->occ_batch[fi];
+  const int occ = ctx->occ_batch[fi][wi];
   if (occ <= 0) return BG_EUNSUPPORTED;
   const int bpc = cfg.blocks_per_cu > 0 ? std::min(cfg.blocks_per_cu, occ) : occ;
   const int64_t grid = std::min<int64_t>((int64_t)ctx->num_cus * bpc, pl->n_tiles);
@@ -657,15 +670,15 @@ int batch_run(bg_context* ctx, const bg_request* segs, int n_segs, const bg_batc
     if (!st) st = ensure_counters(ctx);
     if (st) return st;
   }
-  return launch_status(bg::batch_launch(fp32, tab, pl->tiles, pl->n_tiles, ctx->counter,
+  return launch_status(bg::batch_launch(fp32, waves, tab, pl->tiles, pl->n_tiles, ctx->counter,
                                         ctx->scratch, stride, (int)grid, lds, stream));
 }
 
 bool valid_config(const bg_batch_config* c) {
-  return c && c->blocks_per_cu >= 0 && c->blocks_per_cu <= 64 && c->cobg_tile_events >= 32 &&
-         c->cobg_tile_events <= 4096 && c->cobg_tile_events % 32 == 0 &&
-         c->cdbg_tile_events >= 64 && c->cdbg_tile_events <= 4096 &&
-         c->cdbg_tile_events % 64 == 0 && c->reserved == 0;
+  return c && c->blocks_per_cu >= 0 && c->blocks_per_cu <= 64 && c->cobg_tile_events >= 128 &&
+         c->cobg_tile_events <= 8192 && c->cobg_tile_events % 128 == 0 &&
+         c->cdbg_tile_events >= 256 && c->cdbg_tile_events <= 8192 &&
+         c->cdbg_tile_events % 256 == 0 && (c->waves_per_simd == 1 || c->waves_per_simd == 2);
 }
 
 }  // namespace
@@ -709,7 +722,7 @@ int bg_me2_batch_tune(bg_context* ctx, const bg_request* segs, int n_segs, bg_ba
   hipEvent_t e0 = nullptr, e1 = nullptr;
   st = hip_status(hipEventCreate(&e0), "hipEventCreate");
   if (!st) st = hip_status(hipEventCreate(&e1), "hipEventCreate");
-  bg_batch_config cur = {0, 64, 256, 0};
+  bg_batch_config cur = {0, 128, 256, 2};
   double cur_ms = 1e300;
   auto time_cfg = [&](const bg_batch_config& c, double* ms) -> int {
     int r = batch_run(ctx, segs, n_segs, c, s);  // warm-up, builds the plan
@@ -732,8 +745,8 @@ int bg_me2_batch_tune(bg_context* ctx, const bg_request* segs, int n_segs, bg_ba
     double ms = 0.0;
     int r = time_cfg(c, &ms);
     if (r) return r;
-    BG_LOG("tune: blocks/CU %d cobg tile %d cdbg tile %d -> %.3f ms", c.blocks_per_cu,
-           c.cobg_tile_events, c.cdbg_tile_events, ms);
+    BG_LOG("tune: waves/SIMD %d blocks/CU %d cobg tile %d cdbg tile %d -> %.3f ms",
+           c.waves_per_simd, c.blocks_per_cu, c.cobg_tile_events, c.cdbg_tile_events, ms);
     if (ms < cur_ms) {
       cur_ms = ms;
       cur = c;
@@ -742,15 +755,19 @@ int bg_me2_batch_tune(bg_context* ctx, const bg_request* segs, int n_segs, bg_ba
   };
   if (!st) {
     const bg_batch_config base = cur;
-    for (int b : {0, 1, 2, 3, 4, 6, 8}) {
-      bg_batch_config c = base;
-      c.blocks_per_cu = b;
-      if ((st = try_cfg(c))) break;
+    for (int v : {2, 1}) {
+      for (int b : {0, 1}) {
+        bg_batch_config c = base;
+        c.waves_per_simd = v;
+        c.blocks_per_cu = b;
+        if ((st = try_cfg(c))) break;
+      }
+      if (st) break;
     }
   }
   if (!st) {
     const bg_batch_config base = cur;
-    for (int t : {32, 64, 128, 256}) {
+    for (int t : {128, 256, 512, 1024}) {
       bg_batch_config c = base;
       c.cobg_tile_events = t;
       if ((st = try_cfg(c))) break;
@@ -758,7 +775,7 @@ int bg_me2_batch_tune(bg_context* ctx, const bg_request* segs, int n_segs, bg_ba
   }
   if (!st) {
     const bg_batch_config base = cur;
-    for (int t : {64, 128, 256, 512}) {
+    for (int t : {256, 512, 1024}) {
       bg_batch_config c = base;
       c.cdbg_tile_events = t;
       if ((st = try_cfg(c))) break;

@@ -42,10 +42,11 @@ int contract_y(int K, int64_t E, const double* amp, const double* C, double* Y, 
 
 // Colour-dressed |A|^2 for one colour-flow assignment per event.  ws holds
 // 2 + E unsigned (counters, compacted list of valid events); grid is the
-// number of persistent one-wave blocks.
+// number of persistent blocks (256 lanes each, one event at a time).
 int cdbg_me2(int n, bool fp32, int64_t E, const double* mom, const int8_t* hel, const int8_t* col,
              unsigned* ws, double* me2, int grid, hipStream_t stream);
 size_t cdbg_lds_bytes(int n, bool fp32);
+int cdbg_blocks_per_cu(int n, bool fp32);
 
 // me2[e] (+)= sum_st C_st Re(A_s conj(A_t)); C is K x K row-major on device.
 int contract_valu(int K, int64_t E, const double* amp, const double* C, double* me2,
@@ -96,10 +97,16 @@ struct BatchSegTable {
   BatchSeg s[kBatchMaxSegs];
 };
 
-int batch_blocks_per_cu(bool fp32, size_t lds);
+// Batch blocks are 256 lanes.  LDS for a segment kind (kBatchCobg or
+// kBatchCdbg, without n) and per-block scratch doubles for colour-ordered n.
+size_t batch_lds_bytes(int kind, int n, bool fp32);
+int batch_scratch_doubles(int n);
+// waves: register budget variant, 1 (one wave per SIMD, no cap) or 2 (at
+// most 256 registers per lane).
+int batch_blocks_per_cu(bool fp32, int waves, size_t lds);
 // Enqueues the counter reset and the persistent kernel on stream.
-int batch_launch(bool fp32, const BatchSegTable& segs, const BatchTile* tiles, unsigned n_tiles,
-                 unsigned* counter, double* scratch, int64_t scratch_stride, int grid, size_t lds,
-                 hipStream_t stream);
+int batch_launch(bool fp32, int waves, const BatchSegTable& segs, const BatchTile* tiles,
+                 unsigned n_tiles, unsigned* counter, double* scratch, int64_t scratch_stride,
+                 int grid, size_t lds, hipStream_t stream);
 
 }  // namespace bg

@@ -32,13 +32,32 @@ __global__ void zero_u32_kernel(unsigned* p, int n) {
   if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
 }
 
+// Lanes per event of the standalone kernel (measured on MI355X for 2^20
+// sampled flows: n = 8 fastest with two waves per event, n = 9 with four).
+template <int N>
+struct EventLanes {
+  static constexpr int value = N <= 8 ? 128 : 256;
+};
+
 template <int N, typename T>
 int launch_events(int64_t E, const double* mom, const int8_t* hel, const int8_t* col,
                   const unsigned* list, const unsigned* counters, double* me2, int grid,
                   hipStream_t stream) {
-  hipLaunchKernelGGL((cdbg_event_kernel<N, T>), dim3(grid), dim3(64), (Lay<N, T>::bytes()), stream, E,
-                     mom, hel, col, list, counters, const_cast<unsigned*>(counters) + 1, me2);
+  constexpr int NL = EventLanes<N>::value;
+  hipLaunchKernelGGL((cdbg_event_kernel<N, T, NL>), dim3(grid), dim3(NL), (Lay<N, T>::bytes()),
+                     stream, E, mom, hel, col, list, counters, const_cast<unsigned*>(counters) + 1,
+                     me2);
   return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int N, typename T>
+int event_occupancy() {
+  constexpr int NL = EventLanes<N>::value;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cdbg_event_kernel<N, T, NL>, NL,
+                                                   Lay<N, T>::bytes()) != hipSuccess)
+    return -1;
+  return nb;
 }
 
 }  // namespace cdbgk
@@ -52,6 +71,18 @@ size_t cdbg_lds_bytes(int n, bool fp32) {
     case 8: return fp32 ? cdbgk::Lay<8, float>::bytes() : cdbgk::Lay<8, double>::bytes();
     case 9: return fp32 ? cdbgk::Lay<9, float>::bytes() : cdbgk::Lay<9, double>::bytes();
     default: return 0;
+  }
+}
+
+int cdbg_blocks_per_cu(int n, bool fp32) {
+  switch (n) {
+    case 4: return fp32 ? cdbgk::event_occupancy<4, float>() : cdbgk::event_occupancy<4, double>();
+    case 5: return fp32 ? cdbgk::event_occupancy<5, float>() : cdbgk::event_occupancy<5, double>();
+    case 6: return fp32 ? cdbgk::event_occupancy<6, float>() : cdbgk::event_occupancy<6, double>();
+    case 7: return fp32 ? cdbgk::event_occupancy<7, float>() : cdbgk::event_occupancy<7, double>();
+    case 8: return fp32 ? cdbgk::event_occupancy<8, float>() : cdbgk::event_occupancy<8, double>();
+    case 9: return fp32 ? cdbgk::event_occupancy<9, float>() : cdbgk::event_occupancy<9, double>();
+    default: return -2;
   }
 }
 

@@ -55,13 +55,16 @@ struct Lay {
   static constexpr int kP = NS * 4;          // momenta  [mask][mu]
   static constexpr int kI = NS;              // 1/P^2    [mask]
   static constexpr int kItems = NS * 3;      // target list of one size
+  static constexpr int kPm = 4 * N;          // FP64 momenta of the event [gluon][mu]
   static constexpr size_t bytes() {
-    return sizeof(T) * (size_t)(kJ + kT + kP + kI) + sizeof(int) * (size_t)(NS + kItems + 2 * N + 4);
+    return sizeof(double) * (size_t)kPm + sizeof(T) * (size_t)(kJ + kT + kP + kI) +
+           sizeof(int) * (size_t)(NS + kItems + 2 * N + 16);
   }
 };
 
 template <int N, typename T>
 struct Sm {
+  double* pm;
   T* J;
   T* Tt;
   T* P;
@@ -70,14 +73,15 @@ struct Sm {
   int* items;
   int* ci;     // colours i_k
   int* cj;     // colours j_k
-  int* misc;
+  int* misc;   // [3 w + t]: items of slot t found by wave w; [12]: broadcast
 };
 
 template <int N, typename T>
 __device__ __forceinline__ Sm<N, T> carve(unsigned char* raw) {
   using L = Lay<N, T>;
   Sm<N, T> s;
-  T* t = reinterpret_cast<T*>(raw);
+  s.pm = reinterpret_cast<double*>(raw);
+  T* t = reinterpret_cast<T*>(s.pm + L::kPm);
   s.J = t;
   s.Tt = s.J + L::kJ;
   s.P = s.Tt + L::kT;
@@ -317,8 +321,9 @@ __device__ __forceinline__ bool flow_valid(int n, int64_t E, const int8_t* __res
   return in_range && g.balanced() && g.connected();
 }
 
-// One valid event (colour flow closes into a circuit) on this 64-lane wave.
-template <int N, typename T>
+// One valid event (colour flow closes into a circuit) on the NL lanes of this
+// block (NL = 64: one wave; NL = 256: four waves sharing the event's LDS).
+template <int N, typename T, int NL = kWave>
 __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
                                                const double* __restrict__ mom,
                                                const int8_t* __restrict__ hel,
@@ -327,23 +332,27 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
   using L = Lay<N, T>;
   constexpr int M = N - 1;
   constexpr int NS = L::NS;
+  constexpr int NW = NL / kWave;
+  static_assert(NL % kWave == 0 && NW <= 4, "one to four waves per event");
   const int lane = threadIdx.x;
+  const int w = lane / kWave, lw = lane % kWave;
   // ---- event set-up -------------------------------------------------
-  for (int x = lane; x < L::kJ; x += kWave) sm.J[x] = T(0);
-  for (int x = lane; x < L::kT; x += kWave) sm.Tt[x] = T(0);
+  for (int x = lane; x < L::kJ; x += NL) sm.J[x] = T(0);
+  for (int x = lane; x < L::kT; x += NL) sm.Tt[x] = T(0);
   if (lane < N) {
     sm.ci[lane] = col[(int64_t)lane * E + e];
     sm.cj[lane] = col[((int64_t)N + lane) * E + e];
   }
+  if (lane < 4 * N) sm.pm[lane] = mom[(int64_t)lane * E + e];  // [k][mu] = row 4k + mu
   __syncthreads();
   // subset codes, momenta, 1/P^2 (FP64 sums)
-  for (int mask = lane + 1; mask < NS; mask += kWave) {
+  for (int mask = lane + 1; mask < NS; mask += NL) {
     double q[4] = {0.0, 0.0, 0.0, 0.0};
     ColourGraph g;
     for (int k = 0; k < M; ++k) {
       if (!(mask & (1 << k))) continue;
 #pragma unroll
-      for (int mu = 0; mu < 4; ++mu) q[mu] += mom[((int64_t)k * 4 + mu) * E + e];
+      for (int mu = 0; mu < 4; ++mu) q[mu] += sm.pm[k * 4 + mu];
       g.add(sm.cj[k], sm.ci[k]);
     }
     const int code = g.code();
@@ -357,7 +366,7 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
   if (lane < M) {
     double p[4], er[4], ei[4];
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) p[mu] = mom[((int64_t)lane * 4 + mu) * E + e];
+    for (int mu = 0; mu < 4; ++mu) p[mu] = sm.pm[lane * 4 + mu];
     polarization(p, (int)hel[(int64_t)lane * E + e], er, ei);
     const int ii = sm.ci[lane], jj = sm.cj[lane];
     const int slot = (ii == jj) ? jj : 0;
@@ -382,34 +391,57 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
       }
       nitems = 1;
     } else {
-      for (int base = 0; base < NS; base += kWave) {
+      // compaction of the (mask, slot) targets: slot-major, waves in order
+      for (int base = 0; base < NS; base += NL) {
         const int mask = base + lane;
         int code = 0;
         if (mask > 0 && mask < NS && __popc(mask) == size) code = sm.code[mask];
+        bool ok[3];
+        unsigned long long bal[3];
+#pragma unroll
         for (int t = 0; t < 3; ++t) {
-          bool ok = false;
-          if ((code & 3) == 1) ok = (t == 0);
-          else if ((code & 3) == 2) ok = ((code >> 6) >> t) & 1;
-          const unsigned long long bal = __ballot(ok);
-          const unsigned long long below = lane ? (bal & ((~0ull) >> (64 - lane))) : 0ull;
-          if (ok) sm.items[nitems + __popcll(below)] = mask * 4 + t;
-          nitems += __popcll(bal);
+          ok[t] = false;
+          if ((code & 3) == 1) ok[t] = (t == 0);
+          else if ((code & 3) == 2) ok[t] = ((code >> 6) >> t) & 1;
+          bal[t] = __ballot(ok[t]);
         }
+        if (lw == 0) {
+#pragma unroll
+          for (int t = 0; t < 3; ++t) sm.misc[3 * w + t] = __popcll(bal[t]);
+        }
+        __syncthreads();
+        const unsigned long long below = lw ? ((~0ull) >> (kWave - lw)) : 0ull;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          int before = 0, all = 0;
+#pragma unroll
+          for (int v = 0; v < NW; ++v) {
+            const int cnt = sm.misc[3 * v + t];
+            if (v < w) before += cnt;
+            all += cnt;
+          }
+          if (ok[t]) sm.items[nitems + before + __popcll(bal[t] & below)] = mask * 4 + t;
+          nitems += all;
+        }
+        __syncthreads();  // misc is rewritten by the next base
       }
     }
     __syncthreads();
-    // q adjacent lanes per target, each taking every q-th split directly
-    // (no lane walks the splits it does not evaluate)
-    const int q = (nitems >= kWave || nitems == 0) ? 1 : kWave / nitems;
-    const int per_round = kWave / q;
+    // q adjacent lanes of one wave per target, each taking every q-th split
+    // directly (no lane walks the splits it does not evaluate)
+    int q = nitems == 0 ? 1 : NL / nitems;
+    q = q < 1 ? 1 : (q > kWave ? kWave : q);
+    const int gpw = kWave / q;  // targets per wave and round
+    const int per_round = gpw * NW;
     const int nsplit = (1 << size) - 2;
     for (int r0 = 0; r0 < nitems; r0 += per_round) {
-      const int it = r0 + lane / q;
-      const int sub = lane % q;
+      const int grp = lw / q;
+      const int it = r0 + w * gpw + grp;
+      const int sub = lw % q;
       T gre[4] = {0, 0, 0, 0}, gim[4] = {0, 0, 0, 0};
       T tre[6] = {0, 0, 0, 0, 0, 0}, tim[6] = {0, 0, 0, 0, 0, 0};
       int S = 0, t = 0;
-      const bool active = lane < q * per_round && it < nitems;
+      const bool active = grp < gpw && it < nitems;
       if (active) {
         const int item = sm.items[it];
         S = item >> 2;
@@ -448,7 +480,7 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
         if (top) {
           double p[4], er[4], ei[4];
 #pragma unroll
-          for (int mu = 0; mu < 4; ++mu) p[mu] = mom[((int64_t)M * 4 + mu) * E + e];
+          for (int mu = 0; mu < 4; ++mu) p[mu] = sm.pm[M * 4 + mu];
           polarization(p, (int)hel[(int64_t)M * E + e], er, ei);
           double ar = 0.0, ai = 0.0;
 #pragma unroll
@@ -484,8 +516,10 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
   }
 }
 
-template <int N, typename T>
-__global__ void __launch_bounds__(64) cdbg_event_kernel(int64_t E, const double* __restrict__ mom,
+// Persistent blocks of NL lanes, one valid event at a time from the
+// compacted list.
+template <int N, typename T, int NL>
+__global__ void __launch_bounds__(NL) cdbg_event_kernel(int64_t E, const double* __restrict__ mom,
                                                        const int8_t* __restrict__ hel,
                                                        const int8_t* __restrict__ col,
                                                        const unsigned* __restrict__ list,
@@ -497,11 +531,12 @@ __global__ void __launch_bounds__(64) cdbg_event_kernel(int64_t E, const double*
   const int lane = threadIdx.x;
   const unsigned total = *count;
   for (;;) {
-    unsigned idx = 0;
-    if (lane == 0) idx = atomicAdd(work, 1u);
-    idx = __shfl(idx, 0);
+    if (lane == 0) sm.misc[12] = (int)atomicAdd(work, 1u);
+    __syncthreads();
+    const unsigned idx = (unsigned)sm.misc[12];
+    __syncthreads();  // every lane has read the index before the next pop
     if (idx >= total) break;
-    cdbg_one_event<N, T>(sm, E, mom, hel, col, (int64_t)list[idx], me2);
+    cdbg_one_event<N, T, NL>(sm, E, mom, hel, col, (int64_t)list[idx], me2);
   }
 }
 

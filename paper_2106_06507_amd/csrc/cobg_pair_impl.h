@@ -48,25 +48,30 @@ namespace pairk {
 //     at slots 6 (g-1) .. 6 (g-1) + 5;
 //   T region, [mask][pair]: 1/P_S^2 for subsets S of gluons 0..N-2;
 //   double region, [2 (g-1) + c][lane]: FP64 momentum halves of gluons 1..N-2.
+// P64G: the FP64 momentum halves are re-read from global memory (L1/L2
+// hits) instead of being kept in LDS, which saves 2 (N-2) x 64 doubles where
+// LDS is the occupancy limit.
 template <int N>
 struct Lds {
   static constexpr int kLanes = 64;
   static constexpr int kPairs = 32;
   static constexpr int kGluonSlots = 6 * (N - 2);
   static constexpr int kTabEntries = 1 << (N - 1);
-  template <typename T>
+  template <typename T, bool P64G = false>
   static constexpr size_t bytes() {
     return sizeof(T) * ((size_t)kGluonSlots * kLanes + (size_t)kTabEntries * kPairs) +
-           sizeof(double) * (size_t)(2 * (N - 2)) * kLanes;
+           (P64G ? 0 : sizeof(double) * (size_t)(2 * (N - 2)) * kLanes);
   }
 };
 
 // RAW: amplitudes go unscaled, in T, to amp_raw[(h K + sigma) 32 + pair]
 // (block-private LDS); otherwise scaled, in FP64, to
-// amp[(h K + sigma) astride + acol].
-template <int N, typename T, bool RAW>
+// amp[(h K + sigma) astride + acol].  P64G: see Lds.
+template <int N, typename T, bool RAW, bool P64G>
 struct Ctx {
   static constexpr bool kRaw = RAW;
+  static constexpr bool kP64G = P64G;
+  const double* mom;
   T* gl_slots;      // [slot][lane]
   T* tab;           // [mask][pair]
   double* p64;      // [2 (g-1) + c][lane]
@@ -198,7 +203,12 @@ __device__ __forceinline__ void level(State<N, T>& s, CtxT& c, int used) {
       s.J[D][D].re[m] = c.gl_slots[(base + m) * Lds<N>::kLanes + c.lane];
       s.J[D][D].im[m] = c.gl_slots[(base + 2 + m) * Lds<N>::kLanes + c.lane];
       s.Pg[D].v[m] = c.gl_slots[(base + 4 + m) * Lds<N>::kLanes + c.lane];
-      s.P0[D].v[m] = s.P0[D - 1].v[m] + c.p64[(2 * (g - 1) + m) * Lds<N>::kLanes + c.lane];
+      double pg;
+      if constexpr (CtxT::kP64G)
+        pg = c.mom[((int64_t)g * 4 + 2 * c.h + m) * c.E + c.e];
+      else
+        pg = c.p64[(2 * (g - 1) + m) * Lds<N>::kLanes + c.lane];
+      s.P0[D].v[m] = s.P0[D - 1].v[m] + pg;
     }
     Cx<T> top;
     build_column<N, T, D, D - 1>(s, c, 1 << g, top);
@@ -222,9 +232,10 @@ __device__ __forceinline__ void level(State<N, T>& s, CtxT& c, int used) {
 
 // Amplitudes of the event pair of this lane (event e of an [n][4][E] input);
 // padding pairs (live = false) repeat a valid event and store nothing.  The
-// block must be one 64-lane wave; lds holds Lds<N>::bytes<T>().  RAW: the
+// block's waves must all call it (it synchronises the block); lds is this
+// wave's region of Lds<N>::bytes<T>().  RAW: the
 // unscaled amplitudes go to amp_raw (see Ctx), amp is unused.
-template <int N, typename T, bool RAW = false>
+template <int N, typename T, bool RAW = false, bool P64G = false>
 __device__ __forceinline__ void cobg_pair_body(unsigned char* lds, int64_t E,
                                                const double* __restrict__ mom,
                                                const int8_t* __restrict__ hel, int hconf,
@@ -232,10 +243,11 @@ __device__ __forceinline__ void cobg_pair_body(unsigned char* lds, int64_t E,
                                                int64_t astride, int64_t acol,
                                                T* amp_raw = nullptr) {
   constexpr int M = N - 1;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;  // lane within this wave (the wave owns lds)
   const int pair = lane >> 1;
   const int h = lane & 1;
-  Ctx<N, T, RAW> c;
+  Ctx<N, T, RAW, P64G> c;
+  c.mom = mom;
   c.gl_slots = reinterpret_cast<T*>(lds);
   c.tab = c.gl_slots + (size_t)Lds<N>::kGluonSlots * Lds<N>::kLanes;
   c.p64 = reinterpret_cast<double*>(c.tab + (size_t)Lds<N>::kTabEntries * Lds<N>::kPairs);
@@ -290,7 +302,7 @@ __device__ __forceinline__ void cobg_pair_body(unsigned char* lds, int64_t E,
         c.gl_slots[(base + m) * Lds<N>::kLanes + lane] = cur.re[m];
         c.gl_slots[(base + 2 + m) * Lds<N>::kLanes + lane] = cur.im[m];
         c.gl_slots[(base + 4 + m) * Lds<N>::kLanes + lane] = (T)ph[m];
-        c.p64[(2 * (i - 1) + m) * Lds<N>::kLanes + lane] = ph[m];
+        if constexpr (!P64G) c.p64[(2 * (i - 1) + m) * Lds<N>::kLanes + lane] = ph[m];
       }
     }
   }

@@ -14,10 +14,10 @@
 // move.  Without helicities the tile loops over all 2^n configurations and
 // sums.
 //
-// Colour-dressed chunk (n >= 8 in the batch): up to 64 consecutive events are
-// classified one per lane (closed colour circuit, as in cdbg_impl.h); invalid
-// ones get exactly 0 and the valid ones are evaluated one at a time by the
-// whole wave.
+// Colour-dressed chunk (n >= 8 in the batch): up to 256 consecutive events
+// are classified one per lane (closed colour circuit, as in cdbg_impl.h);
+// invalid ones get exactly 0 and the valid ones are evaluated one at a time by
+// all lanes of the block.
 #pragma once
 
 #include <stdint.h>
@@ -39,9 +39,9 @@ struct Cobg {
   static constexpr int K = (int)Factorial<N - 2>::value;
   static constexpr bool kLdsAmp = N <= 6;
   static constexpr int kScratch = kLdsAmp ? 0 : 2 * K * kTileEvents;  // doubles per block
-  template <typename T>
+  template <typename T, bool P64G = false>
   static constexpr size_t lds_bytes() {
-    return pairk::Lds<N>::template bytes<T>() +
+    return pairk::Lds<N>::template bytes<T, P64G>() +
            (kLdsAmp ? sizeof(T) * 2 * (size_t)K * kTileEvents : 0);
   }
 };
@@ -84,11 +84,12 @@ __device__ __forceinline__ double lower_quadform(const double* __restrict__ Cb, 
   return q;
 }
 
-// Colour-summed |M|^2 of events [first, first + count) (count <= 32) of an
-// [n][4][E] input.  HSUM: sum over all 2^n helicity configurations (hel is
-// ignored); otherwise one configuration per event from hel.  lds holds
-// Cobg<N>::lds_bytes<T>(); blk is the block's scratch slice (n = 7 only).
-template <int N, typename T, bool HSUM>
+// Colour-summed |M|^2 of events [first, first + count) (0 <= count <= 32,
+// event `first` must exist) of an [n][4][E] input, on one wave.  HSUM: sum
+// over all 2^n helicity configurations (hel is ignored); otherwise one
+// configuration per event from hel.  lds is the wave's Cobg<N>::lds_bytes<T>();
+// blk its scratch slice (n = 7 only).
+template <int N, typename T, bool HSUM, bool P64G = false>
 __device__ __forceinline__ void cobg_tile(unsigned char* lds, int64_t E,
                                           const double* __restrict__ mom,
                                           const int8_t* __restrict__ hel,
@@ -96,18 +97,20 @@ __device__ __forceinline__ void cobg_tile(unsigned char* lds, int64_t E,
                                           double* __restrict__ me2, int64_t first, int count) {
   constexpr int K = Cobg<N>::K;
   constexpr bool kL = Cobg<N>::kLdsAmp;
-  T* amp_lds = reinterpret_cast<T*>(lds + pairk::Lds<N>::template bytes<T>());
-  const int lane = threadIdx.x;
+  T* amp_lds = reinterpret_cast<T*>(lds + pairk::Lds<N>::template bytes<T, P64G>());
+  const int lane = threadIdx.x & 63;
   const int pair = lane >> 1;
   const int h = lane & 1;
+  // count = 0: a wave without events in this round still takes part in the
+  // block's barriers, evaluating event `first` without storing it
   const bool live = pair < count;
-  int64_t e = first + (live ? pair : count - 1);
+  int64_t e = first + (live ? pair : (count > 0 ? count - 1 : 0));
   auto one = [&](const int8_t* hp, int hc) -> double {
     if constexpr (kL) {
-      pairk::cobg_pair_body<N, T, true>(lds, E, mom, hp, hc, e, true, nullptr, 0, 0, amp_lds);
+      pairk::cobg_pair_body<N, T, true, P64G>(lds, E, mom, hp, hc, e, true, nullptr, 0, 0, amp_lds);
       return lower_quadform<K>(Cb, amp_lds + (size_t)h * K * kTileEvents + pair, kTileEvents);
     } else {
-      pairk::cobg_pair_body<N, T, false>(lds, E, mom, hp, hc, e, true, blk, kTileEvents, pair);
+      pairk::cobg_pair_body<N, T, false, P64G>(lds, E, mom, hp, hc, e, true, blk, kTileEvents, pair);
       return lower_quadform<K>(Cb, blk + (size_t)h * K * kTileEvents + pair, kTileEvents);
     }
   };
@@ -134,26 +137,35 @@ __device__ __forceinline__ void cobg_tile(unsigned char* lds, int64_t E,
   if (live && h == 0) me2[e] = tot;
 }
 
-// Colour-dressed |A|^2 of events [first, first + count), count <= 64.
-template <int N, typename T>
-__device__ __forceinline__ void cdbg_chunk(unsigned char* lds, int64_t E,
+// Colour-dressed |A|^2 of events [first, first + count), count <= NL, on
+// the NL lanes of the block: one lane classifies each event (invalid flows
+// get exactly 0), then the valid ones are evaluated in order by all lanes.
+// vmask: NL/64 words of LDS for the validity masks.
+template <int N, typename T, int NL>
+__device__ __forceinline__ void cdbg_chunk(unsigned char* lds, unsigned long long* vmask, int64_t E,
                                            const double* __restrict__ mom,
                                            const int8_t* __restrict__ hel,
                                            const int8_t* __restrict__ col,
                                            double* __restrict__ me2, int64_t first, int count) {
   const cdbgk::Sm<N, T> sm = cdbgk::carve<N, T>(lds);
-  const int lane = threadIdx.x;
+  const int t = threadIdx.x;
   bool valid = false;
-  if (lane < count) {
-    valid = cdbgk::flow_valid(N, E, col, first + lane);
-    if (!valid) me2[first + lane] = 0.0;
+  if (t < count) {
+    valid = cdbgk::flow_valid(N, E, col, first + t);
+    if (!valid) me2[first + t] = 0.0;
   }
-  uint64_t m = __ballot(valid);
-  while (m) {
-    const int l = __builtin_ctzll(m);
-    m &= m - 1;
-    cdbgk::cdbg_one_event<N, T>(sm, E, mom, hel, col, first + l, me2);
+  const unsigned long long m = __ballot(valid);
+  if ((t & 63) == 0) vmask[t >> 6] = m;
+  __syncthreads();
+  for (int w = 0; w < NL / 64; ++w) {
+    unsigned long long mm = vmask[w];
+    while (mm) {
+      const int l = __builtin_ctzll(mm);
+      mm &= mm - 1;
+      cdbgk::cdbg_one_event<N, T, NL>(sm, E, mom, hel, col, first + 64 * w + l, me2);
+    }
   }
+  __syncthreads();  // vmask is rewritten by the next chunk
 }
 
 }  // namespace fusedk

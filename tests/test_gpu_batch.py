@@ -2,11 +2,11 @@
 
 The batch kernel evaluates every event with the same device routines as the
 single-request entry point (fused colour-ordered tiles for n <= 7,
-colour-dressed chunks for n >= 8).  In FP64 its output equals bg_me2 on each
-segment alone bit for bit; in FP32 the two kernels may contract multiply-adds
-differently, so they agree to the recursion's rounding.  Within the batch
-kernel the result does not depend on tile or grid shape (bit for bit).  A few
-events of each segment are also checked against the oracle directly.
+colour-dressed chunks for n >= 8).  Colour-ordered segments in FP64 equal
+bg_me2 on each segment alone bit for bit; otherwise the two agree to rounding
+(see _same).  Within the batch kernel the result does not depend on tile or
+grid shape (bit for bit).  A few events of each segment are also checked
+against the oracle directly.
 """
 import numpy as np
 import pytest
@@ -50,28 +50,34 @@ def _single(api, segs, precision):
 
 
 def _same(segs, got, ref, precision, label=""):
-    """FP64: bit-identical.  FP32: the two kernels may contract multiply-adds
-    differently, so the recursion's rounding differs; per-event relative
-    difference median <= 1e-6 and max <= 1e-2 (the conditioning tail of the
-    FP32 parity tests) on events with a non-vanishing tree amplitude; for the
-    colour-dressed segments the zeros (invalid colour flows) coincide."""
+    """Colour-ordered segments in FP64: bit-identical.  Otherwise the two
+    kernels may round differently (FP32: multiply-add contraction; colour-
+    dressed: the batch evaluates an event on 256 lanes, the single request on
+    128 or 256, which splits the vertex sums differently): per-event relative
+    difference median <= 1e-13 / max <= 1e-9 (FP64) or median <= 1e-6 /
+    max <= 1e-2 (FP32, the conditioning tail of the FP32 parity tests) on
+    events with a non-vanishing tree amplitude; for the colour-dressed segments
+    the zeros of invalid colour flows coincide."""
     for s, g, r in zip(segs, got, ref):
         g, r = g.cpu().numpy(), r.cpu().numpy()
-        if precision == "fp64":
+        if precision == "fp64" and s["n"] <= 7:
             assert np.array_equal(g, r), f"{label} n={s['n']}"
             continue
         keep = nonvanishing(s["hel"].cpu().numpy())
         if s["n"] >= 8:
-            # zeros of invalid colour flows coincide; flows whose amplitude
-            # cancels to rounding may give an exact 0 on one side only
+            # flows whose amplitude cancels to rounding may give an exact 0 on
+            # one side only
             typical = np.median(np.abs(r[r != 0.0])) if (r != 0.0).any() else 0.0
             noise = (np.abs(r) < 1e-8 * typical) & (np.abs(g) < 1e-8 * typical)
             assert np.array_equal((g == 0.0) | noise, (r == 0.0) | noise), f"{label} n={s['n']}"
-            keep &= np.abs(r) >= 1e-8 * typical
+            keep &= (np.abs(r) >= 1e-8 * typical) & (r != 0.0)
+        if not keep.any():
+            continue
         rel = np.abs(g - r)[keep] / np.abs(r[keep])
         _say(f"  {label} n={s['n']}: events differing {(g != r).sum()} of {g.size}, "
              f"rel diff median {np.median(rel):.1e} max {rel.max():.1e}")
-        assert np.median(rel) <= 1e-6 and rel.max() <= 1e-2, f"{label} n={s['n']}"
+        med, mx = (1e-13, 1e-9) if precision == "fp64" else (1e-6, 1e-2)
+        assert np.median(rel) <= med and rel.max() <= mx, f"{label} n={s['n']}"
 
 
 def _small_mix():
@@ -112,12 +118,13 @@ def test_batch_spot_checks_against_oracle(api):
 
 
 @pytest.mark.parametrize("cfg", [
-    dict(blocks_per_cu=1, cobg_tile_events=32, cdbg_tile_events=64),
-    dict(blocks_per_cu=2, cobg_tile_events=128, cdbg_tile_events=512),
-    dict(blocks_per_cu=0, cobg_tile_events=4096, cdbg_tile_events=4096),
+    dict(blocks_per_cu=1, cobg_tile_events=128, cdbg_tile_events=256, waves_per_simd=1),
+    dict(blocks_per_cu=2, cobg_tile_events=256, cdbg_tile_events=512, waves_per_simd=2),
+    dict(blocks_per_cu=0, cobg_tile_events=8192, cdbg_tile_events=8192, waves_per_simd=1),
 ])
 def test_batch_result_independent_of_config(api, cfg):
-    """Same kernel, other tiles and grid: bit-identical results."""
+    """Other tiles and grid: bit-identical results; the other register-budget
+    variant: the same up to multiply-add contraction (FP32 rounding)."""
     segs = _segments(_small_mix())
     ref = [r.clone() for r in api.me2_batch(segs, "fp32")]
     old = api.batch_config("fp32")
@@ -128,8 +135,11 @@ def test_batch_result_independent_of_config(api, cfg):
         torch.cuda.synchronize()
     finally:
         api.set_batch_config("fp32", **old)
-    for g, r in zip(got, ref):
-        assert torch.equal(g, r)
+    if cfg["waves_per_simd"] == 2:
+        for g, r in zip(got, ref):
+            assert torch.equal(g, r)
+    else:
+        _same(segs, got, ref, "fp32", "other register budget")
 
 
 def test_batch_rejects_bad_requests(api):
