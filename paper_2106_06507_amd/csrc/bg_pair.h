@@ -27,13 +27,17 @@ struct Cx {
   T re, im;
 };
 
+// quad_perm [1,0,3,2] reads a lane of the same quad, so no lane is out of
+// bounds and the value written for out-of-bounds lanes (bound_ctrl) never
+// matters; with an undefined old value the compiler can fold the move into
+// the consuming add (v_add_f32_dpp).
 __device__ __forceinline__ float xswap(float x) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, true));
 }
 
 __device__ __forceinline__ double xswap(double x) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0xB1, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0xB1, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0xB1, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0xB1, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 
