@@ -132,13 +132,15 @@ __device__ __forceinline__ void tdotj_acc(T* gre, T* gim, const T* tre, const T*
 
 // The x-th subset of S in the order of the binary counter over S's bits
 // (bit b of x selects the b-th lowest member of S): x = 1 .. 2^|S| - 2 runs
-// over the non-empty proper subsets.
+// over the non-empty proper subsets.  Fixed trip count (no divergence).
+template <int M>
 __device__ __forceinline__ int subset_of(int x, int S) {
-  int r = 0;
-  for (int b = 0; S; ++b) {
-    const int low = S & -S;
-    if (x & (1 << b)) r |= low;
-    S ^= low;
+  int r = 0, j = 0;
+#pragma unroll
+  for (int b = 0; b < M; ++b) {
+    const bool in = (S >> b) & 1;
+    r |= (in && ((x >> j) & 1)) ? (1 << b) : 0;
+    j += in ? 1 : 0;
   }
   return r;
 }
@@ -447,7 +449,7 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
         S = item >> 2;
         t = item & 3;
         for (int k = sub; k < nsplit; k += q) {
-          const int m1 = subset_of(k + 1, S);
+          const int m1 = subset_of<M>(k + 1, S);
           const int m2 = S ^ m1;
           int s1, s2;
           if (!split_slots(sm.code[m1], sm.code[m2], t, s1, s2)) continue;
