@@ -11,8 +11,9 @@ sum; the plain FP64 path is timed beside it.
 Further rows (same JSON line): the two-stage path with amplitudes through
 memory and the matrix-core contraction, the colour-dressed gg -> 6g workload
 (n = 8, sampled colour flows), the adjoint d|M|^2/dp for gg -> 4g (2^18
-events), and the mixed-multiplicity batch (n = 4..9) in one persistent launch
-replayed from a recorded graph.
+events), the mixed-multiplicity batch (n = 4..9) in one persistent launch
+replayed from a recorded graph, and phase space generated on the device
+ahead of the evaluation.
 
 Prints one JSON line.  Only one GPU is used: --gpus above 1 exits.
 """
@@ -269,6 +270,32 @@ def section_batch(args, api, torch):
             "single_requests_total_ms": float(sum(single))}
 
 
+def section_pipeline(args, api, torch):
+    """Phase space generated on the device (RAMBO + cuts + helicities) and fed
+    to the fused evaluation: the whole Monte Carlo step with no host data."""
+    n, E = 6, args.events
+    steps = max(2, args.steps // 4)
+    attempts = int(1.5 * E)  # acceptance of the cuts at n = 6 is ~0.86
+    out = api.generate(n, E, 2106065070 + 11, n_attempts=attempts)
+    me2 = torch.empty(E, dtype=torch.float64, device="cuda")
+
+    def gen():
+        api.generate(n, E, 2106065070 + 11, n_attempts=attempts)
+
+    def both():
+        o = api.generate(n, E, 2106065070 + 11, n_attempts=attempts)
+        api.me2(o["mom"], o["hel"], precision="fp32", out=me2)
+
+    log("timing device phase space + fused evaluation")
+    gms = time_events(gen, steps, 1)
+    pms = time_events(both, steps, 1)
+    torch.cuda.synchronize()
+    return {"workload": "gg->4g n=6: RAMBO + cuts + sampled helicities on the device, then the "
+                        "fused FP32 evaluation", "events": int(out["n_generated"]),
+            "attempts": attempts, "generate_ms": gms, "pipeline_ms": pms,
+            "value": E / (pms * 1e-3)}
+
+
 def cpu_baseline(args, ev):
     """The oracle on the first --cpu-sample headline events, one thread (BLAS
     pools limited to 1), in chunks of 2^15 events to bound memory."""
@@ -294,8 +321,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--events", type=int, default=1 << 20)
-    ap.add_argument("--sections", default="cdbg,adjoint,batch",
-                    help="extra rows beside the headline: any of cdbg, adjoint, batch, or none")
+    ap.add_argument("--sections", default="cdbg,adjoint,batch,pipeline",
+                    help="extra rows beside the headline: any of cdbg, adjoint, batch, "
+                         "pipeline, or none")
     ap.add_argument("--cpu-sample", type=int, default=1 << 19,
                     help="events of the headline workload timed on the oracle")
     ap.add_argument("--no-cpu", action="store_true")
@@ -327,6 +355,8 @@ def main():
         extra["adjoint_gg_4g"] = section_adjoint(args, api, torch)
     if "batch" in sections:
         extra["mixed_batch"] = section_batch(args, api, torch)
+    if "pipeline" in sections:
+        extra["device_phase_space_pipeline"] = section_pipeline(args, api, torch)
     cpu = None if args.no_cpu else cpu_baseline(args, ev)
 
     rec = {

@@ -185,6 +185,43 @@ int bg_batch_config_set(bg_context* ctx, int precision, const bg_batch_config* c
 int bg_me2_batch_tune(bg_context* ctx, const bg_request* segs, int n_segs,
                       bg_batch_config* best, double* best_ms, void* stream);
 
+/* On-device phase-space points (Section 3: RAMBO, massless, all momenta
+ * outgoing with the beams (sqrt_s/2)(1,0,0,+-1) negated as gluons 1 and 2;
+ * Section 5: p_T > pt_min for each outgoing gluon and Delta R > dr_min for
+ * each pair, pseudo-rapidity of massless momenta), with sampled helicities and
+ * colour-flow pairs.  Randomness: keyed SplitMix64 (Steele, Lea, Flood 2014);
+ * attempt t takes u_j = ((z >> 11) + 0.5) 2^-53 with
+ * z = mix64(mix64(seed + G (t + 1)) + G (j + 1)), G = 0x9E3779B97F4A7C15,
+ * j = 0 .. 4(n-2)-1 for RAMBO (cos theta = 2u-1, phi = 2 pi u,
+ * E = -log(u u) per outgoing gluon, then the RAMBO boost and scaling), then
+ * n draws for helicities (u < 1/2 -> +1, else -1), then 2n for the colour
+ * pairs (i_k, j_k) = min(floor(3u), 2).  The same stream and laws as the
+ * seeded host generator of the tests, so the two produce the same events.
+ * Attempts first_attempt .. first_attempt + n_attempts - 1 are tried; the
+ * accepted ones, in attempt order, are written at ranks 0 .. max_events - 1
+ * of mom [n][4][max_events], hel [n][max_events] (flag BG_GEN_HEL),
+ * col [2][n][max_events] (flag BG_GEN_COL) and attempt [max_events] (int64,
+ * the attempt index of each event; may be NULL).  *n_generated (DEVICE
+ * int64) receives min(accepted, max_events); slots beyond it are untouched.
+ * Without BG_GEN_CUTS every attempt is accepted.  Asynchronous; uses a
+ * context workspace of about n_attempts / 8 bytes (allocated on first use
+ * of a size).  1 <= n_attempts <= 2^31, max_events >= 1. */
+#define BG_GEN_CUTS 1
+#define BG_GEN_HEL  2
+#define BG_GEN_COL  4
+typedef struct bg_gen_params {
+    int n;                   /* gluons, BG_N_MIN..BG_N_MAX */
+    int flags;               /* BG_GEN_* */
+    double sqrt_s;           /* GeV, > 0 */
+    double pt_min;           /* GeV */
+    double dr_min;
+    uint64_t seed;
+    uint64_t first_attempt;
+} bg_gen_params;
+int bg_generate(bg_context* ctx, const bg_gen_params* params, int64_t n_attempts,
+                int64_t max_events, double* mom, int8_t* hel, int8_t* col, int64_t* attempt,
+                int64_t* n_generated, void* stream);
+
 /* Self-test of the matrix-core operand layout used by bg_color_contract:
  * runs one v_mfma_f64_16x16x4f64 with lane l supplying A[l%16][l/16] =
  * (l%16 + 1) + 100 (l/16) and B[l/16][l%16] = (l%16 + 1) 8^(l/16), and copies

@@ -48,6 +48,20 @@ class bg_batch_config(ctypes.Structure):
 
 BATCH_MAX_SEGS = 32
 
+GEN_CUTS, GEN_HEL, GEN_COL = 1, 2, 4
+
+
+class bg_gen_params(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int),
+        ("flags", ctypes.c_int),
+        ("sqrt_s", ctypes.c_double),
+        ("pt_min", ctypes.c_double),
+        ("dr_min", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("first_attempt", ctypes.c_uint64),
+    ]
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int
 _I64 = ctypes.c_int64
@@ -67,6 +81,7 @@ _SIGNATURES = {
     "bg_batch_config_set": (_I, [_P, _I, ctypes.POINTER(bg_batch_config)]),
     "bg_me2_batch_tune": (_I, [_P, ctypes.POINTER(bg_request), _I, ctypes.POINTER(bg_batch_config),
                                ctypes.POINTER(ctypes.c_double), _P]),
+    "bg_generate": (_I, [_P, ctypes.POINTER(bg_gen_params), _I64, _I64, _P, _P, _P, _P, _P, _P]),
     "bg_mfma_layout_probe": (_I, [_P, _P]),
 }
 

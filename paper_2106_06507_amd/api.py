@@ -11,7 +11,7 @@ import threading
 import torch
 
 from . import _lib
-from ._lib import bg_batch_config, bg_request, check, lib
+from ._lib import bg_batch_config, bg_gen_params, bg_request, check, lib
 
 _PREC = {"fp64": _lib.PREC_FP64, "fp32": _lib.PREC_FP32_MIXED, "mixed": _lib.PREC_FP32_MIXED}
 _MODE = {"cobg": _lib.MODE_COBG, "cdbg": _lib.MODE_CDBG, "auto": _lib.MODE_AUTO}
@@ -271,3 +271,39 @@ class BatchGraph:
     def replay(self):
         self.graph.replay()
         return self.outs
+
+
+# ---------------------------------------------------------------- phase space
+
+
+def generate(n, n_events, seed, n_attempts=None, first_attempt=0, cuts=True, sample_hel=True,
+             sample_col=False, sqrt_s=1000.0, pt_min=20.0, dr_min=0.4, with_attempts=False,
+             device=None, ctx=None):
+    """Events generated on the device (RAMBO + cuts, helicities, colours).
+
+    Tries n_attempts attempts from first_attempt (default: 2 n_events, or
+    n_events without cuts) and returns a dict with mom [n, 4, E], hel, col,
+    attempt (int64 [E], if with_attempts) and n_generated (a 0-d device
+    tensor: min(accepted, n_events); slots beyond it are undefined).  Nothing
+    is synchronised."""
+    if device is None:
+        device = torch.device("cuda", torch.cuda.current_device())
+    ctx = ctx or default_context(device.index)
+    if n_attempts is None:
+        n_attempts = 2 * n_events if cuts else n_events
+    E = int(n_events)
+    mom = torch.empty((n, 4, E), dtype=torch.float64, device=device)
+    hel = torch.empty((n, E), dtype=torch.int8, device=device) if sample_hel else None
+    col = torch.empty((2, n, E), dtype=torch.int8, device=device) if sample_col else None
+    att = torch.empty(E, dtype=torch.int64, device=device) if with_attempts else None
+    ngen = torch.zeros((), dtype=torch.int64, device=device)
+    p = bg_gen_params()
+    p.n = n
+    p.flags = (_lib.GEN_CUTS if cuts else 0) | (_lib.GEN_HEL if sample_hel else 0) | \
+        (_lib.GEN_COL if sample_col else 0)
+    p.sqrt_s, p.pt_min, p.dr_min = sqrt_s, pt_min, dr_min
+    p.seed = seed & 0xFFFFFFFFFFFFFFFF
+    p.first_attempt = first_attempt
+    check(lib().bg_generate(ctx.handle, ctypes.byref(p), int(n_attempts), E, _ptr(mom), _ptr(hel),
+                            _ptr(col), _ptr(att), _ptr(ngen), _stream(device)), "bg_generate")
+    return {"mom": mom, "hel": hel, "col": col, "attempt": att, "n_generated": ngen}

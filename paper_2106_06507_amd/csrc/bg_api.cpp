@@ -49,6 +49,8 @@ struct bg_context {
   size_t scratch_bytes = 0;
   std::vector<void*> retired;                // outgrown scratch buffers, freed on destroy
   unsigned* counter = nullptr;               // tile-queue heads: [0] batch, [1] fused n = 7
+  unsigned* gen_ws = nullptr;                // phase-space generator: acceptance bits, counts
+  size_t gen_ws_words = 0;
   bg_batch_config bcfg[2] = {{0, 128, 256, 2}, {0, 128, 256, 2}};
   std::vector<BatchPlan> plans;
   uint64_t clock = 0;
@@ -316,6 +318,7 @@ void bg_context_destroy(bg_context* ctx) {
   if (ctx->cws) (void)hipFree(ctx->cws);
   if (ctx->scratch) (void)hipFree(ctx->scratch);
   for (void* p : ctx->retired) (void)hipFree(p);
+  if (ctx->gen_ws) (void)hipFree(ctx->gen_ws);
   if (ctx->counter) (void)hipFree(ctx->counter);
   for (BatchPlan& pl : ctx->plans)
     if (pl.tiles) (void)hipFree(pl.tiles);
@@ -788,6 +791,44 @@ int bg_me2_batch_tune(bg_context* ctx, const bg_request* segs, int n_segs, bg_ba
   if (best) *best = cur;
   if (best_ms) *best_ms = cur_ms;
   return BG_OK;
+}
+
+int bg_generate(bg_context* ctx, const bg_gen_params* gp, int64_t n_attempts, int64_t max_events,
+                double* mom, int8_t* hel, int8_t* col, int64_t* attempt, int64_t* n_generated,
+                void* stream) {
+  if (!ctx || !gp || !mom || !n_generated) return BG_EINVAL;
+  if (!valid_n(gp->n)) return BG_EINVAL;
+  if (gp->flags & ~(BG_GEN_CUTS | BG_GEN_HEL | BG_GEN_COL)) return BG_EINVAL;
+  if (((gp->flags & BG_GEN_HEL) && !hel) || ((gp->flags & BG_GEN_COL) && !col)) return BG_EINVAL;
+  if (!(gp->sqrt_s > 0.0) || !(gp->pt_min >= 0.0) || !(gp->dr_min >= 0.0)) return BG_EINVAL;
+  if (n_attempts < 1 || max_events < 1) return BG_EINVAL;
+  if (n_attempts > ((int64_t)1 << 31)) return BG_ERANGE;
+  int st = check_events(gp->n, max_events);
+  if (st) return st;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return BG_EDEVICE;
+  const size_t words = bg::generate_workspace_words(n_attempts);
+  if (ctx->gen_ws_words < words) {
+    if (stream_capturing((hipStream_t)stream)) return BG_EINVAL;
+    unsigned* w = nullptr;
+    st = hip_status(hipMalloc(&w, sizeof(unsigned) * words), "hipMalloc(generator workspace)");
+    if (st) return st;
+    if (ctx->gen_ws) ctx->retired.push_back(ctx->gen_ws);  // queued work may still read it
+    ctx->gen_ws = w;
+    ctx->gen_ws_words = words;
+  }
+  bg::GenParams p;
+  p.n = gp->n;
+  p.cuts = (gp->flags & BG_GEN_CUTS) ? 1 : 0;
+  p.sqrt_s = gp->sqrt_s;
+  p.pt_min = gp->pt_min;
+  p.dr_min = gp->dr_min;
+  p.seed = gp->seed;
+  p.first_attempt = gp->first_attempt;
+  return launch_status(bg::generate_events(p, n_attempts, max_events, ctx->gen_ws, mom,
+                                           (gp->flags & BG_GEN_HEL) ? hel : nullptr,
+                                           (gp->flags & BG_GEN_COL) ? col : nullptr, attempt,
+                                           n_generated, (hipStream_t)stream));
 }
 
 int bg_mfma_layout_probe(bg_context* ctx, double* out) {

@@ -109,4 +109,20 @@ int batch_launch(bool fp32, int waves, const BatchSegTable& segs, const BatchTil
                  unsigned n_tiles, unsigned* counter, double* scratch, int64_t scratch_stride,
                  int grid, size_t lds, hipStream_t stream);
 
+// On-device phase-space generation (rambo.hip).
+struct GenParams {
+  int n;
+  int cuts;
+  double sqrt_s, pt_min, dr_min;
+  uint64_t seed, first_attempt;
+};
+size_t generate_workspace_words(int64_t n_attempts);
+// Attempts [first_attempt, first_attempt + n_attempts): accepted ones, in
+// attempt order, written at ranks < max_events (arrays of stride
+// max_events); *n_out (device) = min(accepted, max_events).  hel, col and
+// attempt may be null.
+int generate_events(const GenParams& gp, int64_t n_attempts, int64_t max_events, unsigned* ws,
+                    double* mom, int8_t* hel, int8_t* col, int64_t* attempt, int64_t* n_out,
+                    hipStream_t stream);
+
 }  // namespace bg

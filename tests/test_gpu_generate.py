@@ -1,0 +1,120 @@
+"""On-device phase-space generation against the seeded host generator.
+
+Both implement the same keyed SplitMix64 stream and the same RAMBO, cut and
+sampling laws (the device from the published definitions in its own code),
+so helicities, colours and the accepted attempts must agree exactly and the
+momenta to rounding (the device's log, sin, cos and sqrt may differ from the
+host's in the last bit; RAMBO's rescaling by sqrt(s)/M amplifies that for
+nearly collinear seeds: median 1e-14, max 1e-10 of sqrt(s)).  An attempt whose cut variables lie within 1e-9 of a
+threshold could be decided differently by that rounding; none occurs in
+these samples, which the tests assert.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from bg_inputs import make_events
+from bg_inputs.rambo import passes_cuts, rambo_massless, PT_MIN, DR_MIN
+from bg_inputs.rng import splitmix64_uniform
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_06507_amd import api as a
+    return a
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _host_accepted(n, seed, t0, n_attempts, cuts=True):
+    """Attempt indices in [t0, t0 + n_attempts) that pass the cuts, and the
+    smallest relative distance of any attempt's cut variables to a threshold."""
+    ctr = np.arange(t0, t0 + n_attempts, dtype=np.uint64)
+    u = splitmix64_uniform(seed, ctr, 4 * (n - 2))
+    p = rambo_massless(u, 1000.0)
+    ok = passes_cuts(p) if cuts else np.ones(n_attempts, dtype=bool)
+    pt = np.hypot(p[..., 1], p[..., 2])
+    margin = np.min(np.abs(pt - PT_MIN) / PT_MIN)
+    eta = np.arcsinh(p[..., 3] / pt)
+    phi = np.arctan2(p[..., 2], p[..., 1])
+    m2 = np.inf
+    for i in range(n - 2):
+        for j in range(i + 1, n - 2):
+            dphi = np.abs(phi[:, i] - phi[:, j])
+            dphi = np.where(dphi > math.pi, 2 * math.pi - dphi, dphi)
+            dr2 = (eta[:, i] - eta[:, j]) ** 2 + dphi ** 2
+            m2 = min(m2, np.min(np.abs(dr2 - DR_MIN ** 2) / DR_MIN ** 2))
+    return t0 + np.nonzero(ok)[0], min(margin, m2)
+
+
+@pytest.mark.parametrize("n,col", [(4, False), (6, False), (8, True), (9, True)])
+def test_generate_matches_host(api, n, col):
+    E, seed = 20000, 4242 + n
+    _say(f"bg_generate n={n} E={E}")
+    out = api.generate(n, E, seed, n_attempts=3 * E, sample_col=col, with_attempts=True)
+    torch.cuda.synchronize()
+    assert int(out["n_generated"]) == E
+    ref = make_events(n, E, seed=seed, cuts=True, sample_hel=True, sample_col=col)
+    acc, margin = _host_accepted(n, seed, 0, 3 * E)
+    assert margin > 1e-9
+    assert np.array_equal(out["attempt"].cpu().numpy(), acc[:E])
+    assert np.array_equal(out["hel"].cpu().numpy(), ref["hel"])
+    if col:
+        assert np.array_equal(out["col"].cpu().numpy(), ref["col"])
+    m = out["mom"].cpu().numpy()
+    # the RAMBO scaling x = sqrt(s) / M amplifies last-bit differences of
+    # log/sin/cos/sqrt when the massless seeds are nearly collinear (M small)
+    d = np.abs(m - ref["mom"]).max(axis=(0, 1)) / 1000.0
+    _say(f"  |dp| / sqrt(s): median {np.median(d):.1e} max {d.max():.1e}")
+    assert np.median(d) < 1e-14 and d.max() < 1e-10
+    # conservation and masslessness of the device momenta
+    assert np.max(np.abs(m.sum(axis=0))) < 1e-9
+    p2 = m[:, 0] ** 2 - m[:, 1] ** 2 - m[:, 2] ** 2 - m[:, 3] ** 2
+    assert np.max(np.abs(p2)) < 1e-7
+
+
+def test_generate_resume_and_short_supply(api):
+    """Attempt ranges concatenate; too few attempts give fewer events."""
+    n, seed = 6, 99
+    a = api.generate(n, 5000, seed, n_attempts=4000, with_attempts=True)
+    b = api.generate(n, 5000, seed, n_attempts=4000, first_attempt=4000, with_attempts=True)
+    c = api.generate(n, 10000, seed, n_attempts=8000, with_attempts=True)
+    torch.cuda.synchronize()
+    na, nb, nc = int(a["n_generated"]), int(b["n_generated"]), int(c["n_generated"])
+    assert na < 4000 and nb < 4000 and nc == na + nb
+    cat = np.concatenate([a["attempt"].cpu().numpy()[:na], b["attempt"].cpu().numpy()[:nb]])
+    assert np.array_equal(cat, c["attempt"].cpu().numpy()[:nc])
+    assert np.array_equal(np.concatenate([a["mom"].cpu().numpy()[:, :, :na], b["mom"].cpu().numpy()[:, :, :nb]], axis=2),
+                          c["mom"].cpu().numpy()[:, :, :nc])
+
+
+def test_generate_without_cuts(api):
+    n, E, seed = 5, 3000, 7
+    out = api.generate(n, E, seed, cuts=False, with_attempts=True)
+    torch.cuda.synchronize()
+    assert int(out["n_generated"]) == E
+    assert np.array_equal(out["attempt"].cpu().numpy(), np.arange(E))
+    ref = make_events(n, E, seed=seed, cuts=False)
+    assert np.max(np.abs(out["mom"].cpu().numpy() - ref["mom"])) / 1000.0 < 1e-10
+
+
+def test_generate_then_evaluate(api):
+    """Generated events feed bg_me2 directly (no host round trip); the result
+    equals evaluating the host generator's events."""
+    n, E, seed = 6, 4096, 2024
+    out = api.generate(n, E, seed)
+    got = api.me2(out["mom"], out["hel"], precision="fp64")
+    ref = make_events(n, E, seed=seed)
+    want = api.me2(torch.from_numpy(ref["mom"]).cuda(), torch.from_numpy(ref["hel"]).cuda(),
+                   precision="fp64")
+    rel = (got - want).abs() / want.abs().clamp_min(1e-300)
+    nz = want != 0
+    assert float(rel[nz].median()) < 1e-12
