@@ -12,8 +12,9 @@ Further rows (same JSON line): the two-stage path with amplitudes through
 memory and the matrix-core contraction, the colour-dressed gg -> 6g workload
 (n = 8, sampled colour flows), the adjoint d|M|^2/dp for gg -> 4g (2^18
 events), the mixed-multiplicity batch (n = 4..9) in one persistent launch
-replayed from a recorded graph, and phase space generated on the device
-ahead of the evaluation.
+replayed from a recorded graph, phase space generated on the device ahead
+of the evaluation, and events/s per gluon multiplicity n = 4..9 (FP32 and
+FP64, with the FP32 error relative to FP64).
 
 Prints one JSON line.  Only one GPU is used: --gpus above 1 exits.
 """
@@ -296,6 +297,50 @@ def section_pipeline(args, api, torch):
             "value": E / (pms * 1e-3)}
 
 
+def section_per_n(args, api, torch):
+    """Events/s per gluon multiplicity, FP32 recursion and FP64, with the
+    FP32 error relative to the FP64 evaluation of the same events.  Inputs are
+    generated on the device (RAMBO + cuts, sampled helicities; sampled colour
+    flows and the colour-dressed recursion for n >= 8)."""
+    rows = {}
+    steps = max(2, args.steps // 4)
+    for n in (4, 5, 6, 7, 8, 9):
+        E = (1 << 18) if n == 7 else args.events
+        cd = n >= 8
+        out = api.generate(n, E, 2106065070 + 20 + n, n_attempts=3 * E, sample_col=cd)
+        torch.cuda.synchronize()
+        got = int(out["n_generated"])
+        if got < E:
+            raise RuntimeError(f"device generator produced {got} < {E} events at n={n}")
+        mom, hel, col = out["mom"], out["hel"], out["col"]
+        mode = "cdbg" if cd else "cobg"
+        res, ms = {}, {}
+        for p in ("fp32", "fp64"):
+            buf = torch.empty(E, dtype=torch.float64, device="cuda")
+            log(f"timing n={n} {mode} {p}")
+            ms[p] = time_events(lambda: api.me2(mom, hel, col, mode=mode, precision=p, out=buf),
+                                steps, 1)
+            res[p] = buf.cpu().numpy()
+        h = hel.cpu().numpy()
+        keep = nonvanishing(h) & (res["fp64"] != 0.0)
+        err = rel_err_stats(res["fp32"][keep], res["fp64"][keep])
+        # against the typical size of |M|^2 at this n: cancelling helicity or
+        # colour configurations make the per-event ratio meaningless
+        typical = float(np.median(np.abs(res["fp64"][keep])))
+        err["scale_relative_max"] = float(np.max(np.abs(res["fp32"][keep] - res["fp64"][keep])) / typical)
+        rows[str(n)] = {
+            "mode": mode, "events": E,
+            "fp32": {"events_per_s": E / (ms["fp32"] * 1e-3), "ms": ms["fp32"]},
+            "fp64": {"events_per_s": E / (ms["fp64"] * 1e-3), "ms": ms["fp64"]},
+            "fp32_rel_err_vs_fp64": err,
+            "note": "per-event |d|/|fp64| on non-vanishing helicities; scale_relative_max = "
+                    "max |d| / median |fp64|",
+        }
+        if cd:
+            rows[str(n)]["valid_fraction"] = float((res["fp64"] != 0.0).mean())
+    return rows
+
+
 def cpu_baseline(args, ev):
     """The oracle on the first --cpu-sample headline events, one thread (BLAS
     pools limited to 1), in chunks of 2^15 events to bound memory."""
@@ -321,9 +366,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--events", type=int, default=1 << 20)
-    ap.add_argument("--sections", default="cdbg,adjoint,batch,pipeline",
+    ap.add_argument("--sections", default="cdbg,adjoint,batch,pipeline,per_n",
                     help="extra rows beside the headline: any of cdbg, adjoint, batch, "
-                         "pipeline, or none")
+                         "pipeline, per_n, or none")
     ap.add_argument("--cpu-sample", type=int, default=1 << 19,
                     help="events of the headline workload timed on the oracle")
     ap.add_argument("--no-cpu", action="store_true")
@@ -357,6 +402,8 @@ def main():
         extra["mixed_batch"] = section_batch(args, api, torch)
     if "pipeline" in sections:
         extra["device_phase_space_pipeline"] = section_pipeline(args, api, torch)
+    if "per_n" in sections:
+        extra["per_multiplicity"] = section_per_n(args, api, torch)
     cpu = None if args.no_cpu else cpu_baseline(args, ev)
 
     rec = {

@@ -75,10 +75,11 @@ def test_generate_matches_host(api, n, col):
     d = np.abs(m - ref["mom"]).max(axis=(0, 1)) / 1000.0
     _say(f"  |dp| / sqrt(s): median {np.median(d):.1e} max {d.max():.1e}")
     assert np.median(d) < 1e-14 and d.max() < 1e-10
-    # conservation and masslessness of the device momenta
-    assert np.max(np.abs(m.sum(axis=0))) < 1e-9
+    # conservation and masslessness of the device momenta (same rounding
+    # amplification as above)
+    assert np.max(np.abs(m.sum(axis=0))) / 1000.0 < 1e-10
     p2 = m[:, 0] ** 2 - m[:, 1] ** 2 - m[:, 2] ** 2 - m[:, 3] ** 2
-    assert np.max(np.abs(p2)) < 1e-7
+    assert np.max(np.abs(p2) / m[:, 0] ** 2) < 1e-10
 
 
 def test_generate_resume_and_short_supply(api):
