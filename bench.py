@@ -338,6 +338,16 @@ def section_per_n(args, api, torch):
         }
         if cd:
             rows[str(n)]["valid_fraction"] = float((res["fp64"] != 0.0).mean())
+        else:
+            # leading-colour mode on the same events: all (n-1)! orderings,
+            # no colour matrix; its deviation from the full colour sum
+            buf = torch.empty(E, dtype=torch.float64, device="cuda")
+            lms = time_events(lambda: api.me2(mom, hel, mode="lc", precision="fp32", out=buf),
+                              steps, 1)
+            lc = buf.cpu().numpy()
+            rows[str(n)]["leading_colour_fp32"] = {
+                "events_per_s": E / (lms * 1e-3), "ms": lms,
+                "rel_dev_from_full_colour": rel_err_stats(lc[keep], res["fp64"][keep])}
     return rows
 
 

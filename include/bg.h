@@ -60,6 +60,9 @@ extern "C" {
 #define BG_MODE_COBG 0       /* colour-ordered recursion + colour matrix */
 #define BG_MODE_CDBG 1       /* colour-dressed recursion, colours sampled (col required) */
 #define BG_MODE_AUTO 2       /* COBG for n <= 7, CDBG for n >= 8 */
+#define BG_MODE_LC   3       /* leading colour: N^(n-2)(N^2-1) sum over the (n-1)! orderings
+                                (1, rho) of |A(1, rho)|^2 (Section 3.1, exact for n <= 5),
+                                n <= 7, hel required; bg_me2 only */
 
 /* arithmetic of the recursion; contraction and |M|^2 sums are always FP64 */
 #define BG_PREC_FP64       0

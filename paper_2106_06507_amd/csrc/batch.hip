@@ -44,6 +44,25 @@ __global__ void __launch_bounds__(64) cobg_fused_queue_kernel(int64_t E,
   }
 }
 
+// Leading colour, one 32-event tile per block.
+template <int N, typename T>
+__global__ void __launch_bounds__(64) lc_kernel(int64_t E, const double* __restrict__ mom,
+                                               const int8_t* __restrict__ hel,
+                                               double* __restrict__ me2) {
+  extern __shared__ __align__(16) unsigned char bg_lc_lds[];
+  const int64_t first = (int64_t)blockIdx.x * kTileEvents;
+  const int64_t left = E - first;
+  lc_tile<N, T>(bg_lc_lds, E, mom, hel, me2, first, (int)(left < kTileEvents ? left : kTileEvents));
+}
+
+template <int N, typename T>
+int lc_launch(int64_t E, const double* mom, const int8_t* hel, double* me2, hipStream_t stream) {
+  const unsigned tiles = (unsigned)((E + kTileEvents - 1) / kTileEvents);
+  hipLaunchKernelGGL((lc_kernel<N, T>), dim3(tiles), dim3(64),
+                     (pairk::Lds<N, true>::template bytes<T>()), stream, E, mom, hel, me2);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 __global__ void zero_counter_kernel(unsigned* c) {
   if (threadIdx.x == 0) c[0] = 0u;
 }
@@ -176,6 +195,18 @@ int fused_occupancy(bool hsum) {
 }
 
 }  // namespace fusedk
+
+int lc_me2(int n, bool fp32, int64_t E, const double* mom, const int8_t* hel, double* me2,
+           hipStream_t stream) {
+  if (E <= 0) return 0;
+  switch (n) {
+    case 4: return fp32 ? fusedk::lc_launch<4, float>(E, mom, hel, me2, stream) : fusedk::lc_launch<4, double>(E, mom, hel, me2, stream);
+    case 5: return fp32 ? fusedk::lc_launch<5, float>(E, mom, hel, me2, stream) : fusedk::lc_launch<5, double>(E, mom, hel, me2, stream);
+    case 6: return fp32 ? fusedk::lc_launch<6, float>(E, mom, hel, me2, stream) : fusedk::lc_launch<6, double>(E, mom, hel, me2, stream);
+    case 7: return fp32 ? fusedk::lc_launch<7, float>(E, mom, hel, me2, stream) : fusedk::lc_launch<7, double>(E, mom, hel, me2, stream);
+    default: return -2;
+  }
+}
 
 int cobg_fused_scratch_doubles(int n) {
   switch (n) {

@@ -410,7 +410,7 @@ static int me2_cdbg(bg_context* ctx, const bg_request* r, hipStream_t stream) {
 static int validate_request(const bg_request* r) {
   if (!r) return BG_EINVAL;
   if (!valid_n(r->n)) return BG_EINVAL;
-  if (r->mode < BG_MODE_COBG || r->mode > BG_MODE_AUTO) return BG_EINVAL;
+  if (r->mode < BG_MODE_COBG || r->mode > BG_MODE_LC) return BG_EINVAL;
   if (r->precision != BG_PREC_FP64 && r->precision != BG_PREC_FP32_MIXED) return BG_EINVAL;
   if (r->reserved != 0) return BG_EINVAL;
   int st = check_events(r->n, r->n_events);
@@ -432,6 +432,12 @@ int bg_me2(bg_context* ctx, const bg_request* r, void* stream) {
   if (!g.ok) return BG_EDEVICE;
   const int mode = r->mode == BG_MODE_AUTO ? (r->n <= 7 ? BG_MODE_COBG : BG_MODE_CDBG) : r->mode;
   if (mode == BG_MODE_COBG) return me2_cobg(ctx, r, (hipStream_t)stream);
+  if (mode == BG_MODE_LC) {
+    if (r->n > 7) return BG_EUNSUPPORTED;
+    if (!r->hel) return BG_EINVAL;
+    return launch_status(bg::lc_me2(r->n, r->precision == BG_PREC_FP32_MIXED, r->n_events, r->mom,
+                                    r->hel, r->me2, (hipStream_t)stream));
+  }
   return me2_cdbg(ctx, r, (hipStream_t)stream);
 }
 
@@ -514,6 +520,7 @@ int validate_batch(bg_context* ctx, const bg_request* segs, int n_segs) {
     if (r->n_events == 0) continue;
     if (!r->me2 || !r->hel) return BG_EINVAL;
     const int mode = resolved_mode(r);
+    if (mode == BG_MODE_LC) return BG_EUNSUPPORTED;
     if (mode == BG_MODE_COBG && r->n > 7) return BG_EUNSUPPORTED;
     const bool fp32 = r->precision == BG_PREC_FP32_MIXED;
     const size_t lds = bg::batch_lds_bytes(mode == BG_MODE_COBG ? bg::kBatchCobg : bg::kBatchCdbg,

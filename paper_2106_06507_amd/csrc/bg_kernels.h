@@ -64,6 +64,9 @@ int cobg_fused_me2(int n, bool fp32, int64_t E, const double* mom, const int8_t*
                    const double* Cb, double* scratch, unsigned* counter, int grid, double* me2,
                    hipStream_t stream);
 int cobg_fused_scratch_doubles(int n);
+// Leading-colour |M|^2 over all (n-1)! orderings, one helicity per event.
+int lc_me2(int n, bool fp32, int64_t E, const double* mom, const int8_t* hel, double* me2,
+           hipStream_t stream);
 int cobg_fused_persistent_blocks_per_cu(bool fp32, bool hsum);
 // LDS of a colour-ordered tile (recursion state plus staged amplitudes).
 size_t cobg_lds_bytes(int n, bool fp32);

@@ -43,34 +43,41 @@
 namespace bg {
 namespace pairk {
 
-// LDS map per 64-lane block (32 events):
-//   T region, [slot][lane]: gluon g in 1..N-2 has eps half (4) and p half (2)
+// LDS map per 64-lane block (32 events), NG movable gluons (1..NG):
+//   T region, [slot][lane]: gluon g in 1..NG has eps half (4) and p half (2)
 //     at slots 6 (g-1) .. 6 (g-1) + 5;
-//   T region, [mask][pair]: 1/P_S^2 for subsets S of gluons 0..N-2;
-//   double region, [2 (g-1) + c][lane]: FP64 momentum halves of gluons 1..N-2.
+//   T region, [mask][pair]: 1/P_S^2 for subsets S of gluons 0..NG;
+//   double region, [2 (g-1) + c][lane]: FP64 momentum halves of gluons 1..NG.
+// Adjoint basis (LC = false): NG = N-2, gluon N-1 closes every ordering.
+// Leading colour (LC = true): NG = N-1, all orderings (1, rho) of gluons
+// 1..N-1; the gluon left after the others are placed closes the ordering.
 // P64G: the FP64 momentum halves are re-read from global memory (L1/L2
-// hits) instead of being kept in LDS, which saves 2 (N-2) x 64 doubles where
+// hits) instead of being kept in LDS, which saves 2 NG x 64 doubles where
 // LDS is the occupancy limit.
-template <int N>
+template <int N, bool LC = false>
 struct Lds {
   static constexpr int kLanes = 64;
   static constexpr int kPairs = 32;
-  static constexpr int kGluonSlots = 6 * (N - 2);
-  static constexpr int kTabEntries = 1 << (N - 1);
+  static constexpr int NG = LC ? N - 1 : N - 2;
+  static constexpr int kGluonSlots = 6 * NG;
+  static constexpr int kTabEntries = 1 << (NG + 1);
   template <typename T, bool P64G = false>
   static constexpr size_t bytes() {
     return sizeof(T) * ((size_t)kGluonSlots * kLanes + (size_t)kTabEntries * kPairs) +
-           (P64G ? 0 : sizeof(double) * (size_t)(2 * (N - 2)) * kLanes);
+           (P64G ? 0 : sizeof(double) * (size_t)(2 * NG) * kLanes);
   }
 };
 
 // RAW: amplitudes go unscaled, in T, to amp_raw[(h K + sigma) 32 + pair]
 // (block-private LDS); otherwise scaled, in FP64, to
-// amp[(h K + sigma) astride + acol].  P64G: see Lds.
-template <int N, typename T, bool RAW, bool P64G>
+// amp[(h K + sigma) astride + acol].  P64G, LC: see Lds; with LC nothing is
+// stored, lcsum accumulates this lane's plane of |A|^2 over the orderings.
+template <int N, typename T, bool RAW, bool P64G, bool LC = false>
 struct Ctx {
   static constexpr bool kRaw = RAW;
   static constexpr bool kP64G = P64G;
+  static constexpr bool kLC = LC;
+  double lcsum;
   const double* mom;
   T* gl_slots;      // [slot][lane]
   T* tab;           // [mask][pair]
@@ -194,7 +201,8 @@ __device__ __forceinline__ void build_column(State<N, T>& s, const CtxT& c, int 
 template <int N, typename T, int D, class CtxT>
 __device__ __forceinline__ void level(State<N, T>& s, CtxT& c, int used) {
   constexpr int M = N - 1;
-  for (int g = 1; g <= N - 2; ++g) {  // wave-uniform
+  constexpr int NG = CtxT::kLC ? N - 1 : N - 2;
+  for (int g = 1; g <= NG; ++g) {  // wave-uniform
     if (used & (1 << g)) continue;
     s.gl[D] = g;
     const int base = 6 * (g - 1);
@@ -211,10 +219,24 @@ __device__ __forceinline__ void level(State<N, T>& s, CtxT& c, int used) {
       s.P0[D].v[m] = s.P0[D - 1].v[m] + pg;
     }
     Cx<T> top;
+    if constexpr (CtxT::kLC && D == M - 1) {
+      // the one gluon not yet placed closes the ordering
+      const int all = ((1 << (NG + 1)) - 1) & ~1;
+      const int rem = __builtin_ctz(all & ~(used | (1 << g)));
+      const int rb = 6 * (rem - 1);
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        c.epsN.re[m] = c.gl_slots[(rb + m) * Lds<N>::kLanes + c.lane];
+        c.epsN.im[m] = c.gl_slots[(rb + 2 + m) * Lds<N>::kLanes + c.lane];
+      }
+    }
     build_column<N, T, D, D - 1>(s, c, 1 << g, top);
     if constexpr (D == M - 1) {
       constexpr int64_t K = Factorial<N - 2>::value;
-      if constexpr (CtxT::kRaw) {
+      if constexpr (CtxT::kLC) {
+        const double v = (double)(c.h == 0 ? top.re : top.im);
+        c.lcsum += v * v;
+      } else if constexpr (CtxT::kRaw) {
         c.amp_raw[(c.h * (int)K + c.sigma) * Lds<N>::kPairs + c.pair] = c.h == 0 ? top.re : top.im;
       } else {
         double scale = 1.0;
@@ -235,8 +257,8 @@ __device__ __forceinline__ void level(State<N, T>& s, CtxT& c, int used) {
 // block's waves must all call it (it synchronises the block); lds is this
 // wave's region of Lds<N>::bytes<T>().  RAW: the
 // unscaled amplitudes go to amp_raw (see Ctx), amp is unused.
-template <int N, typename T, bool RAW = false, bool P64G = false>
-__device__ __forceinline__ void cobg_pair_body(unsigned char* lds, int64_t E,
+template <int N, typename T, bool RAW = false, bool P64G = false, bool LC = false>
+__device__ __forceinline__ double cobg_pair_body(unsigned char* lds, int64_t E,
                                                const double* __restrict__ mom,
                                                const int8_t* __restrict__ hel, int hconf,
                                                int64_t e, bool live, double* __restrict__ amp,
@@ -246,11 +268,13 @@ __device__ __forceinline__ void cobg_pair_body(unsigned char* lds, int64_t E,
   const int lane = threadIdx.x & 63;  // lane within this wave (the wave owns lds)
   const int pair = lane >> 1;
   const int h = lane & 1;
-  Ctx<N, T, RAW, P64G> c;
+  using L = Lds<N, LC>;
+  Ctx<N, T, RAW, P64G, LC> c;
+  c.lcsum = 0.0;
   c.mom = mom;
   c.gl_slots = reinterpret_cast<T*>(lds);
-  c.tab = c.gl_slots + (size_t)Lds<N>::kGluonSlots * Lds<N>::kLanes;
-  c.p64 = reinterpret_cast<double*>(c.tab + (size_t)Lds<N>::kTabEntries * Lds<N>::kPairs);
+  c.tab = c.gl_slots + (size_t)L::kGluonSlots * L::kLanes;
+  c.p64 = reinterpret_cast<double*>(c.tab + (size_t)L::kTabEntries * L::kPairs);
   c.lane = lane;
   c.pair = pair;
   c.h = h;
@@ -293,7 +317,7 @@ __device__ __forceinline__ void cobg_pair_body(unsigned char* lds, int64_t E,
         s.Pg[0].v[m] = (T)ph[m];
         s.P0[0].v[m] = ph[m];
       }
-    } else if (i == N - 1) {
+    } else if (i == N - 1 && !LC) {
       c.epsN = cur;
     } else {
       const int base = 6 * (i - 1);
@@ -307,10 +331,11 @@ __device__ __forceinline__ void cobg_pair_body(unsigned char* lds, int64_t E,
     }
   }
   // 1/P_S^2 table: the two lanes of a pair fill alternate subsets
-  for (int mask = h; mask < (1 << M); mask += 2) {
+  constexpr int MT = L::NG + 1;  // gluons that can appear in a range
+  for (int mask = h; mask < (1 << MT); mask += 2) {
     double q[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int i = 0; i < M; ++i) {
+    for (int i = 0; i < MT; ++i) {
       if (mask & (1 << i)) {
 #pragma unroll
         for (int m = 0; m < 4; ++m) q[m] += p[i][m];
@@ -322,6 +347,7 @@ __device__ __forceinline__ void cobg_pair_body(unsigned char* lds, int64_t E,
   __syncthreads();
   s.gl[0] = 0;
   level<N, T, 1>(s, c, 1);
+  return c.lcsum;
 }
 
 template <int N, typename T>

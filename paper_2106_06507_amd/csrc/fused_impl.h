@@ -137,6 +137,33 @@ __device__ __forceinline__ void cobg_tile(unsigned char* lds, int64_t E,
   if (live && h == 0) me2[e] = tot;
 }
 
+// Leading-colour |M|^2 (Section 3.1): N^(n-2) (N^2 - 1) sum over all (n-1)!
+// orderings (1, rho) of |A(1, rho)|^2, N = 3, for events [first, first +
+// count) (count <= 32), one helicity configuration per event.  lds holds
+// pairk::Lds<N, true>::bytes<T>().
+template <int N, typename T>
+__device__ __forceinline__ void lc_tile(unsigned char* lds, int64_t E,
+                                        const double* __restrict__ mom,
+                                        const int8_t* __restrict__ hel, double* __restrict__ me2,
+                                        int64_t first, int count) {
+  const int lane = threadIdx.x & 63;
+  const int pair = lane >> 1;
+  const int h = lane & 1;
+  const bool live = pair < count;
+  const int64_t e = first + (live ? pair : (count > 0 ? count - 1 : 0));
+  const double q = pairk::cobg_pair_body<N, T, false, false, true>(lds, E, mom, hel, 0, e, false,
+                                                                    nullptr, 0, 0);
+  __syncthreads();
+  double scale = 1.0;  // (g_s / sqrt2)^(n-2) per amplitude, squared
+#pragma unroll
+  for (int i = 0; i < N - 2; ++i) scale *= kGsOverSqrt2;
+  double colour = 8.0;  // N^(n-2) (N^2 - 1)
+#pragma unroll
+  for (int i = 0; i < N - 2; ++i) colour *= 3.0;
+  const double tot = pairk::pair_sum(q) * scale * scale * colour;
+  if (live && h == 0) me2[e] = tot;
+}
+
 // Colour-dressed |A|^2 of events [first, first + count), count <= NL, on
 // the NL lanes of the block: one lane classifies each event (invalid flows
 // get exactly 0), then the valid ones are evaluated in order by all lanes.
