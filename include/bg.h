@@ -63,6 +63,10 @@ extern "C" {
 #define BG_MODE_LC   3       /* leading colour: N^(n-2)(N^2-1) sum over the (n-1)! orderings
                                 (1, rho) of |A(1, rho)|^2 (Section 3.1, exact for n <= 5),
                                 n <= 7, hel required; bg_me2 only */
+#define BG_MODE_COMC 4       /* colour-sampled colour-ordered: the same |A|^2 as CDBG for the
+                                given colour flow, as the sum of A(1, sigma) over the orderings
+                                whose delta chain closes (Section 2.2); col and hel required;
+                                bg_me2 only; synchronises the stream once (item count) */
 
 /* arithmetic of the recursion; contraction and |M|^2 sums are always FP64 */
 #define BG_PREC_FP64       0

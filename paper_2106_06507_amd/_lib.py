@@ -19,7 +19,7 @@ BG_EDEVICE = -4
 BG_ENOMEM = -5
 BG_EUNSUPPORTED = -6
 
-MODE_COBG, MODE_CDBG, MODE_AUTO, MODE_LC = 0, 1, 2, 3
+MODE_COBG, MODE_CDBG, MODE_AUTO, MODE_LC, MODE_COMC = 0, 1, 2, 3, 4
 PREC_FP64, PREC_FP32_MIXED = 0, 1
 
 

@@ -15,7 +15,7 @@ from ._lib import bg_batch_config, bg_gen_params, bg_request, check, lib
 
 _PREC = {"fp64": _lib.PREC_FP64, "fp32": _lib.PREC_FP32_MIXED, "mixed": _lib.PREC_FP32_MIXED}
 _MODE = {"cobg": _lib.MODE_COBG, "cdbg": _lib.MODE_CDBG, "auto": _lib.MODE_AUTO,
-         "lc": _lib.MODE_LC}
+         "lc": _lib.MODE_LC, "comc": _lib.MODE_COMC}
 
 
 class Context:

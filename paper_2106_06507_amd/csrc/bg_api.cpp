@@ -51,6 +51,12 @@ struct bg_context {
   unsigned* counter = nullptr;               // tile-queue heads: [0] batch, [1] fused n = 7
   unsigned* gen_ws = nullptr;                // phase-space generator: acceptance bits, counts
   size_t gen_ws_words = 0;
+  uint64_t* comc_ws = nullptr;               // colour-sampled COBG: block offsets, counts, offsets
+  size_t comc_ws_words = 0;
+  uint64_t* comc_items = nullptr;            // (event, ordering) items
+  double* comc_amp = nullptr;                // their amplitudes
+  size_t comc_cap = 0;
+  int occ_comc[BG_N_MAX + 1][2] = {};
   bg_batch_config bcfg[2] = {{0, 128, 256, 2}, {0, 128, 256, 2}};
   std::vector<BatchPlan> plans;
   uint64_t clock = 0;
@@ -319,6 +325,9 @@ void bg_context_destroy(bg_context* ctx) {
   if (ctx->scratch) (void)hipFree(ctx->scratch);
   for (void* p : ctx->retired) (void)hipFree(p);
   if (ctx->gen_ws) (void)hipFree(ctx->gen_ws);
+  if (ctx->comc_ws) (void)hipFree(ctx->comc_ws);
+  if (ctx->comc_items) (void)hipFree(ctx->comc_items);
+  if (ctx->comc_amp) (void)hipFree(ctx->comc_amp);
   if (ctx->counter) (void)hipFree(ctx->counter);
   for (BatchPlan& pl : ctx->plans)
     if (pl.tiles) (void)hipFree(pl.tiles);
@@ -407,10 +416,69 @@ static int me2_cdbg(bg_context* ctx, const bg_request* r, hipStream_t stream) {
                                     (int)grid, stream));
 }
 
+static int me2_comc(bg_context* ctx, const bg_request* r, hipStream_t stream) {
+  const int n = r->n;
+  const int64_t E = r->n_events;
+  if (E > 0x7fffffffLL) return BG_ERANGE;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive)
+    return BG_EINVAL;  // needs a synchronisation
+  // workspace in 8-byte words: block offsets [nb + 1], then counts and
+  // offsets [E] each as 32-bit words
+  const int64_t nb = (E + 255) / 256;
+  const size_t words = (size_t)(nb + 1 + E);
+  int st;
+  if (ctx->comc_ws_words < words) {
+    st = hip_status(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    if (st) return st;
+    if (ctx->comc_ws) (void)hipFree(ctx->comc_ws);
+    ctx->comc_ws = nullptr;
+    ctx->comc_ws_words = 0;
+    st = hip_status(hipMalloc(&ctx->comc_ws, sizeof(uint64_t) * words), "hipMalloc(comc)");
+    if (st) return st;
+    ctx->comc_ws_words = words;
+  }
+  uint64_t* blocks = ctx->comc_ws;
+  unsigned* counts = reinterpret_cast<unsigned*>(blocks + nb + 1);
+  unsigned* offsets = counts + E;
+  st = launch_status(bg::comc_count(n, E, r->col, r->me2, counts, blocks, stream));
+  if (st) return st;
+  uint64_t total = 0;
+  st = hip_status(hipMemcpyAsync(&total, blocks + nb, sizeof(uint64_t), hipMemcpyDeviceToHost,
+                                 stream), "hipMemcpyAsync(comc total)");
+  if (!st) st = hip_status(hipStreamSynchronize(stream), "hipStreamSynchronize");
+  if (st) return st;
+  if (total == 0) return BG_OK;
+  if (total >= (1ull << 31)) return BG_ERANGE;  // too many (event, ordering) items: split the call
+  if (ctx->comc_cap < total) {
+    st = hip_status(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    if (st) return st;
+    const size_t cap = std::max<size_t>((size_t)total, 2 * ctx->comc_cap);
+    if (ctx->comc_items) (void)hipFree(ctx->comc_items);
+    if (ctx->comc_amp) (void)hipFree(ctx->comc_amp);
+    ctx->comc_items = nullptr;
+    ctx->comc_amp = nullptr;
+    ctx->comc_cap = 0;
+    st = hip_status(hipMalloc(&ctx->comc_items, sizeof(uint64_t) * cap), "hipMalloc(comc items)");
+    if (!st) st = hip_status(hipMalloc(&ctx->comc_amp, 2 * sizeof(double) * cap), "hipMalloc(comc amp)");
+    if (st) return st;
+    ctx->comc_cap = cap;
+  }
+  st = launch_status(bg::comc_items(n, E, r->col, counts, blocks, offsets, ctx->comc_items, stream));
+  if (st) return st;
+  const bool fp32 = r->precision == BG_PREC_FP32_MIXED;
+  const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((total + 31) / 32,
+                                                                 (uint64_t)ctx->num_cus * 8));
+  st = launch_status(bg::comc_amplitudes(n, fp32, E, r->mom, r->hel, ctx->comc_items, blocks + nb,
+                                         ctx->comc_amp, grid, stream));
+  if (st) return st;
+  return launch_status(bg::comc_reduce(E, counts, offsets, ctx->comc_amp, r->me2, stream));
+}
+
 static int validate_request(const bg_request* r) {
   if (!r) return BG_EINVAL;
   if (!valid_n(r->n)) return BG_EINVAL;
-  if (r->mode < BG_MODE_COBG || r->mode > BG_MODE_LC) return BG_EINVAL;
+  if (r->mode < BG_MODE_COBG || r->mode > BG_MODE_COMC) return BG_EINVAL;
   if (r->precision != BG_PREC_FP64 && r->precision != BG_PREC_FP32_MIXED) return BG_EINVAL;
   if (r->reserved != 0) return BG_EINVAL;
   int st = check_events(r->n, r->n_events);
@@ -418,7 +486,7 @@ static int validate_request(const bg_request* r) {
   if (r->n_events == 0) return BG_OK;
   if (!r->mom) return BG_EINVAL;
   const int mode = r->mode == BG_MODE_AUTO ? (r->n <= 7 ? BG_MODE_COBG : BG_MODE_CDBG) : r->mode;
-  if (mode == BG_MODE_CDBG && (!r->col || !r->hel)) return BG_EINVAL;
+  if ((mode == BG_MODE_CDBG || mode == BG_MODE_COMC) && (!r->col || !r->hel)) return BG_EINVAL;
   return BG_OK;
 }
 
@@ -432,6 +500,7 @@ int bg_me2(bg_context* ctx, const bg_request* r, void* stream) {
   if (!g.ok) return BG_EDEVICE;
   const int mode = r->mode == BG_MODE_AUTO ? (r->n <= 7 ? BG_MODE_COBG : BG_MODE_CDBG) : r->mode;
   if (mode == BG_MODE_COBG) return me2_cobg(ctx, r, (hipStream_t)stream);
+  if (mode == BG_MODE_COMC) return me2_comc(ctx, r, (hipStream_t)stream);
   if (mode == BG_MODE_LC) {
     if (r->n > 7) return BG_EUNSUPPORTED;
     if (!r->hel) return BG_EINVAL;
@@ -520,7 +589,7 @@ int validate_batch(bg_context* ctx, const bg_request* segs, int n_segs) {
     if (r->n_events == 0) continue;
     if (!r->me2 || !r->hel) return BG_EINVAL;
     const int mode = resolved_mode(r);
-    if (mode == BG_MODE_LC) return BG_EUNSUPPORTED;
+    if (mode == BG_MODE_LC || mode == BG_MODE_COMC) return BG_EUNSUPPORTED;
     if (mode == BG_MODE_COBG && r->n > 7) return BG_EUNSUPPORTED;
     const bool fp32 = r->precision == BG_PREC_FP32_MIXED;
     const size_t lds = bg::batch_lds_bytes(mode == BG_MODE_COBG ? bg::kBatchCobg : bg::kBatchCdbg,

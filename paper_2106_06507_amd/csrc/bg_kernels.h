@@ -112,6 +112,20 @@ int batch_launch(bool fp32, int waves, const BatchSegTable& segs, const BatchTil
                  unsigned n_tiles, unsigned* counter, double* scratch, int64_t scratch_stride,
                  int grid, size_t lds, hipStream_t stream);
 
+// Colour-sampled colour-ordered |A|^2 (comc.hip).  count: counts [E],
+// blocks [ceil(E/256) + 1] (exclusive offsets, total last; the total must be
+// below 2^31 before items runs); items: offsets [E], items [total];
+// amplitudes: amp [2 total] (persistent grid); reduce.
+int comc_count(int n, int64_t E, const int8_t* col, double* me2, unsigned* counts,
+               uint64_t* blocks, hipStream_t stream);
+int comc_items(int n, int64_t E, const int8_t* col, const unsigned* counts, const uint64_t* blocks,
+               unsigned* offsets, uint64_t* items, hipStream_t stream);
+int comc_amplitudes(int n, bool fp32, int64_t E, const double* mom, const int8_t* hel,
+                    const uint64_t* items, const uint64_t* total, double* amp, int grid,
+                    hipStream_t stream);
+int comc_reduce(int64_t E, const unsigned* counts, const unsigned* offsets, const double* amp,
+                double* me2, hipStream_t stream);
+
 // On-device phase-space generation (rambo.hip).
 struct GenParams {
   int n;

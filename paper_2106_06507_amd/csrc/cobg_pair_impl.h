@@ -77,6 +77,8 @@ struct Ctx {
   static constexpr bool kRaw = RAW;
   static constexpr bool kP64G = P64G;
   static constexpr bool kLC = LC;
+  static constexpr bool kDirectP2 = false;  // 1/P^2 from the per-event table
+  static constexpr bool kNoDt = false;      // V4 dot products from the Dt table
   double lcsum;
   const double* mom;
   T* gl_slots;      // [slot][lane]
@@ -141,7 +143,7 @@ __device__ __forceinline__ void build_range(State<N, T>& s, const CtxT& c, int m
           const HR<T> PL = range_mom<N, T, A, k>(s);
           const HR<T> PR = range_mom<N, T, k + 1, D>(s);
           const Cx<T> d = hdot(s.J[A][k], s.J[k + 1][D], c.g0);
-          if constexpr (!kTop) s.Dt[A][D][k] = d;
+          if constexpr (!kTop && !CtxT::kNoDt) s.Dt[A][D][k] = d;
           HR<T> q2p, p2q, dif;
 #pragma unroll
           for (int m = 0; m < 2; ++m) {
@@ -161,8 +163,14 @@ __device__ __forceinline__ void build_range(State<N, T>& s, const CtxT& c, int m
   for (int j = A; j < D; ++j) {
 #pragma unroll
     for (int k = j + 1; k < D; ++k) {
-      const Cx<T> xy = s.Dt[A][k][j];
-      const Cx<T> yz = s.Dt[j + 1][D][k];
+      Cx<T> xy, yz;
+      if constexpr (CtxT::kNoDt) {
+        xy = hdot(s.J[A][j], s.J[j + 1][k], c.g0);
+        yz = hdot(s.J[j + 1][k], s.J[k + 1][D], c.g0);
+      } else {
+        xy = s.Dt[A][k][j];
+        yz = s.Dt[j + 1][D][k];
+      }
       const Cx<T> xz = hdot(s.J[A][j], s.J[k + 1][D], c.g0);
       coefL[j - A].re -= yz.re;
       coefL[j - A].im -= yz.im;
@@ -179,7 +187,18 @@ __device__ __forceinline__ void build_range(State<N, T>& s, const CtxT& c, int m
   if constexpr (kTop) {
     top = hdot(c.epsN, acc, c.g0);
   } else {
-    const T ip2 = c.tab[mask * Lds<N>::kPairs + c.pair];
+    T ip2;
+    if constexpr (CtxT::kDirectP2) {
+      // P(A..D)^2 from the FP64 prefix momenta (halves + partner exchange)
+      double pv[2];
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+        pv[m] = A == 0 ? s.P0[D].v[m] : s.P0[D].v[m] - s.P0[A - 1].v[m];
+      const double part = (double)c.g0 * pv[0] * pv[0] - pv[1] * pv[1];
+      ip2 = (T)(1.0 / pair_sum(part));
+    } else {
+      ip2 = c.tab[mask * Lds<N>::kPairs + c.pair];
+    }
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       s.J[A][D].re[m] = acc.re[m] * ip2;
