@@ -14,7 +14,8 @@ memory and the matrix-core contraction, the colour-dressed gg -> 6g workload
 events), the mixed-multiplicity batch (n = 4..9) in one persistent launch
 replayed from a recorded graph, phase space generated on the device ahead
 of the evaluation, and events/s per gluon multiplicity n = 4..9 (FP32 and
-FP64, with the FP32 error relative to FP64).
+FP64, with the FP32 error relative to FP64, and the colour-sampled
+colour-ordered and leading-colour modes on the same events).
 
 Prints one JSON line.  Only one GPU is used: --gpus above 1 exits.
 """
@@ -307,7 +308,7 @@ def section_per_n(args, api, torch):
     for n in (4, 5, 6, 7, 8, 9):
         E = (1 << 18) if n == 7 else args.events
         cd = n >= 8
-        out = api.generate(n, E, 2106065070 + 20 + n, n_attempts=3 * E, sample_col=cd)
+        out = api.generate(n, E, 2106065070 + 20 + n, n_attempts=3 * E, sample_col=True)
         torch.cuda.synchronize()
         got = int(out["n_generated"])
         if got < E:
@@ -336,9 +337,28 @@ def section_per_n(args, api, torch):
             "note": "per-event |d|/|fp64| on non-vanishing helicities; scale_relative_max = "
                     "max |d| / median |fp64|",
         }
-        if cd:
-            rows[str(n)]["valid_fraction"] = float((res["fp64"] != 0.0).mean())
-        else:
+        # colour-sampled colour-ordered mode on the same sampled colour flows:
+        # the orderings whose colour chain closes, each by the colour-ordered
+        # recursion; deviation from the dressed recursion in FP64
+        dres = res["fp64"] if cd else None
+        if dres is None:
+            buf = torch.empty(E, dtype=torch.float64, device="cuda")
+            api.me2(mom, hel, col, mode="cdbg", precision="fp64", out=buf)
+            dres = buf.cpu().numpy()
+        co = {}
+        for p in ("fp32", "fp64"):
+            buf = torch.empty(E, dtype=torch.float64, device="cuda")
+            log(f"timing n={n} comc {p}")
+            cms = time_events(lambda: api.me2(mom, hel, col, mode="comc", precision=p, out=buf),
+                              steps, 1)
+            got_c = buf.cpu().numpy()
+            ck = nonvanishing(h) & (dres != 0.0)
+            ck &= np.abs(dres) > 1e-8 * np.median(np.abs(dres[ck]))
+            co[p] = {"events_per_s": E / (cms * 1e-3), "ms": cms,
+                     "rel_dev_from_dressed_fp64": rel_err_stats(got_c[ck], dres[ck])}
+        rows[str(n)]["colour_sampled_ordered"] = co
+        rows[str(n)]["valid_fraction"] = float((dres != 0.0).mean())
+        if not cd:
             # leading-colour mode on the same events: all (n-1)! orderings,
             # no colour matrix; its deviation from the full colour sum
             buf = torch.empty(E, dtype=torch.float64, device="cuda")
