@@ -423,10 +423,11 @@ static int me2_comc(bg_context* ctx, const bg_request* r, hipStream_t stream) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive)
     return BG_EINVAL;  // needs a synchronisation
-  // workspace in 8-byte words: block offsets [nb + 1], then counts and
-  // offsets [E] each as 32-bit words
+  // workspace in 8-byte words: block item and valid-event offsets [nb + 1]
+  // each, then counts, offsets and the valid-event list [E] each as 32-bit
+  // words
   const int64_t nb = (E + 255) / 256;
-  const size_t words = (size_t)(nb + 1 + E);
+  const size_t words = (size_t)(2 * (nb + 1) + (3 * E + 1) / 2);
   int st;
   if (ctx->comc_ws_words < words) {
     st = hip_status(hipDeviceSynchronize(), "hipDeviceSynchronize");
@@ -438,22 +439,29 @@ static int me2_comc(bg_context* ctx, const bg_request* r, hipStream_t stream) {
     if (st) return st;
     ctx->comc_ws_words = words;
   }
-  uint64_t* blocks = ctx->comc_ws;
-  unsigned* counts = reinterpret_cast<unsigned*>(blocks + nb + 1);
+  uint64_t* block_items = ctx->comc_ws;
+  uint64_t* block_valid = block_items + nb + 1;
+  unsigned* counts = reinterpret_cast<unsigned*>(block_valid + nb + 1);
   unsigned* offsets = counts + E;
-  st = launch_status(bg::comc_count(n, E, r->col, r->me2, counts, blocks, stream));
+  unsigned* valid = offsets + E;
+  st = launch_status(bg::comc_count(n, E, r->col, r->me2, counts, offsets, valid, block_items,
+                                    block_valid, stream));
   if (st) return st;
-  uint64_t total = 0;
-  st = hip_status(hipMemcpyAsync(&total, blocks + nb, sizeof(uint64_t), hipMemcpyDeviceToHost,
-                                 stream), "hipMemcpyAsync(comc total)");
+  uint64_t total[2] = {0, 0};
+  st = hip_status(hipMemcpyAsync(&total[0], block_items + nb, sizeof(uint64_t),
+                                 hipMemcpyDeviceToHost, stream), "hipMemcpyAsync(comc total)");
+  if (!st)
+    st = hip_status(hipMemcpyAsync(&total[1], block_valid + nb, sizeof(uint64_t),
+                                   hipMemcpyDeviceToHost, stream), "hipMemcpyAsync(comc valid)");
   if (!st) st = hip_status(hipStreamSynchronize(stream), "hipStreamSynchronize");
   if (st) return st;
-  if (total == 0) return BG_OK;
-  if (total >= (1ull << 31)) return BG_ERANGE;  // too many (event, ordering) items: split the call
-  if (ctx->comc_cap < total) {
+  const uint64_t n_items = total[0], n_valid = total[1];
+  if (n_items == 0) return BG_OK;
+  if (n_items >= (1ull << 31) || n_valid > (uint64_t)E) return BG_ERANGE;  // split the call
+  if (ctx->comc_cap < n_items) {
     st = hip_status(hipDeviceSynchronize(), "hipDeviceSynchronize");
     if (st) return st;
-    const size_t cap = std::max<size_t>((size_t)total, 2 * ctx->comc_cap);
+    const size_t cap = std::max<size_t>((size_t)n_items, 2 * ctx->comc_cap);
     if (ctx->comc_items) (void)hipFree(ctx->comc_items);
     if (ctx->comc_amp) (void)hipFree(ctx->comc_amp);
     ctx->comc_items = nullptr;
@@ -464,13 +472,14 @@ static int me2_comc(bg_context* ctx, const bg_request* r, hipStream_t stream) {
     if (st) return st;
     ctx->comc_cap = cap;
   }
-  st = launch_status(bg::comc_items(n, E, r->col, counts, blocks, offsets, ctx->comc_items, stream));
+  st = launch_status(bg::comc_items(n, E, r->col, valid, (unsigned)n_valid, counts, offsets,
+                                    ctx->comc_items, stream));
   if (st) return st;
   const bool fp32 = r->precision == BG_PREC_FP32_MIXED;
-  const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((total + 31) / 32,
+  const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((n_items + 31) / 32,
                                                                  (uint64_t)ctx->num_cus * 8));
-  st = launch_status(bg::comc_amplitudes(n, fp32, E, r->mom, r->hel, ctx->comc_items, blocks + nb,
-                                         ctx->comc_amp, grid, stream));
+  st = launch_status(bg::comc_amplitudes(n, fp32, E, r->mom, r->hel, ctx->comc_items,
+                                         block_items + nb, ctx->comc_amp, grid, stream));
   if (st) return st;
   return launch_status(bg::comc_reduce(E, counts, offsets, ctx->comc_amp, r->me2, stream));
 }

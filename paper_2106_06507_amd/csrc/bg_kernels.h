@@ -112,14 +112,17 @@ int batch_launch(bool fp32, int waves, const BatchSegTable& segs, const BatchTil
                  unsigned n_tiles, unsigned* counter, double* scratch, int64_t scratch_stride,
                  int grid, size_t lds, hipStream_t stream);
 
-// Colour-sampled colour-ordered |A|^2 (comc.hip).  count: counts [E],
-// blocks [ceil(E/256) + 1] (exclusive offsets, total last; the total must be
-// below 2^31 before items runs); items: offsets [E], items [total];
-// amplitudes: amp [2 total] (persistent grid); reduce.
+// Colour-sampled colour-ordered |A|^2 (comc.hip).  count: counts, offsets
+// and the valid-event list [E] each, block_items and block_valid
+// [ceil(E/256) + 1] (exclusive offsets, totals last; the item total must be
+// below 2^31 before items runs); items: items [total] for the n_valid
+// listed events; amplitudes: amp [2 total] (persistent grid); reduce.
 int comc_count(int n, int64_t E, const int8_t* col, double* me2, unsigned* counts,
-               uint64_t* blocks, hipStream_t stream);
-int comc_items(int n, int64_t E, const int8_t* col, const unsigned* counts, const uint64_t* blocks,
-               unsigned* offsets, uint64_t* items, hipStream_t stream);
+               unsigned* offsets, unsigned* valid, uint64_t* block_items, uint64_t* block_valid,
+               hipStream_t stream);
+int comc_items(int n, int64_t E, const int8_t* col, const unsigned* valid, unsigned n_valid,
+               const unsigned* counts, const unsigned* offsets, uint64_t* items,
+               hipStream_t stream);
 int comc_amplitudes(int n, bool fp32, int64_t E, const double* mom, const int8_t* hel,
                     const uint64_t* items, const uint64_t* total, double* amp, int grid,
                     hipStream_t stream);

@@ -7,15 +7,23 @@
 // only the closing orderings (the Euler circuits of the colour edges that
 // start with gluon 1) are evaluated.
 //
-// Passes: (1) one thread per event classifies the flow and counts its closing
-// orderings (depth-first over the colour chain; invalid flows get exactly 0),
-// (2) one block scans the per-block counts, (3) one thread per event writes
-// its (event, ordering) items at their ranks, (4) one lane pair per item
+// Passes: (1) one thread per event counts its closing orderings without
+// enumerating them: they are the Euler circuits of the colour multigraph
+// (edge j_k -> i_k per gluon) that start with gluon 1's edge, whose number
+// for distinguishable edges is, by the BEST theorem, the number of spanning
+// arborescences towards any vertex (a 2x2 or 1x1 Laplacian minor over the
+// three colours) times the product over vertices of (out-degree - 1)!;
+// unbalanced or disconnected flows get 0 and exactly 0 for |A|^2.
+// (2) one block scans the per-block item and valid-event counts.  (3) one
+// thread per event writes its first item index and lists the valid events.
+// (4) one thread per valid event enumerates its closing orderings
+// depth-first (candidate gluons from per-colour bit masks) and writes its
+// (event, ordering) items at their ranks.  (5) one lane pair per item
 // evaluates A(1, sigma) with the lane-pair recursion of cobg_pair_impl.h on
 // that single ordering (gluons of the ordering differ between pairs; 1/P^2
-// from the FP64 prefix momenta), (5) one thread per event adds its items'
-// amplitudes in order and writes |A|^2.  The item count is read back once
-// (a synchronisation) to size the item arrays.
+// from the FP64 prefix momenta).  (6) one thread per event adds its items'
+// amplitudes in order and writes |A|^2.  The totals are read back once (a
+// synchronisation) to size the item arrays and the enumeration grid.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -30,40 +38,162 @@ using pairk::H;
 using pairk::HR;
 
 constexpr int kThreads = 256;
+constexpr int kWave = 64;
 
-// colours packed two bits per gluon
+// colours packed two bits per gluon; jm[c] = gluons 1..N-1 whose j is c
 template <int N>
 struct Flow {
   int ci, cj;
-  __device__ __forceinline__ int i(int g) const { return (ci >> (2 * g)) & 3; }
-  __device__ __forceinline__ int j(int g) const { return (cj >> (2 * g)) & 3; }
+  unsigned jm[3];
+  __host__ __device__ __forceinline__ int i(int g) const { return (ci >> (2 * g)) & 3; }
+  __host__ __device__ __forceinline__ int j(int g) const { return (cj >> (2 * g)) & 3; }
 };
 
 template <int N>
-__device__ __forceinline__ Flow<N> load_flow(int64_t E, const int8_t* __restrict__ col, int64_t e) {
-  Flow<N> f{0, 0};
+__host__ __device__ __forceinline__ Flow<N> load_flow(int64_t E, const int8_t* __restrict__ col, int64_t e,
+                                             bool& in_range) {
+  Flow<N> f{0, 0, {0u, 0u, 0u}};
+  in_range = true;
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    f.ci |= ((int)col[(int64_t)k * E + e] & 3) << (2 * k);
-    f.cj |= ((int)col[((int64_t)N + k) * E + e] & 3) << (2 * k);
+    const int ii = col[(int64_t)k * E + e];
+    const int jj = col[((int64_t)N + k) * E + e];
+    in_range = in_range && ii >= 0 && ii <= 2 && jj >= 0 && jj <= 2;
+    f.ci |= (ii & 3) << (2 * k);
+    f.cj |= (jj & 3) << (2 * k);
+    if (k > 0) {
+      f.jm[0] |= (unsigned)(jj == 0) << k;
+      f.jm[1] |= (unsigned)(jj == 1) << k;
+      f.jm[2] |= (unsigned)(jj == 2) << k;
+    }
   }
   return f;
+}
+
+// Euler circuits (as cyclic sequences of distinguishable edges) of the
+// multigraph made of the colour edges j_k -> i_k of the gluons k not in
+// `skip`, plus the edge vu -> vv when vu >= 0; 0 when it is unbalanced or
+// disconnected.  BEST theorem: spanning arborescences towards any vertex (a
+// Laplacian minor over the three colours) times the product over vertices
+// of (out-degree - 1)!.
+template <int N>
+__host__ __device__ __forceinline__ unsigned euler_count(const Flow<N>& f, unsigned skip, int vu,
+                                                         int vv) {
+  int out[3] = {0, 0, 0}, in[3] = {0, 0, 0};
+  int a[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // non-loop edges u -> v
+#pragma unroll
+  for (int k = 0; k <= N; ++k) {
+    int u, v;
+    if (k < N) {
+      if ((skip >> k) & 1u) continue;
+      u = f.j(k);
+      v = f.i(k);
+    } else {
+      if (vu < 0) continue;
+      u = vu;
+      v = vv;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      out[c] += u == c;
+      in[c] += v == c;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) a[c][d] += (u == c && v == d && c != d);
+    }
+  }
+  if (out[0] != in[0] || out[1] != in[1] || out[2] != in[2]) return 0u;
+  constexpr unsigned fact[10] = {1u, 1u, 2u, 6u, 24u, 120u, 720u, 5040u, 40320u, 362880u};
+  // Laplacian L[c][d]: out-degree without loops on the diagonal, -a[c][d]
+  // off it; the count towards the first active vertex is the determinant of
+  // L restricted to the other active vertices
+  int act[3], na = 0;
+  unsigned prod = 1u;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (out[c] > 0) {
+      act[na++] = c;
+      prod *= fact[out[c] - 1];
+    }
+  }
+  if (na == 0) return 0u;
+  int t;
+  if (na == 1) {
+    t = 1;
+  } else {
+    int l[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) l[c][d] = c == d ? a[c][0] + a[c][1] + a[c][2] : -a[c][d];
+    }
+    if (na == 2) {
+      t = l[act[1]][act[1]];
+    } else {
+      t = l[1][1] * l[2][2] - l[1][2] * l[2][1];
+    }
+  }
+  return t > 0 ? (unsigned)t * prod : 0u;
+}
+
+// Number of closing orderings: the Euler circuits of all colour edges (each
+// read from gluon 1's edge on).  At most (N-1)!.
+template <int N>
+__host__ __device__ __forceinline__ unsigned closing_count(const Flow<N>& f) {
+  return euler_count<N>(f, 0u, -1, -1);
+}
+
+// Closing orderings that start (1, a, b): the chain holds through b, and the
+// remaining edges form an Euler trail from i_b back to j_1, i.e. an Euler
+// circuit once the edge j_1 -> i_b is added.
+template <int N>
+__host__ __device__ __forceinline__ unsigned prefix_count(const Flow<N>& f, int a, int b) {
+  if (f.j(a) != f.i(0) || f.j(b) != f.i(a)) return 0u;
+  const unsigned skip = 1u | (1u << a) | (1u << b);
+  if (N == 3) return f.i(b) == f.j(0) ? 1u : 0u;
+  return euler_count<N>(f, skip, f.j(0), f.i(b));
+}
+
+// The prefix (a, b) of lane l < (N-1)(N-2), in the depth-first order of the
+// orderings: a ascending, then b ascending.
+template <int N>
+__host__ __device__ __forceinline__ void prefix_of(int l, int& a, int& b) {
+  a = 1 + l / (N - 2);
+  b = 1 + l % (N - 2);
+  b += b >= a;
 }
 
 // Closing orderings: position D (1 .. N-1) takes an unused gluon g with
 // j_g = i of the previous gluon; after position N-1, i_last must equal j_0.
 // visit(code) with nibble D-1 of code = gluon at position D.
 template <int N, int D, class V>
-__device__ __forceinline__ void orderings(const Flow<N>& f, int used, int prev, uint32_t code,
+__host__ __device__ __forceinline__ void orderings(const Flow<N>& f, unsigned used, int prev, uint32_t code,
                                           V& visit) {
   if constexpr (D == N) {
     if (f.i(prev) == f.j(0)) visit(code);
   } else {
-    for (int g = 1; g < N; ++g) {
-      if ((used >> g) & 1) continue;
-      if (f.j(g) != f.i(prev)) continue;
-      orderings<N, D + 1>(f, used | (1 << g), g, code | ((uint32_t)g << (4 * (D - 1))), visit);
+    for (unsigned m = f.jm[f.i(prev)] & ~used; m != 0u; m &= m - 1u) {
+      const int g = __builtin_ctz(m);
+      orderings<N, D + 1>(f, used | (1u << g), g, code | ((uint32_t)g << (4 * (D - 1))), visit);
     }
+  }
+}
+
+__device__ __forceinline__ void block_sum_2(uint64_t x, uint64_t y, uint64_t* out_x,
+                                            uint64_t* out_y) {
+  __shared__ uint64_t px[kThreads], py[kThreads];
+  px[threadIdx.x] = x;
+  py[threadIdx.x] = y;
+  __syncthreads();
+  for (int off = kThreads / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      px[threadIdx.x] += px[threadIdx.x + off];
+      py[threadIdx.x] += py[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out_x[blockIdx.x] = px[0];
+    out_y[blockIdx.x] = py[0];
   }
 }
 
@@ -72,26 +202,18 @@ template <int N>
 __global__ void __launch_bounds__(kThreads) count_kernel(int64_t E, const int8_t* __restrict__ col,
                                                         double* __restrict__ me2,
                                                         unsigned* __restrict__ counts,
-                                                        uint64_t* __restrict__ block_count) {
-  __shared__ unsigned part[kThreads];
+                                                        uint64_t* __restrict__ block_items,
+                                                        uint64_t* __restrict__ block_valid) {
   const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   unsigned c = 0;
   if (e < E) {
-    if (cdbgk::flow_valid(N, E, col, e)) {
-      const Flow<N> f = load_flow<N>(E, col, e);
-      auto visit = [&](uint32_t) { ++c; };
-      orderings<N, 1>(f, 1, 0, 0u, visit);
-    }
+    bool in_range;
+    const Flow<N> f = load_flow<N>(E, col, e, in_range);
+    if (in_range) c = closing_count<N>(f);
     if (c == 0) me2[e] = 0.0;  // no closing ordering: the flow's amplitude is 0
     counts[e] = c;
   }
-  part[threadIdx.x] = c;
-  __syncthreads();
-  for (int off = kThreads / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) block_count[blockIdx.x] = part[0];
+  block_sum_2(c, c != 0, block_items, block_valid);
 }
 
 // Pass 2: exclusive scan of the block counts in place (one block); total at
@@ -122,34 +244,77 @@ __global__ void __launch_bounds__(1024) scan_kernel(uint64_t* __restrict__ block
   if (t == 1023) block_count[n_blocks] = part[1023];
 }
 
-// Pass 3: items (event << 32 | ordering code) at their ranks; the event's
-// first item index goes to offsets[e].
-template <int N>
-__global__ void __launch_bounds__(kThreads) items_kernel(int64_t E, const int8_t* __restrict__ col,
-                                                        const unsigned* __restrict__ counts,
-                                                        const uint64_t* __restrict__ block_offset,
-                                                        unsigned* __restrict__ offsets,
-                                                        uint64_t* __restrict__ items) {
-  __shared__ unsigned part[kThreads];
+// Pass 3: offsets[e] = the event's first item index; valid events listed in
+// event order.  Item ranks fit 32 bits: the host admits only totals below
+// 2^31 to the later passes.
+__global__ void __launch_bounds__(kThreads) offsets_kernel(int64_t E,
+                                                          const unsigned* __restrict__ counts,
+                                                          const uint64_t* __restrict__ block_items,
+                                                          const uint64_t* __restrict__ block_valid,
+                                                          unsigned* __restrict__ offsets,
+                                                          unsigned* __restrict__ valid) {
+  __shared__ unsigned pc[kThreads], pv[kThreads];
   const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const unsigned c = e < E ? counts[e] : 0u;
-  part[threadIdx.x] = c;
+  pc[threadIdx.x] = c;
+  pv[threadIdx.x] = c != 0u;
   __syncthreads();
   for (int off = 1; off < kThreads; off *= 2) {
-    const unsigned v = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+    const bool take = (int)threadIdx.x >= off;
+    const unsigned vc = take ? pc[threadIdx.x - off] : 0u;
+    const unsigned vv = take ? pv[threadIdx.x - off] : 0u;
     __syncthreads();
-    part[threadIdx.x] += v;
+    pc[threadIdx.x] += vc;
+    pv[threadIdx.x] += vv;
     __syncthreads();
   }
   if (e >= E) return;
-  // the host admits only totals below 2^31, so the rank fits 32 bits
-  const unsigned first = (unsigned)(block_offset[blockIdx.x] + part[threadIdx.x] - c);
-  offsets[e] = first;
-  if (c == 0) return;
-  const Flow<N> f = load_flow<N>(E, col, e);
-  unsigned k = first;
-  auto visit = [&](uint32_t code) { items[k++] = ((uint64_t)e << 32) | code; };
-  orderings<N, 1>(f, 1, 0, 0u, visit);
+  offsets[e] = (unsigned)(block_items[blockIdx.x] + pc[threadIdx.x] - c);
+  if (c != 0u) valid[block_valid[blockIdx.x] + pv[threadIdx.x] - 1u] = (unsigned)e;
+}
+
+// Pass 4: one wave per valid event writes its closing orderings
+// (event << 32 | ordering code) from offsets[e] on, never more than
+// counts[e]: lane l takes the orderings that start (1, a, b) (prefix_of),
+// counts them (prefix_count), finds its first rank by a prefix sum over the
+// wave and enumerates the rest of its subtree depth-first, so the items are
+// in the same order as one depth-first walk over the whole event.
+template <int N>
+__global__ void __launch_bounds__(kThreads) enumerate_kernel(int64_t E, const int8_t* __restrict__ col,
+                                                            const unsigned* __restrict__ valid,
+                                                            unsigned n_valid,
+                                                            const unsigned* __restrict__ counts,
+                                                            const unsigned* __restrict__ offsets,
+                                                            uint64_t* __restrict__ items) {
+  static_assert((N - 1) * (N - 2) <= kWave, "one prefix per lane");
+  const int lane = threadIdx.x & (kWave - 1);
+  const unsigned v = blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
+  if (v >= n_valid) return;  // whole waves leave together
+  const int64_t e = valid[v];
+  bool in_range;
+  const Flow<N> f = load_flow<N>(E, col, e, in_range);
+  int a = 1, b = 2;
+  unsigned c = 0u;
+  if (lane < (N - 1) * (N - 2)) {
+    prefix_of<N>(lane, a, b);
+    c = prefix_count<N>(f, a, b);
+  }
+  // inclusive prefix sum over the wave
+  unsigned incl = c;
+#pragma unroll
+  for (int off = 1; off < kWave; off *= 2) {
+    const unsigned t = __shfl_up(incl, off, kWave);
+    if (lane >= off) incl += t;
+  }
+  if (c == 0u) return;
+  const unsigned first = offsets[e];
+  const unsigned end = first + counts[e];
+  unsigned k = first + incl - c;
+  const unsigned stop = k + c < end ? k + c : end;
+  auto visit = [&](uint32_t code) {
+    if (k < stop) items[k++] = ((uint64_t)e << 32) | code;
+  };
+  orderings<N, 3>(f, 1u | (1u << a) | (1u << b), b, (uint32_t)a | ((uint32_t)b << 4), visit);
 }
 
 // Per-lane context for one ordering (see pairk::Ctx; 1/P^2 computed from the
@@ -171,7 +336,8 @@ struct Ctx {
 template <int N, typename T, int D, class C>
 __device__ __forceinline__ void path(pairk::State<N, T>& s, C& c, uint32_t code, Cx<T>& top) {
   constexpr int M = N - 1;
-  const int g = (int)((code >> (4 * (D - 1))) & 15u);
+  int g = (int)((code >> (4 * (D - 1))) & 15u);
+  g = g < 1 ? 1 : (g > N - 1 ? N - 1 : g);  // codes hold 1..N-1; keeps LDS reads in bounds
   s.gl[D] = g;
   const int base = 6 * (g - 1);
 #pragma unroll
@@ -183,7 +349,8 @@ __device__ __forceinline__ void path(pairk::State<N, T>& s, C& c, uint32_t code,
   }
   if constexpr (D == M - 1) {
     // the ordering's last gluon closes it
-    const int gl = (int)((code >> (4 * (N - 2))) & 15u);
+    int gl = (int)((code >> (4 * (N - 2))) & 15u);
+    gl = gl < 1 ? 1 : (gl > N - 1 ? N - 1 : gl);
     const int lb = 6 * (gl - 1);
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
@@ -230,7 +397,8 @@ __global__ void __launch_bounds__(64) amp_kernel(int64_t E, const double* __rest
   for (unsigned base = blockIdx.x * 32u; base < total; base += gridDim.x * 32u) {
     const unsigned it = base + pair < total ? base + pair : total - 1;
     const uint64_t item = items[it];
-    const int64_t e = (int64_t)(item >> 32);
+    int64_t e = (int64_t)(item >> 32);
+    e = e < E ? e : E - 1;  // items always hold e < E; the clamp keeps reads in bounds regardless
     const uint32_t code = (uint32_t)item;
     pairk::State<N, T> s;
 #pragma unroll
@@ -301,21 +469,27 @@ int amp_launch(int64_t E, const double* mom, const int8_t* hel, const uint64_t* 
 }
 
 template <int N>
-int count_launch(int64_t E, const int8_t* col, double* me2, unsigned* counts, uint64_t* blocks,
+int count_launch(int64_t E, const int8_t* col, double* me2, unsigned* counts, unsigned* offsets,
+                 unsigned* valid, uint64_t* block_items, uint64_t* block_valid,
                  hipStream_t stream) {
   const int64_t nb = (E + kThreads - 1) / kThreads;
   hipLaunchKernelGGL((count_kernel<N>), dim3((unsigned)nb), dim3(kThreads), 0, stream, E, col, me2,
-                     counts, blocks);
-  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, stream, blocks, (int)nb);
+                     counts, block_items, block_valid);
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, stream, block_items, (int)nb);
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, stream, block_valid, (int)nb);
+  hipLaunchKernelGGL(offsets_kernel, dim3((unsigned)nb), dim3(kThreads), 0, stream, E, counts,
+                     block_items, block_valid, offsets, valid);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <int N>
-int items_launch(int64_t E, const int8_t* col, const unsigned* counts, const uint64_t* blocks,
-                 unsigned* offsets, uint64_t* items, hipStream_t stream) {
-  const int64_t nb = (E + kThreads - 1) / kThreads;
-  hipLaunchKernelGGL((items_kernel<N>), dim3((unsigned)nb), dim3(kThreads), 0, stream, E, col,
-                     counts, blocks, offsets, items);
+int enumerate_launch(int64_t E, const int8_t* col, const unsigned* valid, unsigned n_valid,
+                     const unsigned* counts, const unsigned* offsets, uint64_t* items,
+                     hipStream_t stream) {
+  constexpr unsigned per_block = kThreads / kWave;  // one wave per valid event
+  const unsigned nb = (n_valid + per_block - 1) / per_block;
+  hipLaunchKernelGGL((enumerate_kernel<N>), dim3(nb), dim3(kThreads), 0, stream, E, col, valid,
+                     n_valid, counts, offsets, items);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -333,15 +507,19 @@ int items_launch(int64_t E, const int8_t* col, const unsigned* counts, const uin
   }
 
 int comc_count(int n, int64_t E, const int8_t* col, double* me2, unsigned* counts,
-               uint64_t* blocks, hipStream_t stream) {
-#define C_(NN) comck::count_launch<NN>(E, col, me2, counts, blocks, stream)
+               unsigned* offsets, unsigned* valid, uint64_t* block_items, uint64_t* block_valid,
+               hipStream_t stream) {
+#define C_(NN) \
+  comck::count_launch<NN>(E, col, me2, counts, offsets, valid, block_items, block_valid, stream)
   BG_COMC_SWITCH(C_)
 #undef C_
 }
 
-int comc_items(int n, int64_t E, const int8_t* col, const unsigned* counts, const uint64_t* blocks,
-               unsigned* offsets, uint64_t* items, hipStream_t stream) {
-#define C_(NN) comck::items_launch<NN>(E, col, counts, blocks, offsets, items, stream)
+int comc_items(int n, int64_t E, const int8_t* col, const unsigned* valid, unsigned n_valid,
+               const unsigned* counts, const unsigned* offsets, uint64_t* items,
+               hipStream_t stream) {
+#define C_(NN) \
+  comck::enumerate_launch<NN>(E, col, valid, n_valid, counts, offsets, items, stream)
   BG_COMC_SWITCH(C_)
 #undef C_
 }
