@@ -481,7 +481,8 @@ static int me2_comc(bg_context* ctx, const bg_request* r, hipStream_t stream) {
   st = launch_status(bg::comc_amplitudes(n, fp32, E, r->mom, r->hel, ctx->comc_items,
                                          block_items + nb, ctx->comc_amp, grid, stream));
   if (st) return st;
-  return launch_status(bg::comc_reduce(E, counts, offsets, ctx->comc_amp, r->me2, stream));
+  return launch_status(bg::comc_reduce(valid, (unsigned)n_valid, counts, offsets, ctx->comc_amp,
+                                       r->me2, stream));
 }
 
 static int validate_request(const bg_request* r) {

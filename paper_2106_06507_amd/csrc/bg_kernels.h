@@ -126,8 +126,8 @@ int comc_items(int n, int64_t E, const int8_t* col, const unsigned* valid, unsig
 int comc_amplitudes(int n, bool fp32, int64_t E, const double* mom, const int8_t* hel,
                     const uint64_t* items, const uint64_t* total, double* amp, int grid,
                     hipStream_t stream);
-int comc_reduce(int64_t E, const unsigned* counts, const unsigned* offsets, const double* amp,
-                double* me2, hipStream_t stream);
+int comc_reduce(const unsigned* valid, unsigned n_valid, const unsigned* counts,
+                const unsigned* offsets, const double* amp, double* me2, hipStream_t stream);
 
 // On-device phase-space generation (rambo.hip).
 struct GenParams {

@@ -16,13 +16,15 @@
 // unbalanced or disconnected flows get 0 and exactly 0 for |A|^2.
 // (2) one block scans the per-block item and valid-event counts.  (3) one
 // thread per event writes its first item index and lists the valid events.
-// (4) one thread per valid event enumerates its closing orderings
-// depth-first (candidate gluons from per-colour bit masks) and writes its
-// (event, ordering) items at their ranks.  (5) one lane pair per item
+// (4) one wave per valid event enumerates its closing orderings, split over
+// the lanes by the two gluons that follow gluon 1 (each prefix's share
+// counted the same way), depth-first with candidate gluons from per-colour
+// bit masks, and writes its (event, ordering) items at their ranks.
+// (5) one lane pair per item
 // evaluates A(1, sigma) with the lane-pair recursion of cobg_pair_impl.h on
 // that single ordering (gluons of the ordering differ between pairs; 1/P^2
-// from the FP64 prefix momenta).  (6) one thread per event adds its items'
-// amplitudes in order and writes |A|^2.  The totals are read back once (a
+// from the FP64 prefix momenta).  (6) one wave per valid event adds its
+// items' amplitudes and writes |A|^2.  The totals are read back once (a
 // synchronisation) to size the item arrays and the enumeration grid.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -441,22 +443,33 @@ __global__ void __launch_bounds__(64) amp_kernel(int64_t E, const double* __rest
   }
 }
 
-// Pass 5: |sum of the event's item amplitudes|^2 (items in ordering order).
-__global__ void __launch_bounds__(kThreads) reduce_kernel(int64_t E, const unsigned* __restrict__ counts,
+// Pass 6: |sum of the event's item amplitudes|^2, one wave per valid event
+// (the others were set to 0 by pass 1): lane l adds items l, l + 64, ...,
+// then a fixed butterfly adds the lanes, so the result does not depend on
+// the launch.
+__global__ void __launch_bounds__(kThreads) reduce_kernel(const unsigned* __restrict__ valid,
+                                                         unsigned n_valid,
+                                                         const unsigned* __restrict__ counts,
                                                          const unsigned* __restrict__ offsets,
                                                          const double* __restrict__ amp,
                                                          double* __restrict__ me2) {
-  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (e >= E) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const unsigned v = blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
+  if (v >= n_valid) return;  // whole waves leave together
+  const unsigned e = valid[v];
   const unsigned c = counts[e];
-  if (c == 0) return;  // invalid flow: already 0
   const unsigned o = offsets[e];
   double re = 0.0, im = 0.0;
-  for (unsigned k = 0; k < c; ++k) {
+  for (unsigned k = lane; k < c; k += kWave) {
     re += amp[2 * (size_t)(o + k)];
     im += amp[2 * (size_t)(o + k) + 1];
   }
-  me2[e] = re * re + im * im;
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    re += __shfl_xor(re, off, kWave);
+    im += __shfl_xor(im, off, kWave);
+  }
+  if (lane == 0) me2[e] = re * re + im * im;
 }
 
 template <int N, typename T>
@@ -534,11 +547,12 @@ int comc_amplitudes(int n, bool fp32, int64_t E, const double* mom, const int8_t
 #undef C_
 }
 
-int comc_reduce(int64_t E, const unsigned* counts, const unsigned* offsets, const double* amp,
-                double* me2, hipStream_t stream) {
-  const int64_t nb = (E + comck::kThreads - 1) / comck::kThreads;
-  hipLaunchKernelGGL(comck::reduce_kernel, dim3((unsigned)nb), dim3(comck::kThreads), 0, stream, E,
-                     counts, offsets, amp, me2);
+int comc_reduce(const unsigned* valid, unsigned n_valid, const unsigned* counts,
+                const unsigned* offsets, const double* amp, double* me2, hipStream_t stream) {
+  constexpr unsigned per_block = comck::kThreads / comck::kWave;  // one wave per valid event
+  const unsigned nb = (n_valid + per_block - 1) / per_block;
+  hipLaunchKernelGGL(comck::reduce_kernel, dim3(nb), dim3(comck::kThreads), 0, stream, valid,
+                     n_valid, counts, offsets, amp, me2);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
