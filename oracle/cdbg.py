@@ -107,22 +107,20 @@ def _flow_matrix(i_k, j_k, E):
     return M
 
 
-def dressed_currents(mom, hel, col, g=G_S, tensor=True):
-    """Dressed currents of all subsets of gluons 1..n-1 (0-based 0..n-2).
+def dressed_recursion(ps, eps, colmats, g=G_S, tensor=True):
+    """Dressed currents of all subsets of gluons 1..n-1 (0-based 0..n-2) for
+    external currents eps[k] [4,E] and external colour matrices colmats[k]
+    [3,3,E] (a colour-flow assignment, or any other colour wavefunction).
 
     Returns dict mask -> J [3,3,4,E]; the full mask holds P^2 J (amputated).
     """
-    n = mom.shape[0]
-    E = mom.shape[2]
-    m = n - 1
-    ps = momenta_list(mom)
-    eps = external_currents(ps, hel)
+    m = len(ps) - 1
+    E = np.shape(ps[0][0])[-1]
     J, T, P = {}, {}, {}
     for k in range(m):
         mk = 1 << k
-        fm = _flow_matrix(col[0, k], col[1, k], E)
         e = np.array(eps[k])  # [4,E]
-        J[mk] = fm[:, :, None, :] * e[None, None]
+        J[mk] = colmats[k][:, :, None, :] * e[None, None]
         T[mk] = np.zeros((3, 3, 4, 4, E), dtype=np.complex128)
         P[mk] = ps[k]
     full = (1 << m) - 1
@@ -152,6 +150,17 @@ def dressed_currents(mom, hel, col, g=G_S, tensor=True):
                 p2 = mdot(P[S], P[S])
                 J[S] = (-1j / p2) * acc
     return J
+
+
+def dressed_currents(mom, hel, col, g=G_S, tensor=True):
+    """Dressed currents for helicity labels hel [n][E] and the colour-flow
+    assignment col [2][n][E] (see dressed_recursion)."""
+    n = mom.shape[0]
+    E = mom.shape[2]
+    ps = momenta_list(mom)
+    eps = external_currents(ps, hel)
+    colmats = [_flow_matrix(col[0, k], col[1, k], E) for k in range(n - 1)]
+    return dressed_recursion(ps, eps, colmats, g=g, tensor=tensor)
 
 
 def flow_amplitude(mom, hel, col, g=G_S, tensor=True):
