@@ -229,6 +229,31 @@ int bg_generate(bg_context* ctx, const bg_gen_params* params, int64_t n_attempts
                 int64_t max_events, double* mom, int8_t* hel, int8_t* col, int64_t* attempt,
                 int64_t* n_generated, void* stream);
 
+/* Continuous colour and polarization sampling with the colour-dressed
+ * recursion, all arithmetic real (Section 2.1 eqs. polarization_kleiss,
+ * polarization_simple, color_angles, gluon_color_polarization; Section 2.3
+ * eq. color_dressed_currents).  Per event and gluon k:
+ *   phi : double [n][E], the polarization angle; gluon k's polarization is
+ *         e_k = e^{i phi} X^+ + e^{-i phi} X^- = sqrt2 (cos phi e1 + sin phi e2)
+ *         with the helicity currents X^h and e1, e2 of `hel` above, so the
+ *         average over phi of |A|^2 is the helicity sum;
+ *   eta : double [2][n][3][E], eta[0][k] = eta(z_k), eta[1][k] = eta(zbar_k),
+ *         the two colour vectors of eq. gluon_color_polarization (unit vectors
+ *         for the sampling; any real vectors are accepted, the amplitude is
+ *         linear in each).  Gluon k's colour matrix is eta(zbar_k) eta(z_k)^T
+ *         (a colour-flow pair (i, j) is eta(z) = e_i, eta(zbar) = e_j).
+ * me2[e] = A^2 of the (real) amplitude.  With phi uniform in [0, 2 pi) and the
+ * eta vectors uniform on the unit sphere, 9^n E[me2] is the colour- and
+ * helicity-summed |M|^2 (each sphere integral carries N_c).  n in [4, 9];
+ * both precisions (FP32: currents in FP32, invariants 1/P^2 and the final
+ * contraction in FP64).  The first FP64 call at n = 9 allocates a per-block
+ * state buffer in the context (its state exceeds the LDS).  One event per
+ * workgroup; every split of every subset costs a 3x3 colour-matrix product,
+ * so this is compute-bound and far costlier per event than CDBG, but no
+ * sampled event has a zero weight. */
+int bg_me2_continuous(bg_context* ctx, int n, int precision, int64_t n_events, const double* mom,
+                      const double* phi, const double* eta, double* me2, void* stream);
+
 /* Self-test of the matrix-core operand layout used by bg_color_contract:
  * runs one v_mfma_f64_16x16x4f64 with lane l supplying A[l%16][l/16] =
  * (l%16 + 1) + 100 (l/16) and B[l/16][l%16] = (l%16 + 1) 8^(l/16), and copies

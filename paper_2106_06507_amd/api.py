@@ -277,6 +277,27 @@ class BatchGraph:
 # ---------------------------------------------------------------- phase space
 
 
+def me2_continuous(mom, phi, eta, precision="fp64", out=None, ctx=None):
+    """A^2 per event (float64 [E]) for real polarization angles phi [n, E]
+    and colour vectors eta [2, n, 3, E] (float64, CUDA); 9^n times its mean
+    over uniform phi and sphere vectors is the colour- and helicity-summed
+    |M|^2."""
+    n, E = _check_mom(mom)
+    if not (phi.is_cuda and phi.dtype == torch.float64 and tuple(phi.shape) == (n, E)):
+        raise ValueError("phi must be a CUDA float64 tensor [n, E]")
+    if not (eta.is_cuda and eta.dtype == torch.float64 and tuple(eta.shape) == (2, n, 3, E)):
+        raise ValueError("eta must be a CUDA float64 tensor [2, n, 3, E]")
+    phi = phi.contiguous()
+    eta = eta.contiguous()
+    ctx = ctx or default_context(mom.device.index)
+    if out is None:
+        out = torch.empty(E, dtype=torch.float64, device=mom.device)
+    check(lib().bg_me2_continuous(ctx.handle, n, _PREC[precision], E, mom.data_ptr(), phi.data_ptr(),
+                                  eta.data_ptr(), out.data_ptr(), _stream(mom.device)),
+          "bg_me2_continuous")
+    return out
+
+
 def generate(n, n_events, seed, n_attempts=None, first_attempt=0, cuts=True, sample_hel=True,
              sample_col=False, sqrt_s=1000.0, pt_min=20.0, dr_min=0.4, with_attempts=False,
              device=None, ctx=None):

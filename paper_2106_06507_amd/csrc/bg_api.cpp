@@ -56,7 +56,9 @@ struct bg_context {
   uint64_t* comc_items = nullptr;            // (event, ordering) items
   double* comc_amp = nullptr;                // their amplitudes
   size_t comc_cap = 0;
-  int occ_comc[BG_N_MAX + 1][2] = {};
+  void* cdmc_state = nullptr;                // per-block state slabs (FP64, n = 9)
+  size_t cdmc_state_bytes = 0;
+  int occ_cdmc[BG_N_MAX + 1][2] = {};
   bg_batch_config bcfg[2] = {{0, 128, 256, 2}, {0, 128, 256, 2}};
   std::vector<BatchPlan> plans;
   uint64_t clock = 0;
@@ -328,6 +330,7 @@ void bg_context_destroy(bg_context* ctx) {
   if (ctx->comc_ws) (void)hipFree(ctx->comc_ws);
   if (ctx->comc_items) (void)hipFree(ctx->comc_items);
   if (ctx->comc_amp) (void)hipFree(ctx->comc_amp);
+  if (ctx->cdmc_state) (void)hipFree(ctx->cdmc_state);
   if (ctx->counter) (void)hipFree(ctx->counter);
   for (BatchPlan& pl : ctx->plans)
     if (pl.tiles) (void)hipFree(pl.tiles);
@@ -877,6 +880,43 @@ int bg_me2_batch_tune(bg_context* ctx, const bg_request* segs, int n_segs, bg_ba
   if (best) *best = cur;
   if (best_ms) *best_ms = cur_ms;
   return BG_OK;
+}
+
+int bg_me2_continuous(bg_context* ctx, int n, int precision, int64_t n_events, const double* mom,
+                      const double* phi, const double* eta, double* me2, void* stream) {
+  if (!ctx) return BG_EINVAL;
+  if (!valid_n(n)) return BG_EINVAL;
+  if (precision != BG_PREC_FP64 && precision != BG_PREC_FP32_MIXED) return BG_EINVAL;
+  int st = check_events(n, n_events);
+  if (st) return st;
+  if (n_events == 0) return BG_OK;
+  if (!mom || !phi || !eta || !me2) return BG_EINVAL;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return BG_EDEVICE;
+  const bool fp32 = precision == BG_PREC_FP32_MIXED;
+  int& per_cu = ctx->occ_cdmc[n][fp32 ? 1 : 0];
+  if (per_cu <= 0) per_cu = bg::cdmc_blocks_per_cu(n, fp32);
+  if (per_cu <= 0) return BG_EUNSUPPORTED;
+  int64_t grid = (int64_t)ctx->num_cus * (int64_t)per_cu;
+  if (grid > n_events) grid = n_events;
+  void* gstate = nullptr;
+  if (bg::cdmc_global_state(n, fp32)) {
+    // one slab per block of the largest grid, allocated once per context
+    const size_t need = bg::cdmc_state_bytes(n, fp32) * (size_t)ctx->num_cus * (size_t)per_cu;
+    if (ctx->cdmc_state_bytes < need) {
+      st = hip_status(hipDeviceSynchronize(), "hipDeviceSynchronize");
+      if (st) return st;
+      if (ctx->cdmc_state) (void)hipFree(ctx->cdmc_state);
+      ctx->cdmc_state = nullptr;
+      ctx->cdmc_state_bytes = 0;
+      st = hip_status(hipMalloc(&ctx->cdmc_state, need), "hipMalloc(continuous state)");
+      if (st) return st;
+      ctx->cdmc_state_bytes = need;
+    }
+    gstate = ctx->cdmc_state;
+  }
+  return launch_status(bg::cdmc_me2(n, fp32, n_events, mom, phi, eta, gstate, (int)grid, me2,
+                                    (hipStream_t)stream));
 }
 
 int bg_generate(bg_context* ctx, const bg_gen_params* gp, int64_t n_attempts, int64_t max_events,

@@ -129,6 +129,14 @@ int comc_amplitudes(int n, bool fp32, int64_t E, const double* mom, const int8_t
 int comc_reduce(const unsigned* valid, unsigned n_valid, const unsigned* counts,
                 const unsigned* offsets, const double* amp, double* me2, hipStream_t stream);
 
+// Continuous colour / real-polarization sampling with the dressed recursion
+// (cdmc.hip).  gstate: blocks x cdmc_state_bytes when cdmc_global_state.
+size_t cdmc_state_bytes(int n, bool fp32);
+bool cdmc_global_state(int n, bool fp32);
+int cdmc_blocks_per_cu(int n, bool fp32);
+int cdmc_me2(int n, bool fp32, int64_t E, const double* mom, const double* phi, const double* eta,
+             void* gstate, int grid, double* me2, hipStream_t stream);
+
 // On-device phase-space generation (rambo.hip).
 struct GenParams {
   int n;
