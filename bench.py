@@ -15,7 +15,9 @@ events), the mixed-multiplicity batch (n = 4..9) in one persistent launch
 replayed from a recorded graph, phase space generated on the device ahead
 of the evaluation, and events/s per gluon multiplicity n = 4..9 (FP32 and
 FP64, with the FP32 error relative to FP64, and the colour-sampled
-colour-ordered and leading-colour modes on the same events).
+colour-ordered and leading-colour modes on the same events), and the
+statistical efficiency of the colour treatments (colour sum, sampled flows,
+continuous colours and polarizations) on shared phase-space points.
 
 Prints one JSON line.  Only one GPU is used: --gpus above 1 exits.
 """
@@ -299,6 +301,7 @@ def section_pipeline(args, api, torch):
 
 
 def section_per_n(args, api, torch):
+    from paper_2106_06507_amd import workmodel as wm
     """Events/s per gluon multiplicity, FP32 recursion and FP64, with the
     FP32 error relative to the FP64 evaluation of the same events.  Inputs are
     generated on the device (RAMBO + cuts, sampled helicities; sampled colour
@@ -357,6 +360,34 @@ def section_per_n(args, api, torch):
             co[p] = {"events_per_s": E / (cms * 1e-3), "ms": cms,
                      "rel_dev_from_dressed_fp64": rel_err_stats(got_c[ck], dres[ck])}
         rows[str(n)]["colour_sampled_ordered"] = co
+        # continuous colours and real polarizations (all-real dressed
+        # recursion) on the first Ec of these points
+        from bg_inputs import continuous_states
+        Ec = min(E, 1 << (22 - n))
+        phi_c, eta_c = continuous_states(n, Ec, 2106065070 + 60 + n)
+        phi_c, eta_c = torch.from_numpy(phi_c).cuda(), torch.from_numpy(eta_c).cuda()
+        mom_c = mom[:, :, :Ec].contiguous()
+        cres, cms = {}, {}
+        for p in ("fp32", "fp64"):
+            buf = torch.empty(Ec, dtype=torch.float64, device="cuda")
+            log(f"timing n={n} continuous {p}")
+            cms[p] = time_events(lambda: api.me2_continuous(mom_c, phi_c, eta_c, precision=p, out=buf),
+                                 steps, 1)
+            cres[p] = buf.cpu().numpy()
+        flops = wm.continuous_flops_per_event(n)
+        ck = cres["fp64"] > 1e-3 * np.median(cres["fp64"])
+        cerr = rel_err_stats(cres["fp32"][ck], cres["fp64"][ck])
+        cerr["max_abs_over_max"] = float(np.max(np.abs(cres["fp32"] - cres["fp64"])) / np.max(cres["fp64"]))
+        rows[str(n)]["continuous_colour_polarization"] = {
+            "events": Ec, "flops_per_event": flops,
+            "fp32": {"events_per_s": Ec / (cms["fp32"] * 1e-3), "ms": cms["fp32"],
+                     "tflops": flops * Ec / (cms["fp32"] * 1e-3) / 1e12,
+                     "frac_of_fp32_without_packed": flops * Ec / (cms["fp32"] * 1e-3) / 1e12
+                     / wm.PEAK_FP32_VALU_NOPK_TFLOPS},
+            "fp64": {"events_per_s": Ec / (cms["fp64"] * 1e-3), "ms": cms["fp64"],
+                     "tflops": flops * Ec / (cms["fp64"] * 1e-3) / 1e12,
+                     "frac_of_fp64": flops * Ec / (cms["fp64"] * 1e-3) / 1e12 / wm.PEAK_FP64_VALU_TFLOPS},
+            "fp32_rel_err_vs_fp64": cerr}
         rows[str(n)]["valid_fraction"] = float((dres != 0.0).mean())
         if not cd:
             # leading-colour mode on the same events: all (n-1)! orderings,
@@ -369,6 +400,70 @@ def section_per_n(args, api, torch):
                 "events_per_s": E / (lms * 1e-3), "ms": lms,
                 "rel_dev_from_full_colour": rel_err_stats(lc[keep], res["fp64"][keep])}
     return rows
+
+
+def section_sampling(args, api, torch):
+    """Statistical efficiency of the colour treatments.  Each method gives an
+    unbiased per-event estimate w of the colour- and helicity-summed |M|^2:
+      colour-summed colour-ordered, sampled helicity:   2^n |M_h|^2 (n <= 7)
+      colour-dressed or colour-sampled colour-ordered,
+        uniform colour flow and helicity:               2^n 9^n |A_flow,h|^2
+      continuous colours and polarizations:             9^n A^2
+    To separate the colour/helicity variance from the phase-space variance,
+    64 device-generated phase-space points are each repeated 4096 times with
+    independent colour and helicity samples.  Per point the relative variance
+    var(w)/mean(w)^2 is taken; reported: its median over the points, the
+    events/s of the method (FP32) and the effective rate events/s /
+    (1 + median relative variance), i.e. colour- and helicity-exact
+    equivalent events per second at a fixed phase-space point."""
+    from bg_inputs import continuous_states
+    out = {}
+    steps = max(2, args.steps // 8)
+    P, R = 64, 4096
+    E = P * R
+    for n in (6, 8):
+        g = api.generate(n, E, 2106065070 + 40 + n, n_attempts=3 * E, sample_col=True)
+        torch.cuda.synchronize()
+        if int(g["n_generated"]) < E:
+            raise RuntimeError(f"device generator produced too few events at n={n}")
+        mom = g["mom"][:, :, :P].repeat_interleave(R, dim=2).contiguous()
+        hel, col = g["hel"], g["col"]
+        phi, eta = continuous_states(n, E, 2106065070 + 50 + n)
+        phi, eta = torch.from_numpy(phi).cuda(), torch.from_numpy(eta).cuda()
+        buf = torch.empty(E, dtype=torch.float64, device="cuda")
+        runs = []
+        if n <= 7:
+            runs.append(("colour_summed_ordered", 2.0 ** n,
+                         lambda: api.me2(mom, hel, precision="fp32", out=buf)))
+        runs.append(("colour_dressed_flow", 2.0 ** n * 9.0 ** n,
+                     lambda: api.me2(mom, hel, col, mode="cdbg", precision="fp32", out=buf)))
+        runs.append(("colour_sampled_ordered_flow", 2.0 ** n * 9.0 ** n,
+                     lambda: api.me2(mom, hel, col, mode="comc", precision="fp32", out=buf)))
+        runs.append(("continuous_colour_polarization", 9.0 ** n,
+                     lambda: api.me2_continuous(mom, phi, eta, precision="fp32", out=buf)))
+        row = {"points": P, "samples_per_point": R}
+        exact = None
+        if n <= 7:
+            exact = api.me2(g["mom"][:, :, :P].contiguous(), None, precision="fp64").cpu().numpy()
+        for name, scale, fn in runs:
+            log(f"timing sampling n={n} {name}")
+            ms = time_events(fn, steps, 1)
+            w = (scale * buf.cpu().numpy()).reshape(P, R)
+            mean = w.mean(axis=1)
+            rv = w.var(axis=1) / mean ** 2
+            rate = E / (ms * 1e-3)
+            r = {"ms": ms, "events_per_s": rate,
+                 "rel_variance_median": float(np.median(rv)),
+                 "rel_variance_mean": float(np.mean(rv)),
+                 "effective_events_per_s": rate / (1.0 + float(np.median(rv)))}
+            if exact is not None:
+                # per-point sample mean against the exact colour and helicity sum
+                pull = (mean - exact) / (w.std(axis=1) / np.sqrt(R))
+                r["pull_vs_exact_sum"] = {"median_abs": float(np.median(np.abs(pull))),
+                                          "max_abs": float(np.max(np.abs(pull)))}
+            row[name] = r
+        out[str(n)] = row
+    return out
 
 
 def cpu_baseline(args, ev):
@@ -396,9 +491,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--events", type=int, default=1 << 20)
-    ap.add_argument("--sections", default="cdbg,adjoint,batch,pipeline,per_n",
+    ap.add_argument("--sections", default="cdbg,adjoint,batch,pipeline,per_n,sampling",
                     help="extra rows beside the headline: any of cdbg, adjoint, batch, "
-                         "pipeline, per_n, or none")
+                         "pipeline, per_n, sampling, or none")
     ap.add_argument("--cpu-sample", type=int, default=1 << 19,
                     help="events of the headline workload timed on the oracle")
     ap.add_argument("--no-cpu", action="store_true")
@@ -434,6 +529,8 @@ def main():
         extra["device_phase_space_pipeline"] = section_pipeline(args, api, torch)
     if "per_n" in sections:
         extra["per_multiplicity"] = section_per_n(args, api, torch)
+    if "sampling" in sections:
+        extra["sampling_efficiency"] = section_sampling(args, api, torch)
     cpu = None if args.no_cpu else cpu_baseline(args, ev)
 
     rec = {

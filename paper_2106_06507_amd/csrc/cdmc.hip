@@ -28,8 +28,9 @@
 // Layout: one event per block of NW waves; within a wave, groups of nine
 // lanes hold the nine colour entries (i, j) (lane 63 idles).  Subsets are
 // processed by size; the targets of one size are spread over the groups,
-// with q groups per target splitting its ordered splits when targets are
-// fewer than groups, and the q partial sums added in a fixed order.  The
+// with q groups per target taking contiguous ranges of its ordered splits
+// when targets are fewer than groups, and the q partial sums added in a
+// fixed order.  The
 // subset state (J, T, P as T, 1/P^2 from FP64 momenta) lives in LDS, or for
 // FP64 at n = 9 in a global slab per block (it exceeds the LDS).
 #include <hip/hip_runtime.h>
@@ -301,9 +302,15 @@ cdmc_kernel(int64_t E, const double* __restrict__ mom, const double* __restrict_
         T outJ[4] = {T(0), T(0), T(0), T(0)};
         T outT[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
         if (active) {
-          for (int x = 1 + slice; x <= nsplit; x += q) {
-            const int A = submask(S, x);
+          // a contiguous range of splits per slice; the next sub-mask of S
+          // in increasing order is (A - S) & S
+          const int per = (nsplit + q - 1) / q;
+          const int x0 = 1 + slice * per;
+          const int x1 = x0 + per - 1 < nsplit ? x0 + per - 1 : nsplit;
+          int A = x0 <= x1 ? submask(S, x0) : 0;
+          for (int x = x0; x <= x1; ++x) {
             split_term<N, T>(st, A, S ^ A, ci, cj, !top, outJ, outT);
+            A = (A - S) & S;
           }
         }
         if (top) {

@@ -58,6 +58,36 @@ def colour_sum_flops_per_event(n):
     return 2 * 2 * (K * (K + 1) // 2 + K)
 
 
+def continuous_flops_per_event(n):
+    """Real flops of the continuous-colour dressed recursion per event, from
+    the formulas as written, summed over every subset S of gluons 1..n-1
+    with |S| >= 2 and every ordered split (A, B) of S:
+      per split: (2P_B + P_A), (2P_A + P_B), P_A - P_B            20
+      per split and colour entry (nine entries):
+        V3 with the 3x3 colour product (3 + 6 Minkowski dots,
+          the two k-sums and the (P_A - P_B) term)              121
+        J(A) T(B) term when |B| >= 2                              72
+        T(A) J(B) term when |A| >= 2                              72
+        tensor current of S (six components) unless S is full     72
+      per subset and entry: times 1/P^2 (4); at the full set the
+      contraction with e_n and the two colour vectors (10)."""
+    m = n - 1
+    full = (1 << m) - 1
+    total = 0
+    for S in range(1, full + 1):
+        if bin(S).count("1") < 2:
+            continue
+        A = (S - 1) & S
+        while A:
+            B = S ^ A
+            per = 121 + (72 if bin(B).count("1") >= 2 else 0) + (72 if bin(A).count("1") >= 2 else 0)
+            per += 72 if S != full else 0
+            total += 20 + 9 * per
+            A = (A - 1) & S
+        total += 9 * (10 if S == full else 4)
+    return total
+
+
 def cobg_bytes_per_event(n, amp_out=True):
     """HBM bytes of the recursion kernel: momenta and helicities in, amplitudes out."""
     K = math.factorial(n - 2)
