@@ -16,6 +16,8 @@ Contents (each module cites the passage of the paper it follows):
   me2           colour- and helicity-summed |M|^2 (Section 2.2)
   cdbg          colour-dressed recursion in the colour-flow basis (Section 2.3)
                 and the brute-force colour-flow sum (Section 2.2)
+  cdmc          the dressed recursion with continuous colour vectors and real
+                polarizations (Section 2.1)
   grad          d|M|^2/dp from forward-mode dual numbers
 Every function works in float64 / complex128 numpy arrays vectorised over
 events (the last axis); nothing is blocked, fused or reordered beyond the
