@@ -98,21 +98,27 @@ __device__ __forceinline__ constexpr int pidx(int a, int b) {
   return a == 0 ? b - 1 : (a == 1 ? b + 1 : 5);
 }
 
-// X[nu] = sum_b g_bb J^b T^{nu b} for antisymmetric T given by t[6]
+// out[nu] += sgn sum_b g_bb J^b T^{nu b} for the antisymmetric T given by
+// t[6] (pairs 01, 02, 03, 12, 13, 23); one multiply-add per term
 template <typename T>
-__device__ __forceinline__ void jt_contract(const T J[4], const T t[6], T X[4]) {
-  X[0] = -J[1] * t[0] - J[2] * t[1] - J[3] * t[2];
-  X[1] = -J[0] * t[0] - J[2] * t[3] - J[3] * t[4];
-  X[2] = -J[0] * t[1] + J[1] * t[3] - J[3] * t[5];
-  X[3] = -J[0] * t[2] + J[1] * t[4] + J[2] * t[5];
-}
-
-template <typename T>
-__device__ __forceinline__ T mdot4(const T a[4], const T b[4]) {
-  return a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+__device__ __forceinline__ void jt_accumulate(const T J[4], const T t[6], T sgn, T out[4]) {
+  const T j0 = sgn * J[0], j1 = sgn * J[1], j2 = sgn * J[2], j3 = sgn * J[3];
+  out[0] -= j1 * t[0];
+  out[0] -= j2 * t[1];
+  out[0] -= j3 * t[2];
+  out[1] -= j0 * t[0];
+  out[1] -= j2 * t[3];
+  out[1] -= j3 * t[4];
+  out[2] -= j0 * t[1];
+  out[2] += j1 * t[3];
+  out[2] -= j3 * t[5];
+  out[3] -= j0 * t[2];
+  out[3] += j1 * t[4];
+  out[3] += j2 * t[5];
 }
 
 // Accumulate the contribution of the ordered split (A, B) to entry (i, j).
+// Every product is accumulated with its own multiply-add.
 template <int N, typename T>
 __device__ __forceinline__ void split_term(const T* __restrict__ st, int A, int B, int i, int j,
                                            bool want_t, T outJ[4], T outT[6]) {
@@ -131,45 +137,53 @@ __device__ __forceinline__ void split_term(const T* __restrict__ st, int A, int 
       b[k][m] = st[L::oJ + 36 * B + 12 * k + 4 * j + m];
     }
   }
-  T q[4], p[4], d[4];
+  // metric folded into the momenta: qg = g (2 P_B + P_A), pg = g (2 P_A + P_B)
+  T qg[4], pg[4];
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    q[m] = T(2) * P2[m] + P1[m];
-    p[m] = T(2) * P1[m] + P2[m];
-    d[m] = P1[m] - P2[m];
+    const T sg = m == 0 ? T(1) : T(-1);
+    qg[m] = sg * (T(2) * P2[m] + P1[m]);
+    pg[m] = sg * (T(2) * P1[m] + P2[m]);
   }
   T ab = T(0);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    ab += mdot4(a[k], b[k]);
-    const T qa = mdot4(q, a[k]);
-    const T pb = mdot4(p, b[k]);
+    ab += a[k][0] * b[k][0];
+    ab -= a[k][1] * b[k][1];
+    ab -= a[k][2] * b[k][2];
+    ab -= a[k][3] * b[k][3];
+    T qa = qg[0] * a[k][0];
+    T pb = pg[0] * b[k][0];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) outJ[m] += qa * b[k][m] - pb * a[k][m];
+    for (int m = 1; m < 4; ++m) {
+      qa += qg[m] * a[k][m];
+      pb += pg[m] * b[k][m];
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      outJ[m] += qa * b[k][m];
+      outJ[m] -= pb * a[k][m];
+    }
   }
 #pragma unroll
-  for (int m = 0; m < 4; ++m) outJ[m] += ab * d[m];
+  for (int m = 0; m < 4; ++m) outJ[m] += ab * (P1[m] - P2[m]);
   if (__popc(B) >= 2) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      T t[6], X[4];
+      T t[6];
 #pragma unroll
       for (int c = 0; c < 6; ++c) t[c] = st[L::oT + 54 * B + 18 * k + 6 * j + c];
-      jt_contract(a[k], t, X);
-#pragma unroll
-      for (int m = 0; m < 4; ++m) outJ[m] += X[m];
+      jt_accumulate(a[k], t, T(1), outJ);
     }
   }
   if (__popc(A) >= 2) {
     // sum_a g_aa T1^{a nu} J2^a = -sum_a g_aa T1^{nu a} J2^a
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      T t[6], X[4];
+      T t[6];
 #pragma unroll
       for (int c = 0; c < 6; ++c) t[c] = st[L::oT + 54 * A + 18 * i + 6 * k + c];
-      jt_contract(b[k], t, X);
-#pragma unroll
-      for (int m = 0; m < 4; ++m) outJ[m] -= X[m];
+      jt_accumulate(b[k], t, T(-1), outJ);
     }
   }
   if (want_t) {
@@ -178,7 +192,10 @@ __device__ __forceinline__ void split_term(const T* __restrict__ st, int A, int 
 #pragma unroll
       for (int x = 0; x < 4; ++x) {
 #pragma unroll
-        for (int y = x + 1; y < 4; ++y) outT[pidx(x, y)] += a[k][x] * b[k][y] - a[k][y] * b[k][x];
+        for (int y = x + 1; y < 4; ++y) {
+          outT[pidx(x, y)] += a[k][x] * b[k][y];
+          outT[pidx(x, y)] -= a[k][y] * b[k][x];
+        }
       }
     }
   }
