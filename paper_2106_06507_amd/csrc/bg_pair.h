@@ -61,12 +61,15 @@ __device__ __forceinline__ Cx<T> hrdot(const HR<T>& p, const H<T>& a, T g0) {
   return Cx<T>{pr + xswap(pr), pi + xswap(pi)};
 }
 
+// acc += s v with one multiply-add per real product
 template <typename T>
 __device__ __forceinline__ void caxpy(H<T>& acc, const Cx<T>& s, const H<T>& v) {
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
-    acc.re[m] += s.re * v.re[m] - s.im * v.im[m];
-    acc.im[m] += s.re * v.im[m] + s.im * v.re[m];
+    acc.re[m] += s.re * v.re[m];
+    acc.re[m] -= s.im * v.im[m];
+    acc.im[m] += s.re * v.im[m];
+    acc.im[m] += s.im * v.re[m];
   }
 }
 

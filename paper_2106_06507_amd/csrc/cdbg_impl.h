@@ -95,39 +95,39 @@ __device__ __forceinline__ Sm<N, T> carve(unsigned char* raw) {
   return s;
 }
 
+// g += s t j for complex t, j and a real sign s, one multiply-add per real
+// product
+template <typename T>
+__device__ __forceinline__ void cmac(T& gr, T& gi, T s, T tr, T ti, T jr, T ji) {
+  const T str = s * tr, sti = s * ti;
+  gr += str * jr;
+  gr -= sti * ji;
+  gi += str * ji;
+  gi += sti * jr;
+}
+
 // (T.J)^nu = T^{nu beta} g_beta beta J^beta for antisymmetric T stored as
 // components (01, 02, 03, 12, 13, 23); acc += sgn * T.J (complex).
 template <typename T>
 __device__ __forceinline__ void tdotj_acc(T* gre, T* gim, const T* tre, const T* tim,
                                           const T* jre, const T* jim, T sgn) {
-  // complex product helper: (a + ib)(c + id)
-#define BG_CM(ar, ai, br, bi, outr, outi) \
-  outr = (ar) * (br) - (ai) * (bi);      \
-  outi = (ar) * (bi) + (ai) * (br);
-  T r, i, sr, si;
+  const T m = -sgn;
   // nu = 0: -(T01 J1 + T02 J2 + T03 J3)
-  sr = 0; si = 0;
-  BG_CM(tre[0], tim[0], jre[1], jim[1], r, i) sr += r; si += i;
-  BG_CM(tre[1], tim[1], jre[2], jim[2], r, i) sr += r; si += i;
-  BG_CM(tre[2], tim[2], jre[3], jim[3], r, i) sr += r; si += i;
-  gre[0] -= sgn * sr; gim[0] -= sgn * si;
+  cmac(gre[0], gim[0], m, tre[0], tim[0], jre[1], jim[1]);
+  cmac(gre[0], gim[0], m, tre[1], tim[1], jre[2], jim[2]);
+  cmac(gre[0], gim[0], m, tre[2], tim[2], jre[3], jim[3]);
   // nu = 1: -T01 J0 - T12 J2 - T13 J3
-  sr = 0; si = 0;
-  BG_CM(tre[0], tim[0], jre[0], jim[0], r, i) sr += r; si += i;
-  BG_CM(tre[3], tim[3], jre[2], jim[2], r, i) sr += r; si += i;
-  BG_CM(tre[4], tim[4], jre[3], jim[3], r, i) sr += r; si += i;
-  gre[1] -= sgn * sr; gim[1] -= sgn * si;
+  cmac(gre[1], gim[1], m, tre[0], tim[0], jre[0], jim[0]);
+  cmac(gre[1], gim[1], m, tre[3], tim[3], jre[2], jim[2]);
+  cmac(gre[1], gim[1], m, tre[4], tim[4], jre[3], jim[3]);
   // nu = 2: -T02 J0 + T12 J1 - T23 J3
-  BG_CM(tre[1], tim[1], jre[0], jim[0], r, i) sr = -r; si = -i;
-  BG_CM(tre[3], tim[3], jre[1], jim[1], r, i) sr += r; si += i;
-  BG_CM(tre[5], tim[5], jre[3], jim[3], r, i) sr -= r; si -= i;
-  gre[2] += sgn * sr; gim[2] += sgn * si;
+  cmac(gre[2], gim[2], m, tre[1], tim[1], jre[0], jim[0]);
+  cmac(gre[2], gim[2], sgn, tre[3], tim[3], jre[1], jim[1]);
+  cmac(gre[2], gim[2], m, tre[5], tim[5], jre[3], jim[3]);
   // nu = 3: -T03 J0 + T13 J1 + T23 J2
-  BG_CM(tre[2], tim[2], jre[0], jim[0], r, i) sr = -r; si = -i;
-  BG_CM(tre[4], tim[4], jre[1], jim[1], r, i) sr += r; si += i;
-  BG_CM(tre[5], tim[5], jre[2], jim[2], r, i) sr += r; si += i;
-  gre[3] += sgn * sr; gim[3] += sgn * si;
-#undef BG_CM
+  cmac(gre[3], gim[3], m, tre[2], tim[2], jre[0], jim[0]);
+  cmac(gre[3], gim[3], sgn, tre[4], tim[4], jre[1], jim[1]);
+  cmac(gre[3], gim[3], sgn, tre[5], tim[5], jre[2], jim[2]);
 }
 
 // The x-th subset of S in the order of the binary counter over S's bits
@@ -205,8 +205,10 @@ __device__ __forceinline__ void split_contrib(const Sm<N, T>& sm, int m1, int m2
   T c2r = (T(2) * P1[0] + P2[0]) * b_re[0], c2i = (T(2) * P1[0] + P2[0]) * b_im[0];
 #pragma unroll
   for (int mu = 1; mu < 4; ++mu) {
-    abr -= a_re[mu] * b_re[mu] - a_im[mu] * b_im[mu];
-    abi -= a_re[mu] * b_im[mu] + a_im[mu] * b_re[mu];
+    abr -= a_re[mu] * b_re[mu];
+    abr += a_im[mu] * b_im[mu];
+    abi -= a_re[mu] * b_im[mu];
+    abi -= a_im[mu] * b_re[mu];
     const T q = T(2) * P2[mu] + P1[mu], p = T(2) * P1[mu] + P2[mu];
     c1r -= q * a_re[mu];
     c1i -= q * a_im[mu];
@@ -216,8 +218,16 @@ __device__ __forceinline__ void split_contrib(const Sm<N, T>& sm, int m1, int m2
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
     const T d = P1[mu] - P2[mu];
-    gre[mu] += abr * d + (c1r * b_re[mu] - c1i * b_im[mu]) - (c2r * a_re[mu] - c2i * a_im[mu]);
-    gim[mu] += abi * d + (c1r * b_im[mu] + c1i * b_re[mu]) - (c2r * a_im[mu] + c2i * a_re[mu]);
+    gre[mu] += abr * d;
+    gre[mu] += c1r * b_re[mu];
+    gre[mu] -= c1i * b_im[mu];
+    gre[mu] -= c2r * a_re[mu];
+    gre[mu] += c2i * a_im[mu];
+    gim[mu] += abi * d;
+    gim[mu] += c1r * b_im[mu];
+    gim[mu] += c1i * b_re[mu];
+    gim[mu] -= c2r * a_im[mu];
+    gim[mu] -= c2i * a_re[mu];
   }
   // tensor couplings: + T2.J1 - T1.J2
   const T* T1 = sm.Tt + (m1 * 3 + s1) * 12;
@@ -244,8 +254,14 @@ __device__ __forceinline__ void split_contrib(const Sm<N, T>& sm, int m1, int m2
 #pragma unroll
     for (int x = 0; x < 6; ++x) {
       const int a = ia[x], b = ib[x];
-      tre[x] += (a_re[a] * b_re[b] - a_im[a] * b_im[b]) - (a_re[b] * b_re[a] - a_im[b] * b_im[a]);
-      tim[x] += (a_re[a] * b_im[b] + a_im[a] * b_re[b]) - (a_re[b] * b_im[a] + a_im[b] * b_re[a]);
+      tre[x] += a_re[a] * b_re[b];
+      tre[x] -= a_im[a] * b_im[b];
+      tre[x] -= a_re[b] * b_re[a];
+      tre[x] += a_im[b] * b_im[a];
+      tim[x] += a_re[a] * b_im[b];
+      tim[x] += a_im[a] * b_re[b];
+      tim[x] -= a_re[b] * b_im[a];
+      tim[x] -= a_im[b] * b_re[a];
     }
   }
 }

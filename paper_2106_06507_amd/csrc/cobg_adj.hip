@@ -90,8 +90,10 @@ __device__ __forceinline__ Cx<T> psum(const H<T>& a, const H<T>& b) {
   T r = 0, i = 0;
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
-    r += a.re[m] * b.re[m] - a.im[m] * b.im[m];
-    i += a.re[m] * b.im[m] + a.im[m] * b.re[m];
+    r += a.re[m] * b.re[m];
+    r -= a.im[m] * b.im[m];
+    i += a.re[m] * b.im[m];
+    i += a.im[m] * b.re[m];
   }
   return Cx<T>{pair_sum(r), pair_sum(i)};
 }
@@ -112,8 +114,10 @@ template <typename T>
 __device__ __forceinline__ void axpy(H<T>& y, Cx<T> s, const H<T>& x) {
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
-    y.re[m] += s.re * x.re[m] - s.im * x.im[m];
-    y.im[m] += s.re * x.im[m] + s.im * x.re[m];
+    y.re[m] += s.re * x.re[m];
+    y.re[m] -= s.im * x.im[m];
+    y.im[m] += s.re * x.im[m];
+    y.im[m] += s.im * x.re[m];
   }
 }
 
@@ -123,8 +127,11 @@ __device__ __forceinline__ void axpyg(H<T>& y, Cx<T> s, const H<T>& x, T g0) {
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
     const T g = gm(g0, m);
-    y.re[m] += g * (s.re * x.re[m] - s.im * x.im[m]);
-    y.im[m] += g * (s.re * x.im[m] + s.im * x.re[m]);
+    const T gr = g * s.re, gi = g * s.im;
+    y.re[m] += gr * x.re[m];
+    y.re[m] -= gi * x.im[m];
+    y.im[m] += gr * x.im[m];
+    y.im[m] += gi * x.re[m];
   }
 }
 
@@ -153,8 +160,16 @@ __device__ __forceinline__ void v3(H<T>& acc, const HR<T>& P, const HR<T>& Q, co
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
     const T d = P.v[m] - Q.v[m];
-    acc.re[m] += s.re * d + (c1.re * B.re[m] - c1.im * B.im[m]) - (c2.re * A.re[m] - c2.im * A.im[m]);
-    acc.im[m] += s.im * d + (c1.re * B.im[m] + c1.im * B.re[m]) - (c2.re * A.im[m] + c2.im * A.re[m]);
+    acc.re[m] += s.re * d;
+    acc.re[m] += c1.re * B.re[m];
+    acc.re[m] -= c1.im * B.im[m];
+    acc.re[m] -= c2.re * A.re[m];
+    acc.re[m] += c2.im * A.im[m];
+    acc.im[m] += s.im * d;
+    acc.im[m] += c1.re * B.im[m];
+    acc.im[m] += c1.im * B.re[m];
+    acc.im[m] -= c2.re * A.im[m];
+    acc.im[m] -= c2.im * A.re[m];
   }
 }
 
