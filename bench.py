@@ -185,7 +185,11 @@ def section_headline(args, api, wm, torch):
                      "note": "FP32 recursion flops + 2 x FP64 colour-sum flops per event "
                              "(FP64 vector rate is half the FP32 rate); the published FP32 "
                              "peak counts packed FP32 instructions, which this build does not "
-                             "emit"},
+                             "emit.  The flops are those of the vertex formulas as written per "
+                             "vertex; the kernel shares the dot products of a range's splits "
+                             "(coefficient collection) and fuses every product into a "
+                             "multiply-add, so it executes fewer operations than counted and "
+                             "frac_without_packed_fp32 can exceed 1"},
         "roofline_fp64": {"bound": "alu", "kernel": "cobg_fused_kernel<6,double,false>",
                           "achieved": achieved64, "peak": wm.PEAK_FP64_VALU_TFLOPS,
                           "unit": "TFLOP/s", "frac": achieved64 / wm.PEAK_FP64_VALU_TFLOPS},
