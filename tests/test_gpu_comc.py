@@ -14,7 +14,7 @@ import pytest
 
 from bg_inputs import make_events
 from oracle import cdbg as ocdbg
-from tests.helpers import valid_colours, nonvanishing
+from tests.helpers import valid_colours, nonvanishing, mhv_helicities
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -124,3 +124,47 @@ def test_rejects_missing_colours(api):
     ev = make_events(5, 10, seed=7400, cuts=True)
     with pytest.raises(Exception):
         api.me2(_dev(ev["mom"]), _dev(ev["hel"]), None, mode="comc")
+
+
+def test_degenerate_flows(api):
+    """Flows with the most closing orderings, against the dressed path on
+    the same assignments: every gluon (1, 1) (all 40320 orderings close at
+    n = 9; the amplitude vanishes by U(1) decoupling, both sides give
+    rounding noise), a two-colour cycle with seven loops (5040 orderings),
+    and ordinary closed flows."""
+    n, E = 9, 64
+    ev = make_events(n, E, seed=7500, cuts=True, sample_hel=True)
+    col = valid_colours(n, E, np.random.default_rng(75))
+    col[:, :, 0:4] = 1
+    col[:, :, 4:8] = 1
+    col[0, 0, 4:8], col[1, 0, 4:8] = 1, 0   # gluon 1: colour 0 -> 1
+    col[0, 1, 4:8], col[1, 1, 4:8] = 0, 1   # gluon 2: colour 1 -> 0
+    m, h, c = _dev(ev["mom"]), _dev(ev["hel"]), _dev(col)
+    _say(f"bg_me2 comc degenerate flows n={n} E={E}")
+    a = api.me2(m, h, c, mode="comc").cpu().numpy()
+    b = api.me2(m, h, c, mode="cdbg").cpu().numpy()
+    typical = np.median(np.abs(b[8:]))
+    assert np.all(np.abs(a[0:4]) < 1e-8 * typical) and np.all(np.abs(b[0:4]) < 1e-8 * typical)
+    keep = nonvanishing(ev["hel"]) & (np.abs(b) > 1e-8 * typical)
+    keep[0:4] = False
+    rel = np.abs(a - b)[keep] / np.abs(b[keep])
+    _say(f"  kept {keep.sum()} (two-colour {keep[4:8].sum()}), rel diff median "
+         f"{np.median(rel):.2e} max {rel.max():.2e}")
+    assert keep[8:].sum() > 20
+    assert np.median(rel) < 1e-12 and rel.max() < 1e-9
+
+
+def test_all_invalid_and_single_event(api):
+    """No valid flow at all (no items: the call returns after the count) and
+    a single event."""
+    n, E = 6, 40
+    ev = make_events(n, E, seed=7600, cuts=True)
+    col = np.zeros((2, n, E), dtype=np.int8)
+    col[1, 0, :] = 1  # gluon 1 leaves colour 1 but nothing returns to it: unbalanced
+    got = api.me2(_dev(ev["mom"]), _dev(ev["hel"]), _dev(col), mode="comc").cpu().numpy()
+    assert np.all(got == 0.0)
+    col1 = valid_colours(n, 1, np.random.default_rng(76))
+    h1 = mhv_helicities(n, 1, np.random.default_rng(77))
+    one = api.me2(_dev(ev["mom"][:, :, :1]), _dev(h1), _dev(col1), mode="comc").cpu().numpy()
+    ref = np.abs(ocdbg.flow_amplitude(ev["mom"][:, :, :1], h1, col1)) ** 2
+    assert abs(one[0] - ref[0]) <= 1e-12 * abs(ref[0])
