@@ -445,8 +445,8 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
       }
     }
     __syncthreads();
-    // q adjacent lanes of one wave per target, each taking every q-th split
-    // directly (no lane walks the splits it does not evaluate)
+    // q adjacent lanes of one wave per target, each taking a contiguous
+    // range of its splits
     int q = nitems == 0 ? 1 : NL / nitems;
     q = q < 1 ? 1 : (q > kWave ? kWave : q);
     const int gpw = kWave / q;  // targets per wave and round
@@ -464,8 +464,13 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
         const int item = sm.items[it];
         S = item >> 2;
         t = item & 3;
-        for (int k = sub; k < nsplit; k += q) {
-          const int m1 = subset_of<M>(k + 1, S);
+        // a contiguous range of splits per lane: the first sub-mask is
+        // deposited into S's bits, the next ones follow as (m1 - S) & S
+        const int per = (nsplit + q - 1) / q;
+        const int k0 = sub * per;
+        const int k1 = k0 + per < nsplit ? k0 + per : nsplit;
+        int m1 = k0 < k1 ? subset_of<M>(k0 + 1, S) : 0;
+        for (int k = k0; k < k1; ++k, m1 = (m1 - S) & S) {
           const int m2 = S ^ m1;
           int s1, s2;
           if (!split_slots(sm.code[m1], sm.code[m2], t, s1, s2)) continue;
