@@ -24,9 +24,10 @@ def _unit(u_cos, u_az):
     return np.stack([c, s * np.cos(a), s * np.sin(a)])  # [3][E]
 
 
-def continuous_states(n, n_events, seed):
-    """(phi [n][E], eta [2][n][3][E]) for events 0 .. n_events-1 of stream seed."""
-    ctr = np.arange(n_events, dtype=np.uint64)
+def continuous_states(n, n_events, seed, first=0):
+    """(phi [n][E], eta [2][n][3][E]) for events first .. first+n_events-1 of
+    stream seed."""
+    ctr = np.arange(first, first + n_events, dtype=np.uint64)
     u = splitmix64_uniform(seed, ctr, 5 * n)  # [E, 5n]
     phi = np.empty((n, n_events))
     eta = np.empty((2, n, 3, n_events))

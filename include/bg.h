@@ -254,6 +254,16 @@ int bg_generate(bg_context* ctx, const bg_gen_params* params, int64_t n_attempts
 int bg_me2_continuous(bg_context* ctx, int n, int precision, int64_t n_events, const double* mom,
                       const double* phi, const double* eta, double* me2, void* stream);
 
+/* The continuous variables of bg_me2_continuous, drawn on the device from
+ * the same keyed SplitMix64 stream as bg_generate: event e uses counter
+ * first_event + e and, for gluon k, draws 5k .. 5k+4: phi = 2 pi u, then
+ * (cos theta = 2u - 1, azimuth = 2 pi u) of eta(z_k) and of eta(zbar_k)
+ * (uniform on the sphere, Section 2.1 eq. color_angles).  Writes phi [n][E]
+ * and eta [2][n][3][E] (device pointers, caller-owned).  Stream-ordered,
+ * allocates nothing. */
+int bg_generate_continuous(bg_context* ctx, int n, uint64_t seed, uint64_t first_event,
+                           int64_t n_events, double* phi, double* eta, void* stream);
+
 /* Self-test of the matrix-core operand layout used by bg_color_contract:
  * runs one v_mfma_f64_16x16x4f64 with lane l supplying A[l%16][l/16] =
  * (l%16 + 1) + 100 (l/16) and B[l/16][l%16] = (l%16 + 1) 8^(l/16), and copies

@@ -83,6 +83,7 @@ _SIGNATURES = {
                                ctypes.POINTER(ctypes.c_double), _P]),
     "bg_generate": (_I, [_P, ctypes.POINTER(bg_gen_params), _I64, _I64, _P, _P, _P, _P, _P, _P]),
     "bg_me2_continuous": (_I, [_P, _I, _I, _I64, _P, _P, _P, _P, _P]),
+    "bg_generate_continuous": (_I, [_P, _I, ctypes.c_uint64, ctypes.c_uint64, _I64, _P, _P, _P]),
     "bg_mfma_layout_probe": (_I, [_P, _P]),
 }
 

@@ -298,6 +298,17 @@ def me2_continuous(mom, phi, eta, precision="fp64", out=None, ctx=None):
     return out
 
 
+def generate_continuous(n, n_events, seed, first_event=0, device=None, ctx=None):
+    """(phi [n, E], eta [2, n, 3, E]) drawn on the device for bg_me2_continuous."""
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    ctx = ctx or default_context(dev.index)
+    phi = torch.empty((n, n_events), dtype=torch.float64, device=dev)
+    eta = torch.empty((2, n, 3, n_events), dtype=torch.float64, device=dev)
+    check(lib().bg_generate_continuous(ctx.handle, n, seed, first_event, n_events, phi.data_ptr(),
+                                       eta.data_ptr(), _stream(dev)), "bg_generate_continuous")
+    return phi, eta
+
+
 def generate(n, n_events, seed, n_attempts=None, first_attempt=0, cuts=True, sample_hel=True,
              sample_col=False, sqrt_s=1000.0, pt_min=20.0, dr_min=0.4, with_attempts=False,
              device=None, ctx=None):

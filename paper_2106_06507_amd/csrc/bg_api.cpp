@@ -919,6 +919,21 @@ int bg_me2_continuous(bg_context* ctx, int n, int precision, int64_t n_events, c
                                     (hipStream_t)stream));
 }
 
+int bg_generate_continuous(bg_context* ctx, int n, uint64_t seed, uint64_t first_event,
+                           int64_t n_events, double* phi, double* eta, void* stream) {
+  if (!ctx) return BG_EINVAL;
+  if (!valid_n(n)) return BG_EINVAL;
+  int st = check_events(n, n_events);
+  if (st) return st;
+  if (n_events == 0) return BG_OK;
+  if (!phi || !eta) return BG_EINVAL;
+  if (n_events > ((int64_t)1 << 31) * 256) return BG_ERANGE;  // grid limit
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return BG_EDEVICE;
+  return launch_status(bg::generate_continuous(n, seed, first_event, n_events, phi, eta,
+                                               (hipStream_t)stream));
+}
+
 int bg_generate(bg_context* ctx, const bg_gen_params* gp, int64_t n_attempts, int64_t max_events,
                 double* mom, int8_t* hel, int8_t* col, int64_t* attempt, int64_t* n_generated,
                 void* stream) {

@@ -137,6 +137,10 @@ int cdmc_blocks_per_cu(int n, bool fp32);
 int cdmc_me2(int n, bool fp32, int64_t E, const double* mom, const double* phi, const double* eta,
              void* gstate, int grid, double* me2, hipStream_t stream);
 
+// Continuous colour / polarization variables on the device (rambo.hip).
+int generate_continuous(int n, uint64_t seed, uint64_t first, int64_t E, double* phi, double* eta,
+                        hipStream_t stream);
+
 // On-device phase-space generation (rambo.hip).
 struct GenParams {
   int n;

@@ -237,6 +237,45 @@ int launch(const GenParams& gp, int64_t n_attempts, int64_t max_events, unsigned
 
 }  // namespace genk
 
+namespace genk {
+
+// Continuous colour and polarization variables of event t = first + e:
+// draws 5k .. 5k+4 of the event's stream for gluon k: phi = 2 pi u, then
+// (cos theta, azimuth) of eta(z_k) and of eta(zbar_k) with
+// cos theta = 2u - 1, azimuth 2 pi u (uniform on the unit sphere, Section
+// 2.1 eq. color_angles).  phi [n][E], eta [2][n][3][E].
+__global__ void __launch_bounds__(kThreads) continuous_kernel(int n, uint64_t seed, uint64_t first,
+                                                             int64_t E, double* __restrict__ phi,
+                                                             double* __restrict__ eta) {
+  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (e >= E) return;
+  const Stream st = stream_of(seed, first + (uint64_t)e);
+  for (int k = 0; k < n; ++k) {
+    phi[(int64_t)k * E + e] = 2.0 * M_PI * st.uniform(5 * k);
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const double c = 2.0 * st.uniform(5 * k + 1 + 2 * v) - 1.0;
+      const double sn = sqrt(fmax(0.0, 1.0 - c * c));
+      const double a = 2.0 * M_PI * st.uniform(5 * k + 2 + 2 * v);
+      double* out = eta + ((int64_t)(v * n + k) * 3) * E + e;
+      out[0] = c;
+      out[E] = sn * cos(a);
+      out[2 * E] = sn * sin(a);
+    }
+  }
+}
+
+}  // namespace genk
+
+int generate_continuous(int n, uint64_t seed, uint64_t first, int64_t E, double* phi, double* eta,
+                        hipStream_t stream) {
+  if (E <= 0) return 0;
+  const int64_t blocks = (E + genk::kThreads - 1) / genk::kThreads;
+  hipLaunchKernelGGL(genk::continuous_kernel, dim3((unsigned)blocks), dim3(genk::kThreads), 0, stream,
+                     n, seed, first, E, phi, eta);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 size_t generate_workspace_words(int64_t n_attempts) {
   const int64_t blocks = (n_attempts + genk::kThreads - 1) / genk::kThreads;
   return (size_t)((n_attempts + 31) / 32 + blocks + 1);

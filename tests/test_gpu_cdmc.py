@@ -120,3 +120,24 @@ def test_bad_shapes(api):
         api.me2_continuous(_dev(ev["mom"]), _dev(phi[:4]), _dev(eta))
     out = api.me2_continuous(_dev(ev["mom"][:, :, :0]), _dev(phi[:, :0]), _dev(eta[..., :0]))
     assert out.numel() == 0
+
+
+def test_device_variables_match_host_generator(api):
+    """bg_generate_continuous draws the same variables as the host generator
+    (same keyed stream and draw layout): angles exactly, unit vectors to a
+    few units in the last place of the angle (the two sides' cos and sin
+    differ by that); a resumed range equals the tail of a full one."""
+    n, E, seed = 7, 5000, 2106
+    phi_d, eta_d = api.generate_continuous(n, E, seed, first_event=0)
+    phi_h, eta_h = continuous_states(n, E, seed)
+    assert np.array_equal(phi_d.cpu().numpy(), phi_h)
+    assert np.max(np.abs(eta_d.cpu().numpy() - eta_h)) < 1e-14
+    phi_r, eta_r = api.generate_continuous(n, 1000, seed, first_event=4000)
+    assert torch.equal(phi_r, phi_d[:, 4000:])
+    assert torch.equal(eta_r, eta_d[..., 4000:])
+    # feeding the device variables to the evaluation gives the host-input result
+    ev = make_events(n, 64, seed=8400, cuts=True)
+    m = _dev(ev["mom"])
+    a = api.me2_continuous(m, phi_d[:, :64].contiguous(), eta_d[..., :64].contiguous()).cpu().numpy()
+    b = api.me2_continuous(m, _dev(phi_h[:, :64]), _dev(eta_h[..., :64])).cpu().numpy()
+    assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b))

@@ -76,6 +76,7 @@ def test_entry_points_validate_before_launch():
     gp = _lib.bg_gen_params(6, 1, 1000.0, 20.0, 0.4, 1, 0)
     assert L.bg_generate(None, ctypes.byref(gp), 10, 10, None, None, None, None, None, None) == _lib.BG_EINVAL
     assert L.bg_me2_continuous(None, 6, 0, 10, None, None, None, None, None) == _lib.BG_EINVAL
+    assert L.bg_generate_continuous(None, 6, 1, 0, 10, None, None, None) == _lib.BG_EINVAL
     L.bg_context_destroy(None)  # no-op
 
 
