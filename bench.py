@@ -366,10 +366,8 @@ def section_per_n(args, api, torch):
         rows[str(n)]["colour_sampled_ordered"] = co
         # continuous colours and real polarizations (all-real dressed
         # recursion) on the first Ec of these points
-        from bg_inputs import continuous_states
         Ec = min(E, 1 << (22 - n))
-        phi_c, eta_c = continuous_states(n, Ec, 2106065070 + 60 + n)
-        phi_c, eta_c = torch.from_numpy(phi_c).cuda(), torch.from_numpy(eta_c).cuda()
+        phi_c, eta_c = api.generate_continuous(n, Ec, 2106065070 + 60 + n)
         mom_c = mom[:, :, :Ec].contiguous()
         cres, cms = {}, {}
         for p in ("fp32", "fp64"):
@@ -420,7 +418,6 @@ def section_sampling(args, api, torch):
     events/s of the method (FP32) and the effective rate events/s /
     (1 + median relative variance), i.e. colour- and helicity-exact
     equivalent events per second at a fixed phase-space point."""
-    from bg_inputs import continuous_states
     out = {}
     steps = max(2, args.steps // 8)
     P, R = 64, 4096
@@ -432,8 +429,7 @@ def section_sampling(args, api, torch):
             raise RuntimeError(f"device generator produced too few events at n={n}")
         mom = g["mom"][:, :, :P].repeat_interleave(R, dim=2).contiguous()
         hel, col = g["hel"], g["col"]
-        phi, eta = continuous_states(n, E, 2106065070 + 50 + n)
-        phi, eta = torch.from_numpy(phi).cuda(), torch.from_numpy(eta).cuda()
+        phi, eta = api.generate_continuous(n, E, 2106065070 + 50 + n)
         buf = torch.empty(E, dtype=torch.float64, device="cuda")
         runs = []
         if n <= 7:
