@@ -12,6 +12,12 @@
  *     eq. color_coefficient_adjoint;
  *   - colour-dressed (CDBG, Section 2.3 eq. color_dressed_currents) for one
  *     sampled colour-flow assignment per event (eq. color_decomposition_colorflow).
+ * Beside these: the same flow amplitude as a sum over the colour-ordered
+ * amplitudes whose colour chain closes (BG_MODE_COMC), the leading-colour sum
+ * (BG_MODE_LC), the gradient of the colour-summed |M|^2 (bg_me2_grad), many
+ * multiplicities in one launch (bg_me2_batch), continuous colour and real
+ * polarization sampling (bg_me2_continuous), and phase space and sampled
+ * quantum numbers drawn on the device (bg_generate, bg_generate_continuous).
  *
  * Conventions shared by every entry point
  *   - Pointers named mom/hel/col/amp/me2/grad are DEVICE pointers owned by the

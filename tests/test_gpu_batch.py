@@ -153,6 +153,10 @@ def test_batch_rejects_bad_requests(api):
         api.me2_batch([dict(segs[4], col=None, mode="cdbg")], "fp32")
     with pytest.raises(BGError):
         api.set_batch_config("fp32", cobg_tile_events=48)
+    with pytest.raises(BGError):  # leading colour is not a batch mode
+        api.me2_batch([dict(segs[0], mode="lc")], "fp32")
+    with pytest.raises(BGError):  # nor the colour-sampled colour-ordered one (it synchronises)
+        api.me2_batch([dict(segs[4], mode="comc")], "fp32")
     assert api.me2_batch([], "fp32") == []
 
 
