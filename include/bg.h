@@ -72,7 +72,10 @@ extern "C" {
 #define BG_MODE_COMC 4       /* colour-sampled colour-ordered: the same |A|^2 as CDBG for the
                                 given colour flow, as the sum of A(1, sigma) over the orderings
                                 whose delta chain closes (Section 2.2); col and hel required;
-                                bg_me2 only; synchronises the stream once (item count) */
+                                bg_me2 only; synchronises the stream once per call (item count)
+                                and the device when its item buffers grow; refused (BG_EINVAL)
+                                while the stream is being captured; BG_ERANGE beyond 2^31
+                                (event, ordering) items per call */
 
 /* arithmetic of the recursion; contraction and |M|^2 sums are always FP64 */
 #define BG_PREC_FP64       0
@@ -253,7 +256,8 @@ int bg_generate(bg_context* ctx, const bg_gen_params* params, int64_t n_attempts
  * helicity-summed |M|^2 (each sphere integral carries N_c).  n in [4, 9];
  * both precisions (FP32: currents in FP32, invariants 1/P^2 and the final
  * contraction in FP64).  The first FP64 call at n = 9 allocates a per-block
- * state buffer in the context (its state exceeds the LDS).  One event per
+ * state buffer in the context (its state exceeds the LDS), synchronising the
+ * device; later calls allocate nothing.  One event per
  * workgroup; every split of every subset costs a 3x3 colour-matrix product,
  * so this is compute-bound and far costlier per event than CDBG, but no
  * sampled event has a zero weight. */
