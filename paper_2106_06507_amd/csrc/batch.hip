@@ -22,7 +22,7 @@ __global__ void __launch_bounds__(64) cobg_fused_kernel(int64_t E, const double*
 // n = 7: persistent blocks, each with its own scratch slice, take tiles from
 // an atomic queue (reset by zero_counter_kernel before the launch).
 template <typename T, bool HSUM>
-__global__ void __launch_bounds__(64) cobg_fused_queue_kernel(int64_t E,
+__global__ void __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) cobg_fused_queue_kernel(int64_t E,
                                                              const double* __restrict__ mom,
                                                              const int8_t* __restrict__ hel,
                                                              const double* __restrict__ Cb,
