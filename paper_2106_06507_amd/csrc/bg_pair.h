@@ -53,6 +53,21 @@ __device__ __forceinline__ Cx<T> hdot(const H<T>& a, const H<T>& b, T g0) {
   return Cx<T>{pr + xswap(pr), pi + xswap(pi)};
 }
 
+// hdot(a, b, g0) with the lane's first component of b pre-multiplied by its
+// metric sign: bg = g0 (b.re[0], b.im[0]); one multiply-add per real product
+template <typename T>
+__device__ __forceinline__ Cx<T> hdot_g(const H<T>& a, const H<T>& b, const Cx<T>& bg) {
+  T pr = a.im[1] * b.im[1];
+  pr -= a.re[1] * b.re[1];
+  pr -= a.im[0] * bg.im;
+  pr += a.re[0] * bg.re;
+  T pi = a.re[0] * bg.im;
+  pi += a.im[0] * bg.re;
+  pi -= a.re[1] * b.im[1];
+  pi -= a.im[1] * b.re[1];
+  return Cx<T>{pr + xswap(pr), pi + xswap(pi)};
+}
+
 // full product p.J of a real and a complex four-vector
 template <typename T>
 __device__ __forceinline__ Cx<T> hrdot(const HR<T>& p, const H<T>& a, T g0) {

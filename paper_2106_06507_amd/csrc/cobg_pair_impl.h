@@ -104,8 +104,15 @@ struct State {
   Cx<T> Dt[M][M][M];  // [a][b][k] = J(a..k).J(k+1..b)
   HR<double> P0[M];   // prefix momenta P(0..b), FP64 halves
   HR<T> Pg[M];        // momentum half of the gluon at each position
+  Cx<T> Gd[M];        // [a]: g0 times the lane's first component of J(a..d), d the
+                      // column being built (the right operand of its products)
   int gl[M];          // gluon at each position (wave-uniform)
 };
+
+template <int N, typename T, int A, int D, class CtxT>
+__device__ __forceinline__ void set_gd(State<N, T>& s, const CtxT& c) {
+  s.Gd[A] = Cx<T>{c.g0 * s.J[A][D].re[0], c.g0 * s.J[A][D].im[0]};
+}
 
 template <int N, typename T, int A, int B>
 __device__ __forceinline__ HR<T> range_mom(const State<N, T>& s) {
@@ -142,7 +149,7 @@ __device__ __forceinline__ void build_range(State<N, T>& s, const CtxT& c, int m
           constexpr int k = A + Ks;
           const HR<T> PL = range_mom<N, T, A, k>(s);
           const HR<T> PR = range_mom<N, T, k + 1, D>(s);
-          const Cx<T> d = hdot(s.J[A][k], s.J[k + 1][D], c.g0);
+          const Cx<T> d = hdot_g(s.J[A][k], s.J[k + 1][D], s.Gd[k + 1]);
           if constexpr (!kTop && !CtxT::kNoDt) s.Dt[A][D][k] = d;
           HR<T> q2p, p2q, dif;
 #pragma unroll
@@ -166,12 +173,12 @@ __device__ __forceinline__ void build_range(State<N, T>& s, const CtxT& c, int m
       Cx<T> xy, yz;
       if constexpr (CtxT::kNoDt) {
         xy = hdot(s.J[A][j], s.J[j + 1][k], c.g0);
-        yz = hdot(s.J[j + 1][k], s.J[k + 1][D], c.g0);
+        yz = hdot_g(s.J[j + 1][k], s.J[k + 1][D], s.Gd[k + 1]);
       } else {
         xy = s.Dt[A][k][j];
         yz = s.Dt[j + 1][D][k];
       }
-      const Cx<T> xz = hdot(s.J[A][j], s.J[k + 1][D], c.g0);
+      const Cx<T> xz = hdot_g(s.J[A][j], s.J[k + 1][D], s.Gd[k + 1]);
       coefL[j - A].re -= yz.re;
       coefL[j - A].im -= yz.im;
       coefR[k - A].re -= xy.re;
@@ -204,6 +211,7 @@ __device__ __forceinline__ void build_range(State<N, T>& s, const CtxT& c, int m
       s.J[A][D].re[m] = acc.re[m] * ip2;
       s.J[A][D].im[m] = acc.im[m] * ip2;
     }
+    set_gd<N, T, A, D>(s, c);
   }
 }
 
@@ -237,6 +245,7 @@ __device__ __forceinline__ void level(State<N, T>& s, CtxT& c, int used) {
         pg = c.p64[(2 * (g - 1) + m) * Lds<N>::kLanes + c.lane];
       s.P0[D].v[m] = s.P0[D - 1].v[m] + pg;
     }
+    set_gd<N, T, D, D>(s, c);
     Cx<T> top;
     if constexpr (CtxT::kLC && D == M - 1) {
       // the one gluon not yet placed closes the ordering

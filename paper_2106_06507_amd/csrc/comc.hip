@@ -349,6 +349,7 @@ __device__ __forceinline__ void path(pairk::State<N, T>& s, C& c, uint32_t code,
     s.Pg[D].v[m] = c.gl_slots[(base + 4 + m) * 64 + c.lane];
     s.P0[D].v[m] = s.P0[D - 1].v[m] + c.p64[(2 * (g - 1) + m) * 64 + c.lane];
   }
+  pairk::set_gd<N, T, D, D>(s, c);
   if constexpr (D == M - 1) {
     // the ordering's last gluon closes it
     int gl = (int)((code >> (4 * (N - 2))) & 15u);

@@ -119,7 +119,10 @@ def test_helicity_sum_fused(api, n):
 def test_fused_equals_two_stage(api, n, precision):
     """bg_me2 (recursion and colour sum in one kernel) against bg_currents
     followed by bg_color_contract (amplitudes through memory, matrix cores at
-    n = 6): same amplitudes, colour sums in a different order."""
+    n = 6): the same recursion, colour sums in a different order.  In FP64
+    the two agree to rounding of the sums; in FP32 the compiler may fuse a
+    product into a different multiply-add in the two kernels, so they agree
+    to FP32 rounding amplified by the event's cancellations."""
     E = 1000 if n < 7 else 200
     mom, hel = _events(n, E, 3180 + n)
     dm, dh = _dev(mom), _dev(hel)
@@ -128,8 +131,11 @@ def test_fused_equals_two_stage(api, n, precision):
     two = api.color_contract(api.currents(dm, dh, precision), n).cpu().numpy()
     nz = nonvanishing(hel)
     rel = np.abs(fused - two)[nz] / np.abs(two[nz])
-    _say(f"  max rel {rel.max():.2e}")
-    assert rel.max() < 1e-12
+    _say(f"  max rel {rel.max():.2e} median {np.median(rel):.2e}")
+    if precision == "fp64":
+        assert rel.max() < 1e-12
+    else:
+        assert np.median(rel) < 1e-6 and rel.max() < 1e-4
 
 
 @pytest.mark.parametrize("n", [5, 6])
