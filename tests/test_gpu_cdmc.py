@@ -141,3 +141,22 @@ def test_device_variables_match_host_generator(api):
     a = api.me2_continuous(m, phi_d[:, :64].contiguous(), eta_d[..., :64].contiguous()).cpu().numpy()
     b = api.me2_continuous(m, _dev(phi_h[:, :64]), _dev(eta_h[..., :64])).cpu().numpy()
     assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b))
+
+
+@pytest.mark.parametrize("n", [4, 5, 6, 7, 8, 9])
+def test_single_event(api, n):
+    """One event per call (grid of one workgroup), every multiplicity."""
+    ev = make_events(n, 1, seed=8500 + n, cuts=True)
+    phi, eta = continuous_states(n, 1, 85 + n)
+    ref = ocdmc.me2_continuous(ev["mom"], phi, eta)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-3)):
+        got = api.me2_continuous(_dev(ev["mom"]), _dev(phi), _dev(eta), precision=prec).cpu().numpy()
+        assert abs(got[0] - ref[0]) <= tol * abs(ref[0]), (prec, got[0], ref[0])
+
+
+def test_generate_continuous_edges(api):
+    from paper_2106_06507_amd._lib import BGError
+    phi, eta = api.generate_continuous(5, 0, 1)
+    assert phi.shape == (5, 0) and eta.shape == (2, 5, 3, 0)
+    with pytest.raises(BGError):
+        api.generate_continuous(3, 10, 1)
