@@ -16,7 +16,7 @@ import pytest
 
 from bg_inputs import make_events, workload
 from oracle import cdbg as ocdbg
-from tests.helpers import valid_colours, nonvanishing
+from tests.helpers import valid_colours, nonvanishing, mhv_helicities
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -121,3 +121,15 @@ def test_full_size_gg_6g_sampled(api):
     ref = np.abs(ocdbg.flow_amplitude(mom[:, :, idx], hel[:, idx], col[:, :, idx])) ** 2
     _check(g64[idx], ref, hel[:, idx], "fp64", "full")
     _check(g32[idx], ref, hel[:, idx], "fp32", "full")
+
+
+@pytest.mark.parametrize("n", [4, 6, 8, 9])
+def test_single_event(api, n):
+    """One event per call (a grid of one block) on a closed colour flow."""
+    ev = make_events(n, 1, seed=5300 + n, cuts=True)
+    col = valid_colours(n, 1, np.random.default_rng(53 + n))
+    hel = mhv_helicities(n, 1, np.random.default_rng(54 + n))
+    ref = np.abs(ocdbg.flow_amplitude(ev["mom"], hel, col)) ** 2
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-3)):
+        got = api.me2(_dev(ev["mom"]), _dev(hel), _dev(col), mode="cdbg", precision=prec).cpu().numpy()
+        assert abs(got[0] - ref[0]) <= tol * abs(ref[0]), (prec, got[0], ref[0])

@@ -19,7 +19,7 @@ import pytest
 from bg_inputs import make_events, workload
 from oracle import cobg as ocobg
 from oracle import me2 as ome2
-from tests.helpers import nonvanishing, helicity_scale
+from tests.helpers import nonvanishing, helicity_scale, mhv_helicities
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -200,3 +200,17 @@ def test_full_size_gg_4g_sampled(api):
     _check_sampled(g64[idx], ref, scale, nz, "fp64")
     _check_sampled(g32[idx], ref, scale, nz, "fp32")
     assert np.all(np.isfinite(g64)) and np.all(np.isfinite(g32))
+
+
+@pytest.mark.parametrize("n", [4, 5, 6, 7])
+def test_single_event(api, n):
+    """One event per call: a single partial tile (and for n = 7 a single
+    queue entry), helicity-summed and sampled."""
+    mom, hel = _events(n, 1, 3300 + n)
+    hel = mhv_helicities(n, 1, np.random.default_rng(33 + n))
+    dm = _dev(mom)
+    for h in (hel, None):
+        ref = ome2.me2_cobg(mom, h)
+        for prec, tol in (("fp64", 1e-12), ("fp32", 1e-4)):
+            got = api.me2(dm, None if h is None else _dev(h), precision=prec).cpu().numpy()
+            assert abs(got[0] - ref[0]) <= tol * abs(ref[0]), (prec, h is None, got[0], ref[0])
