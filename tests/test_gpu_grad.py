@@ -143,3 +143,13 @@ def test_full_size_adjoint_sampled(api):
     idx = np.sort(np.random.default_rng(11).choice(ok, 6, replace=False))
     f, gref = ograd.me2_and_grad(mom[:, :, idx], hel[:, idx])
     _compare(g[:, :, idx], gref, f, mom[:, :, idx], "full fp64", 1e-11, 1e-7)
+
+
+def test_gradient_single_event(api):
+    """One event per call (a single partial tile of the adjoint kernel)."""
+    n = 6
+    mom, hel = _nonvanishing_events(n, 1, 6700)
+    me2, g = api.me2_grad(_dev(mom), _dev(hel))
+    f, gref = ograd.me2_and_grad(mom, hel)
+    assert abs(me2.cpu().numpy()[0] - f[0]) <= 1e-12 * abs(f[0])
+    _compare(g.cpu().numpy(), gref, f, mom, "single event fp64", 1e-11, 1e-7)

@@ -69,3 +69,14 @@ def test_lc_rejections(api):
     ev = make_events(6, 10, seed=1)
     with pytest.raises(BGError):  # helicities required
         api.me2(_dev(ev["mom"]), None, mode="lc")
+
+
+@pytest.mark.parametrize("n", [4, 5, 6, 7])
+def test_lc_single_event(api, n):
+    """One event per call (a single partial tile)."""
+    ev = make_events(n, 40, seed=8300 + n)
+    k = int(np.nonzero(nonvanishing(ev["hel"]))[0][0])
+    mom, hel = ev["mom"][:, :, k:k + 1], ev["hel"][:, k:k + 1]
+    ref = ome2.me2_leading_colour(mom, hel)
+    got = api.me2(_dev(mom), _dev(hel), mode="lc", precision="fp64").cpu().numpy()
+    assert abs(got[0] - ref[0]) <= 1e-12 * abs(ref[0])
