@@ -33,6 +33,7 @@ import numpy as np
 
 from .cobg import G_S, momenta_list, external_currents, ordered_amplitude
 from .lorentz import mdot
+from .numeric import complex_type, coupling, sqrt2
 
 _G = np.array([1.0, -1.0, -1.0, -1.0])
 
@@ -44,7 +45,7 @@ def _mdot_vec(p, J):
 
 def _v3_dressed(P1, P2, J1, J2, g):
     """sum_k V3(P1,P2; J1[i,k], J2[k,j]) including i g/sqrt2: [3,3,4,E]."""
-    c = 1j * g / math.sqrt(2.0)
+    c = 1j * (g / sqrt2(g))
     ab = np.einsum("ikme,kjme,m->ije", J1, J2, _G)
     q = [2.0 * P2[m] + P1[m] for m in range(4)]
     p = [2.0 * P1[m] + P2[m] for m in range(4)]
@@ -58,7 +59,7 @@ def _v3_dressed(P1, P2, J1, J2, g):
 
 def _v4_dressed(J1, J2, J3, g):
     """sum V4(J1[i,k], J2[k,l], J3[l,j]) including i g^2/2."""
-    c = 1j * g * g / 2.0
+    c = 1j * (g * g / 2)
     d12 = np.einsum("ikme,klme,m->ile", J1, J2, _G)
     d23 = np.einsum("klme,ljme,m->kje", J2, J3, _G)
     # 2 (J1.J3) J2 - (J2.J3) J1 - (J1.J2) J3
@@ -70,14 +71,14 @@ def _v4_dressed(J1, J2, J3, g):
 
 def _vt_jj(J1, J2, g):
     """V_T[J1 J2] with both tensor indices up: [3,3,4,4,E]."""
-    c = 0.5j * g / math.sqrt(2.0)
+    c = 0.5j * (g / sqrt2(g))
     x = np.einsum("ikae,kjbe->ijabe", J1, J2)
     return c * (x - np.swapaxes(x, 2, 3))
 
 
 def _vt_jt(J, T, g):
     """V_T^{nu kappa alpha beta} J_kappa T_alpha_beta with colour [J T]."""
-    c = 0.5j * g / math.sqrt(2.0)
+    c = 0.5j * (g / sqrt2(g))
     s1 = np.einsum("ikbe,kjnbe,b->ijne", J, T, _G)  # T^{nu b} J_b
     s2 = np.einsum("ikae,kjane,a->ijne", J, T, _G)  # J_a T^{a nu}
     return c * (s1 - s2)
@@ -85,7 +86,7 @@ def _vt_jt(J, T, g):
 
 def _vt_tj(T, J, g):
     """V_T^{lambda nu alpha beta} T_alpha_beta J_lambda with colour [T J]."""
-    c = 0.5j * g / math.sqrt(2.0)
+    c = 0.5j * (g / sqrt2(g))
     s1 = np.einsum("ikane,kjae,a->ijne", T, J, _G)  # J_a T^{a nu}
     s2 = np.einsum("iknbe,kjbe,b->ijne", T, J, _G)  # T^{nu b} J_b
     return c * (s1 - s2)
@@ -107,7 +108,7 @@ def _flow_matrix(i_k, j_k, E):
     return M
 
 
-def dressed_recursion(ps, eps, colmats, g=G_S, tensor=True):
+def dressed_recursion(ps, eps, colmats, g=None, tensor=True):
     """Dressed currents of all subsets of gluons 1..n-1 (0-based 0..n-2) for
     external currents eps[k] [4,E] and external colour matrices colmats[k]
     [3,3,E] (a colour-flow assignment, or any other colour wavefunction).
@@ -116,20 +117,23 @@ def dressed_recursion(ps, eps, colmats, g=G_S, tensor=True):
     """
     m = len(ps) - 1
     E = np.shape(ps[0][0])[-1]
+    if g is None:
+        g = coupling(ps[0][0])
+    ct = complex_type(ps[0][0])
     J, T, P = {}, {}, {}
     for k in range(m):
         mk = 1 << k
         e = np.array(eps[k])  # [4,E]
         J[mk] = colmats[k][:, :, None, :] * e[None, None]
-        T[mk] = np.zeros((3, 3, 4, 4, E), dtype=np.complex128)
+        T[mk] = np.zeros((3, 3, 4, 4, E), dtype=ct)
         P[mk] = ps[k]
     full = (1 << m) - 1
     for size in range(2, m + 1):
         for bits in itertools.combinations(range(m), size):
             S = sum(1 << b for b in bits)
             P[S] = [sum(ps[b][mu] for b in bits) for mu in range(4)]
-            acc = np.zeros((3, 3, 4, E), dtype=np.complex128)
-            tacc = np.zeros((3, 3, 4, 4, E), dtype=np.complex128)
+            acc = np.zeros((3, 3, 4, E), dtype=ct)
+            tacc = np.zeros((3, 3, 4, 4, E), dtype=ct)
             for A in _submasks(S):
                 B = S ^ A
                 acc = acc + _v3_dressed(P[A], P[B], J[A], J[B], g)
@@ -152,7 +156,7 @@ def dressed_recursion(ps, eps, colmats, g=G_S, tensor=True):
     return J
 
 
-def dressed_currents(mom, hel, col, g=G_S, tensor=True):
+def dressed_currents(mom, hel, col, g=None, tensor=True):
     """Dressed currents for helicity labels hel [n][E] and the colour-flow
     assignment col [2][n][E] (see dressed_recursion)."""
     n = mom.shape[0]
@@ -163,7 +167,7 @@ def dressed_currents(mom, hel, col, g=G_S, tensor=True):
     return dressed_recursion(ps, eps, colmats, g=g, tensor=tensor)
 
 
-def flow_amplitude(mom, hel, col, g=G_S, tensor=True):
+def flow_amplitude(mom, hel, col, g=None, tensor=True):
     """Colour-flow amplitude from the dressed recursion: complex [E]."""
     n = mom.shape[0]
     E = mom.shape[2]
@@ -186,12 +190,12 @@ def chain_weight(col, order):
     return w
 
 
-def flow_amplitude_bruteforce(mom, hel, col, g=G_S):
+def flow_amplitude_bruteforce(mom, hel, col, g=None):
     """sum over orderings (1, s) with s in S_(n-1) of chain weight x A(1, s)."""
     n = mom.shape[0]
     ps = momenta_list(mom)
     eps = external_currents(ps, hel)
-    out = np.zeros(mom.shape[2], dtype=np.complex128)
+    out = np.zeros(mom.shape[2], dtype=complex_type(mom))
     for s in itertools.permutations(range(1, n)):
         order = (0,) + s
         w = chain_weight(col, order)

@@ -37,6 +37,7 @@ import numpy as np
 from .cdbg import dressed_recursion
 from .cobg import G_S, momenta_list
 from .lorentz import mdot
+from .numeric import sqrt2
 from .polarization import basis
 
 NC = 3
@@ -49,7 +50,7 @@ def real_polarizations(ps, phi):
     for k, p in enumerate(ps):
         e1, e2 = basis(p)
         c, s = np.cos(phi[k]), np.sin(phi[k])
-        out.append([math.sqrt(2.0) * (c * e1[m] + s * e2[m]) for m in range(4)])
+        out.append([sqrt2(p[0]) * (c * e1[m] + s * e2[m]) for m in range(4)])
     return out
 
 
@@ -59,7 +60,7 @@ def colour_matrices(eta):
     return [eta[1, k][:, None, :] * eta[0, k][None, :, :] for k in range(n)]
 
 
-def amplitude_general(ps, eps, colmats, eta_n, etabar_n, g=G_S, tensor=True):
+def amplitude_general(ps, eps, colmats, eta_n, etabar_n, g=None, tensor=True):
     """eta_n^T (eps_n . P^2 J(1..n-1)) etabar_n for given external currents and
     colour matrices of gluons 1..n-1: complex [E]."""
     n = len(ps)
@@ -69,7 +70,7 @@ def amplitude_general(ps, eps, colmats, eta_n, etabar_n, g=G_S, tensor=True):
     return np.einsum("ae,abe,be->e", eta_n, m, etabar_n)
 
 
-def continuous_amplitude(mom, phi, eta, g=G_S, tensor=True):
+def continuous_amplitude(mom, phi, eta, g=None, tensor=True):
     """Amplitude for real polarizations e(phi) and colour vectors eta: complex
     [E] whose imaginary part vanishes (kept for the reality check)."""
     ps = momenta_list(mom)
@@ -79,7 +80,7 @@ def continuous_amplitude(mom, phi, eta, g=G_S, tensor=True):
                              g=g, tensor=tensor)
 
 
-def me2_continuous(mom, phi, eta, g=G_S, tensor=True):
+def me2_continuous(mom, phi, eta, g=None, tensor=True):
     """A^2 per event (float [E]); 9^n times its mean is the colour- and
     helicity-summed |M|^2."""
     a = continuous_amplitude(mom, phi, eta, g=g, tensor=tensor)

@@ -29,15 +29,16 @@ import math
 import numpy as np
 
 from .lorentz import mdot
+from .numeric import coupling, sqrt2
 from .polarization import external_current
 
 ALPHA_S = 0.118
-G_S = math.sqrt(4.0 * math.pi * ALPHA_S)
+G_S = math.sqrt(4.0 * math.pi * ALPHA_S)   # FP64 value; see ``numeric.coupling``
 
 
 def _v3(p, q, ja, jb, g):
     """V3^{nu kappa lambda}(p, q) ja_kappa jb_lambda (paper's vertex, with i g/sqrt2)."""
-    c = 1j * g / math.sqrt(2.0)
+    c = 1j * (g / sqrt2(g))
     ab = mdot(ja, jb)
     qa = mdot([2.0 * q[i] + p[i] for i in range(4)], ja)
     pb = mdot([2.0 * p[i] + q[i] for i in range(4)], jb)
@@ -46,7 +47,7 @@ def _v3(p, q, ja, jb, g):
 
 def _v4(j1, j2, j3, g):
     """V4^{nu rho kappa lambda} j1_rho j2_kappa j3_lambda (with i g^2/2)."""
-    c = 1j * g * g / 2.0
+    c = 1j * (g * g / 2)
     d13 = mdot(j1, j3)
     d12 = mdot(j1, j2)
     d23 = mdot(j2, j3)
@@ -66,13 +67,15 @@ def range_momenta(ps, order):
     return P
 
 
-def currents(ps, eps, order, g=G_S, amputate_top=False):
+def currents(ps, eps, order, g=None, amputate_top=False):
     """All range currents J[(a, b)] of the ordered gluons ``order`` (eq. cobg).
 
     ps[i]: momentum (list of 4 arrays) of gluon i; eps[i]: its external current.
     With amputate_top the full range carries p^2 J instead of J.
     """
     m = len(order)
+    if g is None:
+        g = coupling(ps[0][0])
     P = range_momenta(ps, order)
     J = {}
     for a in range(m):
@@ -98,7 +101,7 @@ def currents(ps, eps, order, g=G_S, amputate_top=False):
 
 def _vt_jj(ja, jb, g):
     """V_T^{gamma delta kappa lambda} ja_kappa jb_lambda, both tensor indices up."""
-    c = 0.5j * g / math.sqrt(2.0)
+    c = 0.5j * (g / sqrt2(g))
     return [[c * (ja[x] * jb[y] - ja[y] * jb[x]) for y in range(4)] for x in range(4)]
 
 
@@ -108,7 +111,7 @@ def _metric(i):
 
 def _vt_jt(j, t, g):
     """V_T^{nu kappa alpha beta} j_kappa T_{alpha beta} (gluon left of tensor)."""
-    c = 0.5j * g / math.sqrt(2.0)
+    c = 0.5j * (g / sqrt2(g))
     out = []
     for nu in range(4):
         s1 = 0.0
@@ -122,7 +125,7 @@ def _vt_jt(j, t, g):
 
 def _vt_tj(t, j, g):
     """V_T^{lambda nu alpha beta} T_{alpha beta} j_lambda (tensor left of gluon)."""
-    c = 0.5j * g / math.sqrt(2.0)
+    c = 0.5j * (g / sqrt2(g))
     out = []
     for nu in range(4):
         s1 = 0.0
@@ -139,9 +142,11 @@ def _prop_tensor(x):
     return [[-1j * (x[a][b] - x[b][a]) for b in range(4)] for a in range(4)]
 
 
-def currents_tensor(ps, eps, order, g=G_S, amputate_top=False):
+def currents_tensor(ps, eps, order, g=None, amputate_top=False):
     """Range currents from the tensor form (eqs. cobg_tensor, cobg_tensor_current)."""
     m = len(order)
+    if g is None:
+        g = coupling(ps[0][0])
     P = range_momenta(ps, order)
     J = {}
     T = {}
@@ -181,7 +186,7 @@ def external_currents(ps, hel):
     return [external_current(ps[i], hel[i]) for i in range(len(ps))]
 
 
-def ordered_amplitude(ps, eps, order, g=G_S, tensor=False):
+def ordered_amplitude(ps, eps, order, g=None, tensor=False):
     """A(order) = eps_last . (p^2 J(order[:-1])) (eq. cobg_full_amplitude)."""
     f = currents_tensor if tensor else currents
     J = f(ps, eps, order[:-1], g=g, amputate_top=True)
@@ -194,10 +199,11 @@ def ddm_orderings(n):
     return [(0,) + s + (n - 1,) for s in itertools.permutations(range(1, n - 1))]
 
 
-def partial_amplitudes(mom, hel, g=G_S, tensor=False):
+def partial_amplitudes(mom, hel, g=None, tensor=False):
     """A_sigma for the (n-2)! DDM orderings: complex array [K, E].
 
-    mom: [n][4][E] float64; hel: [n][E] of +-1 (or [n] scalars).
+    mom: [n][4][E] float64 (or long double / mpmath objects: the evaluation
+    runs in that precision); hel: [n][E] of +-1 (or [n] scalars).
     """
     n = mom.shape[0]
     ps = momenta_list(mom)
@@ -206,7 +212,7 @@ def partial_amplitudes(mom, hel, g=G_S, tensor=False):
     return np.array([np.broadcast_to(a, mom.shape[2:]) for a in amps])
 
 
-def amplitude_of(mom, hel, order, g=G_S):
+def amplitude_of(mom, hel, order, g=None):
     """A(order) for an arbitrary ordering of all n gluons: complex array [E]."""
     ps = momenta_list(mom)
     eps = external_currents(ps, hel)

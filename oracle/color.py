@@ -148,6 +148,29 @@ def adjoint_F():
     return np.einsum("abij,cji->abc", comm, T)
 
 
+def color_row_gellmann(n, row=0):
+    """Row `row` of C(n) from the definition with explicit F matrices (float).
+
+    Only two colour chains are held at a time (8^n entries each), so this
+    reaches n = 7 where the full brute-force matrix would not fit."""
+    F = adjoint_F()
+    perms = middle_permutations(n)
+    k = n - 2
+
+    def chain(sigma):
+        M = None
+        for gl in sigma:
+            Fb = np.moveaxis(F.reshape((8,) + (1,) * (k - 1) + (8, 8)), 0, gl - 1)
+            M = Fb if M is None else np.einsum("...ij,...jk->...ik", M, Fb)
+        return M
+
+    ref = chain(perms[row])
+    out = np.zeros(len(perms))
+    for j, sigma in enumerate(perms):
+        out[j] = np.real(np.sum(ref * np.conj(chain(sigma))))
+    return out
+
+
 def color_matrix_gellmann(n):
     """C(n) from its definition with explicit F matrices (float, n <= 6)."""
     F = adjoint_F()

@@ -15,7 +15,7 @@ from .color import color_matrix_cached
 from .dual import Dual
 
 
-def me2_and_grad(mom, hel, g=G_S, C=None):
+def me2_and_grad(mom, hel, g=None, C=None):
     """(me2 [E], grad [n][4][E]) for per-event helicities hel [n][E]."""
     n = mom.shape[0]
     E = mom.shape[2]

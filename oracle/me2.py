@@ -30,7 +30,7 @@ def contract(amps, C):
     return np.real(np.einsum("se,st,te->e", amps, Cf, np.conj(amps)))
 
 
-def me2_cobg(mom, hel=None, g=G_S, C=None):
+def me2_cobg(mom, hel=None, g=None, C=None):
     """Colour-summed |M|^2 per event: float64 [E]."""
     n = mom.shape[0]
     if C is None:
@@ -44,7 +44,7 @@ def me2_cobg(mom, hel=None, g=G_S, C=None):
     return out
 
 
-def me2_leading_colour(mom, hel, g=G_S, nc=NC):
+def me2_leading_colour(mom, hel, g=None, nc=NC):
     """N^(n-2)(N^2-1) sum over orderings (1, rho) of |A|^2 for one helicity."""
     n = mom.shape[0]
     ps = momenta_list(mom)

@@ -35,6 +35,7 @@ import numpy as np
 
 from .dual import value
 from .lorentz import mdot, levi_civita_contract
+from .numeric import sqrt2
 
 R_REF = (3.0 / 7.0, -6.0 / 7.0, 2.0 / 7.0)
 INV_SQRT2 = 1.0 / math.sqrt(2.0)
@@ -85,7 +86,8 @@ def external_current(p, h, basis_fn=None):
     """(eps^h(k))* = (e1 - i h e2)/sqrt(2); h is an array of +-1."""
     e1, e2 = (basis_fn or basis)(p)
     ih = 1j * np.asarray(h, dtype=np.float64)
-    return [(e1[i] - ih * e2[i]) * INV_SQRT2 for i in range(4)]
+    inv = 1 / sqrt2(p[0])
+    return [(e1[i] - ih * e2[i]) * inv for i in range(4)]
 
 
 def projector(p, kref):

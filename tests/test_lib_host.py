@@ -29,6 +29,20 @@ def test_colour_matrix_matches_oracle(n):
     assert np.array_equal(out.reshape(K, K), ref.astype(np.float64))
 
 
+def test_colour_matrix_matches_golden_files():
+    """The library's C(n) against the stored fixtures of tests/golden (n = 4..6
+    whole, n = 7 first row)."""
+    import os
+    gold = os.path.join(os.path.dirname(__file__), "golden")
+    for n in (4, 5, 6, 7):
+        K = _lib.lib().bg_num_orderings(n)
+        out = np.zeros(K * K)
+        assert lib().bg_color_matrix(n, out.ctypes.data_as(ctypes.c_void_p), K * K) == 0
+        name = f"colour_matrix_n{n}.txt" if n < 7 else "colour_matrix_n7_row0.txt"
+        stored = np.loadtxt(os.path.join(gold, name), ndmin=2)
+        assert np.array_equal(out.reshape(K, K)[: stored.shape[0]], stored)
+
+
 def test_colour_matrix_n8_sampled_entries():
     n = 8
     K = 720
