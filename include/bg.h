@@ -42,7 +42,13 @@
  *     returned before anything is enqueued; device faults surface on a later
  *     synchronisation.
  *   - A context is bound to one device and is not thread-safe; use one per host
- *     thread.  It owns the colour matrices and a reusable workspace.
+ *     thread.  It owns the colour matrices and a reusable workspace.  Calls on
+ *     one context that use its workspace (bg_me2, bg_me2_grad, bg_me2_batch,
+ *     bg_generate, bg_me2_continuous) are ordered even when they are issued on
+ *     different streams: each such call records a context-owned event on its
+ *     stream, and the next such call on another stream waits for it first.
+ *     Work recorded into a graph is not ordered this way (the wait is skipped
+ *     while a stream captures); the caller orders graph replays.
  */
 #ifndef BG_H_
 #define BG_H_
@@ -79,7 +85,17 @@ extern "C" {
 
 /* arithmetic of the recursion; contraction and |M|^2 sums are always FP64 */
 #define BG_PREC_FP64       0
-#define BG_PREC_FP32_MIXED 1 /* FP32 complex currents, FP64 invariants/contraction */
+#define BG_PREC_FP32_MIXED 1 /* FP32 complex currents, FP64 invariants/contraction, and
+                                FP64 re-evaluation of the events whose FP32 evaluation is
+                                ill-conditioned (see bg_fp32_check_set) */
+
+/* request and context flags */
+#define BG_FLAG_VALIDATE       1u  /* check before any launch that every hel is +1 or -1 and
+                                      every col entry is 0, 1 or 2 (BG_EINVAL otherwise);
+                                      reads the inputs once and synchronises the stream;
+                                      refused (BG_EINVAL) while the stream captures */
+#define BG_FLAG_FP32_UNCHECKED 2u  /* BG_PREC_FP32_MIXED without the FP64 re-evaluation of
+                                      ill-conditioned events (plain FP32 recursion) */
 
 #define BG_N_MIN 4
 #define BG_N_MAX 9
@@ -87,8 +103,10 @@ extern "C" {
 typedef struct bg_context bg_context;
 
 /* Create a context on HIP device `device`.  Returns BG_ENODEV if the device is
- * missing or not gfx950.  *out is set only on success. */
-int bg_context_create(bg_context** out, int device);
+ * missing or not gfx950, BG_EINVAL for unknown flags.  `flags` (BG_FLAG_*) are
+ * applied to every request made through the context, in addition to the
+ * request's own.  *out is set only on success. */
+int bg_context_create(bg_context** out, int device, uint32_t flags);
 void bg_context_destroy(bg_context* ctx);
 
 /* Static message for a status code (never NULL). */
@@ -121,7 +139,7 @@ typedef struct bg_request {
     int n;               /* gluons, BG_N_MIN..BG_N_MAX */
     int mode;            /* BG_MODE_* */
     int precision;       /* BG_PREC_* */
-    int reserved;        /* must be 0 */
+    uint32_t flags;      /* BG_FLAG_* (0 for none) */
     int64_t n_events;    /* E >= 0 (0 is a no-op) */
     const double* mom;   /* [n][4][E] */
     const int8_t* hel;   /* [n][E], or NULL = sum over all 2^n helicities (COBG only) */
@@ -140,6 +158,32 @@ typedef struct bg_request {
  * give exactly 0.  May allocate context workspace on first use of a size. */
 int bg_me2(bg_context* ctx, const bg_request* req, void* stream);
 
+/* FP32 accuracy control (BG_PREC_FP32_MIXED).  While the FP32 recursion runs
+ * it also carries, per current, a bound on its components computed as if
+ * every product were taken in modulus (the classical running error bound, up
+ * to constant factors): 1 for an external polarization, and for a current of
+ * a gluon range or subset |1/P^2| (E sum_splits S_1 S_2 + ...), E the sum of
+ * |p^0| over the gluons, the remaining terms being the four-gluon vertex
+ * (colour-ordered, Section 2.3 eq. cobg) or the tensor couplings
+ * (colour-dressed, eq. color_dressed_currents) term by term.  An event whose
+ *   est = sum_sigma S_sigma^2 / sum_sigma |A_sigma|^2   (colour-ordered), or
+ *   est = S^2 / |A|^2                                    (colour-dressed)
+ * exceeds tau(mode, n) -- its amplitudes cancel strongly, so FP32 rounding of
+ * the inputs and of the recursion is amplified -- is listed on the device and
+ * evaluated again in FP64 by a second kernel on the same stream (no host
+ * synchronisation), which overwrites its me2.  Helicity configurations whose
+ * tree amplitude vanishes identically (fewer than two gluons of either
+ * helicity) are never listed.  The default tau are chosen so that the
+ * per-event relative error of me2 against FP64 stays below 1e-5 for 99% of
+ * the sampled-helicity (and sampled-flow) events of the RAMBO workloads.
+ * mode: BG_MODE_COBG (n in [4, 7]) or BG_MODE_CDBG (n in [4, 9]), the bg_me2
+ * modes the check applies to.  tau = 0 lists every non-vanishing event (then
+ * me2 equals the FP64 path bit for bit); tau = +inf lists none (as
+ * BG_FLAG_FP32_UNCHECKED).  Host only; BG_EINVAL for another mode or n, or
+ * tau < 0 or NaN. */
+int bg_fp32_check_set(bg_context* ctx, int mode, int n, float tau);
+int bg_fp32_check_get(bg_context* ctx, int mode, int n, float* tau);
+
 /* Gradient of the COBG colour-summed |M|^2 with respect to every momentum
  * component, contracted with an upstream gradient:
  *   grad_mom[i][mu][e] = grad_me2[e] * d me2[e] / d mom[i][mu][e]
@@ -155,8 +199,19 @@ int bg_me2_grad(bg_context* ctx, const bg_request* req, const double* grad_me2,
  * for n >= 8 per segment; explicit modes are honoured (COBG needs n <= 7).
  * Every segment must have the same precision, hel non-NULL, me2 non-NULL when
  * its n_events > 0, and col for CDBG; at most BG_BATCH_MAX_SEGS segments.
- * Results are identical, bit for bit, to bg_me2 on each segment alone (the
- * same device routines evaluate every event; only the scheduling differs).
+ * Colour-ordered FP64 segments give bg_me2's results on each segment alone
+ * bit for bit (the same device routines evaluate every event; only the
+ * scheduling differs).  Other segments agree within the two paths' error
+ * bars: the FP32 kernels may contract products into multiply-adds
+ * differently, a colour-dressed event is split over 256 lanes here and over
+ * 128 or 256 in bg_me2, and an FP32 event close to the check threshold of
+ * bg_fp32_check_set may be re-evaluated in FP64 by one path only.
+ * BG_PREC_FP32_MIXED batches apply that check per segment (threshold of the
+ * segment's mode and n; BG_FLAG_FP32_UNCHECKED in a segment's flags turns it
+ * off for that segment): an FP32 pass lists the events, a one-block kernel
+ * turns the per-segment counts into a tile table on the device, and an FP64
+ * pass of the same persistent kernel re-evaluates them; all three launches
+ * can be recorded into a graph.
  * The events are cut into tiles (config below), the tiles are ordered by
  * decreasing estimated cost and the blocks of the persistent grid take them
  * from an atomic queue.
@@ -165,7 +220,7 @@ int bg_me2_grad(bg_context* ctx, const bg_request* req, const double* grad_me2,
  * (synchronous host-to-device upload) and cached in the context (at most
  * BG_BATCH_MAX_PLANS shapes; older ones are evicted after a device
  * synchronisation).  A call whose shape is cached allocates nothing, copies
- * nothing and only enqueues two kernels on `stream`, so it may be recorded
+ * nothing and only enqueues kernels on `stream`, so it may be recorded
  * into a HIP graph; such a graph remains valid while its shape stays cached
  * and the context lives.  Recording a call whose shape is not cached returns
  * BG_EINVAL.  Calls on one context must not overlap in time (they share the

@@ -21,6 +21,7 @@ BG_EUNSUPPORTED = -6
 
 MODE_COBG, MODE_CDBG, MODE_AUTO, MODE_LC, MODE_COMC = 0, 1, 2, 3, 4
 PREC_FP64, PREC_FP32_MIXED = 0, 1
+FLAG_VALIDATE, FLAG_FP32_UNCHECKED = 1, 2
 
 
 class bg_request(ctypes.Structure):
@@ -28,7 +29,7 @@ class bg_request(ctypes.Structure):
         ("n", ctypes.c_int),
         ("mode", ctypes.c_int),
         ("precision", ctypes.c_int),
-        ("reserved", ctypes.c_int),
+        ("flags", ctypes.c_uint32),
         ("n_events", ctypes.c_int64),
         ("mom", ctypes.c_void_p),
         ("hel", ctypes.c_void_p),
@@ -67,7 +68,9 @@ _I = ctypes.c_int
 _I64 = ctypes.c_int64
 
 _SIGNATURES = {
-    "bg_context_create": (_I, [ctypes.POINTER(_P), _I]),
+    "bg_context_create": (_I, [ctypes.POINTER(_P), _I, ctypes.c_uint32]),
+    "bg_fp32_check_set": (_I, [_P, _I, _I, ctypes.c_float]),
+    "bg_fp32_check_get": (_I, [_P, _I, _I, ctypes.POINTER(ctypes.c_float)]),
     "bg_context_destroy": (None, [_P]),
     "bg_status_string": (ctypes.c_char_p, [_I]),
     "bg_num_orderings": (_I64, [_I]),

@@ -13,20 +13,25 @@ import torch
 from . import _lib
 from ._lib import bg_batch_config, bg_gen_params, bg_request, check, lib
 
-_PREC = {"fp64": _lib.PREC_FP64, "fp32": _lib.PREC_FP32_MIXED, "mixed": _lib.PREC_FP32_MIXED}
+_PREC = {"fp64": _lib.PREC_FP64, "fp32": _lib.PREC_FP32_MIXED, "mixed": _lib.PREC_FP32_MIXED,
+         "fp32_unchecked": _lib.PREC_FP32_MIXED}
+# precision names that add request flags: the plain FP32 recursion without the
+# FP64 re-evaluation of ill-conditioned events
+_PREC_FLAGS = {"fp32_unchecked": _lib.FLAG_FP32_UNCHECKED}
 _MODE = {"cobg": _lib.MODE_COBG, "cdbg": _lib.MODE_CDBG, "auto": _lib.MODE_AUTO,
          "lc": _lib.MODE_LC, "comc": _lib.MODE_COMC}
 
 
 class Context:
-    """Owns a bg_context (colour matrices, workspace) on one device."""
+    """Owns a bg_context (colour matrices, workspace) on one device; flags
+    (FLAG_* of the library) apply to every request made through it."""
 
-    def __init__(self, device=None):
+    def __init__(self, device=None, flags=0):
         if device is None:
             device = torch.cuda.current_device()
         self.device = int(device)
         h = ctypes.c_void_p()
-        check(lib().bg_context_create(ctypes.byref(h), self.device), "bg_context_create")
+        check(lib().bg_context_create(ctypes.byref(h), self.device, int(flags)), "bg_context_create")
         self._h = h
 
     @property
@@ -120,7 +125,7 @@ def color_contract(amp, n, out=None, accumulate=False, ctx=None):
     return out
 
 
-def _request(mom, hel, col, mode, precision, me2):
+def _request(mom, hel, col, mode, precision, me2, validate=False):
     n, E = _check_mom(mom)
     _check_i8(hel, (n, E), "hel")
     _check_i8(col, (2, n, E), "col")
@@ -128,7 +133,7 @@ def _request(mom, hel, col, mode, precision, me2):
     r.n = n
     r.mode = _MODE[mode]
     r.precision = _PREC[precision]
-    r.reserved = 0
+    r.flags = _PREC_FLAGS.get(precision, 0) | (_lib.FLAG_VALIDATE if validate else 0)
     r.n_events = E
     r.mom = mom.data_ptr()
     r.hel = hel.data_ptr() if hel is not None else None
@@ -137,15 +142,32 @@ def _request(mom, hel, col, mode, precision, me2):
     return r
 
 
-def me2(mom, hel=None, col=None, mode="cobg", precision="fp64", out=None, ctx=None):
-    """Per-event |M|^2 (float64 [E]); hel None sums over helicities (COBG)."""
+def me2(mom, hel=None, col=None, mode="cobg", precision="fp64", out=None, ctx=None,
+        validate=False):
+    """Per-event |M|^2 (float64 [E]); hel None sums over helicities (COBG).
+    precision: "fp64", "fp32" (FP32 recursion with FP64 re-evaluation of
+    ill-conditioned events) or "fp32_unchecked" (FP32 recursion only).
+    validate: check the hel and col values on the device first."""
     n, E = _check_mom(mom)
     ctx = ctx or default_context(mom.device.index)
     if out is None:
         out = torch.empty(E, dtype=torch.float64, device=mom.device)
-    r = _request(mom, hel, col, mode, precision, out)
+    r = _request(mom, hel, col, mode, precision, out, validate)
     check(lib().bg_me2(ctx.handle, ctypes.byref(r), _stream(mom.device)), "bg_me2")
     return out
+
+
+def fp32_check(n, tau=None, mode="cobg", ctx=None):
+    """Threshold of the FP32 accuracy check of `mode` ("cobg" or "cdbg") at n
+    (bg_fp32_check_get/set): returns the current value; sets it first if tau
+    is given."""
+    ctx = ctx or default_context()
+    m = _MODE[mode]
+    if tau is not None:
+        check(lib().bg_fp32_check_set(ctx.handle, m, n, ctypes.c_float(tau)), "bg_fp32_check_set")
+    t = ctypes.c_float()
+    check(lib().bg_fp32_check_get(ctx.handle, m, n, ctypes.byref(t)), "bg_fp32_check_get")
+    return t.value
 
 
 def me2_grad(mom, hel, grad_me2=None, precision="fp64", ctx=None, want_me2=True):

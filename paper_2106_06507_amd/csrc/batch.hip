@@ -6,29 +6,31 @@ namespace bg {
 namespace fusedk {
 
 // n <= 6: one 32-event tile per block, amplitudes in LDS; the hardware
-// dispatcher balances the blocks.
-template <int N, typename T, bool HSUM>
+// dispatcher balances the blocks.  CHK: FP32 pass that lists ill-conditioned
+// events (TileCheck).
+template <int N, typename T, bool HSUM, bool CHK = false>
 __global__ void __launch_bounds__(64) cobg_fused_kernel(int64_t E, const double* __restrict__ mom,
                                                        const int8_t* __restrict__ hel,
                                                        const double* __restrict__ Cb,
-                                                       double* __restrict__ me2) {
+                                                       double* __restrict__ me2, TileCheck chk) {
   extern __shared__ __align__(16) unsigned char bg_fused_lds[];
   const int64_t first = (int64_t)blockIdx.x * kTileEvents;
   const int64_t left = E - first;
-  cobg_tile<N, T, HSUM>(bg_fused_lds, E, mom, hel, Cb, nullptr, me2, first,
-                        (int)(left < kTileEvents ? left : kTileEvents));
+  cobg_tile<N, T, HSUM, false, CHK>(bg_fused_lds, E, mom, hel, Cb, nullptr, me2, first,
+                                    (int)(left < kTileEvents ? left : kTileEvents), chk);
 }
 
 // n = 7: persistent blocks, each with its own scratch slice, take tiles from
 // an atomic queue (reset by zero_counter_kernel before the launch).
-template <typename T, bool HSUM>
+template <typename T, bool HSUM, bool CHK = false>
 __global__ void __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) cobg_fused_queue_kernel(int64_t E,
                                                              const double* __restrict__ mom,
                                                              const int8_t* __restrict__ hel,
                                                              const double* __restrict__ Cb,
                                                              double* __restrict__ scratch,
                                                              unsigned* __restrict__ counter,
-                                                             double* __restrict__ me2) {
+                                                             double* __restrict__ me2,
+                                                             TileCheck chk) {
   extern __shared__ __align__(16) unsigned char bg_fused_lds[];
   double* blk = scratch + (size_t)blockIdx.x * Cobg<7>::kScratch;
   const unsigned tiles = (unsigned)((E + kTileEvents - 1) / kTileEvents);
@@ -39,8 +41,31 @@ __global__ void __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) cobg_fused_queue_k
     if (t >= tiles) break;
     const int64_t first = (int64_t)t * kTileEvents;
     const int64_t left = E - first;
-    cobg_tile<7, T, HSUM>(bg_fused_lds, E, mom, hel, Cb, blk, me2, first,
-                          (int)(left < kTileEvents ? left : kTileEvents));
+    cobg_tile<7, T, HSUM, false, CHK>(bg_fused_lds, E, mom, hel, Cb, blk, me2, first,
+                                      (int)(left < kTileEvents ? left : kTileEvents), chk);
+  }
+}
+
+// FP64 re-evaluation of the events listed by a CHK pass: persistent blocks
+// stride over 32-event tiles of the list; the list length is read on the
+// device, so the launch needs no host synchronisation.  scratch: one slice
+// of Cobg<N>::kScratch doubles per block (n = 7).
+template <int N, bool HSUM>
+__global__ void __launch_bounds__(64) cobg_fix_kernel(int64_t E, const double* __restrict__ mom,
+                                                     const int8_t* __restrict__ hel,
+                                                     const double* __restrict__ Cb,
+                                                     double* __restrict__ scratch,
+                                                     const unsigned* __restrict__ count,
+                                                     const unsigned* __restrict__ list,
+                                                     double* __restrict__ me2) {
+  extern __shared__ __align__(16) unsigned char bg_fused_lds[];
+  double* blk = Cobg<N>::kScratch ? scratch + (size_t)blockIdx.x * Cobg<N>::kScratch : nullptr;
+  const unsigned cnt = *count;
+  for (unsigned first = blockIdx.x * kTileEvents; first < cnt; first += gridDim.x * kTileEvents) {
+    const unsigned left = cnt - first;
+    cobg_tile<N, double, HSUM, false, false, true>(
+        bg_fused_lds, E, mom, hel, Cb, blk, me2, first,
+        (int)(left < (unsigned)kTileEvents ? left : (unsigned)kTileEvents), TileCheck{}, list);
   }
 }
 
@@ -85,7 +110,7 @@ struct BatchP64G {
   static constexpr bool value = N >= 6;
 };
 
-template <int N, typename T>
+template <int N, typename T, int PASS>
 __device__ __forceinline__ void run_cobg(unsigned char* lds, const BatchSeg& s, double* blk,
                                          int64_t first, int count) {
   constexpr bool G = BatchP64G<N>::value;
@@ -97,17 +122,25 @@ __device__ __forceinline__ void run_cobg(unsigned char* lds, const BatchSeg& s, 
     const int j = i + w;
     const int off = j * kTileEvents;
     const int c = j < nsub ? (count - off < kTileEvents ? count - off : kTileEvents) : 0;
-    cobg_tile<N, T, false, G>(mine, s.E, s.mom, s.hel, s.Cl, myblk, s.me2,
-                              first + (j < nsub ? off : 0), c);
+    const int64_t f = first + (j < nsub ? off : 0);
+    if constexpr (PASS == kBatchFix)
+      cobg_tile<N, T, false, G, false, true>(mine, s.E, s.mom, s.hel, s.Cl, myblk, s.me2, f, c,
+                                             TileCheck{}, s.idx);
+    else if constexpr (PASS == kBatchCheck)
+      cobg_tile<N, T, false, G, true>(mine, s.E, s.mom, s.hel, s.Cl, myblk, s.me2, f, c,
+                                      TileCheck{s.tau, s.fcount, s.flist});
+    else
+      cobg_tile<N, T, false, G>(mine, s.E, s.mom, s.hel, s.Cl, myblk, s.me2, f, c);
   }
 }
 
-template <int N, typename T>
+template <int N, typename T, int PASS>
 __device__ __forceinline__ void run_cdbg(unsigned char* lds, unsigned long long* vmask,
                                          const BatchSeg& s, int64_t first, int count) {
   for (int off = 0; off < count; off += kBatchLanes) {
     const int c = count - off < kBatchLanes ? count - off : kBatchLanes;
-    cdbg_chunk<N, T, kBatchLanes>(lds, vmask, s.E, s.mom, s.hel, s.col, s.me2, first + off, c);
+    cdbg_chunk<N, T, kBatchLanes, PASS>(lds, vmask, s.E, s.mom, s.hel, s.col, s.me2, first + off,
+                                        c, s.idx, cdbgk::DressedCheck{s.tau, s.fcount, s.flist});
   }
 }
 
@@ -118,11 +151,13 @@ __device__ __forceinline__ void run_cdbg(unsigned char* lds, unsigned long long*
 // largest branch (n = 7 colour-ordered) keeps all its registers and one
 // block fits on a CU; 2: at most 256 registers per lane, two blocks per CU
 // (the colour-dressed branches need ~130 and gain from the second block, the
-// n = 7 branch spills a little).  The autotuner picks one.
-template <typename T, int WAVES>
+// n = 7 branch spills a little).  The autotuner picks one.  PASS: BatchPass;
+// the re-evaluation pass reads its tile count from n_tiles_dev.
+template <typename T, int WAVES, int PASS>
 __global__ void __launch_bounds__(kBatchLanes, WAVES) batch_kernel(const BatchSegTable segs,
                                                            const BatchTile* __restrict__ tiles,
                                                            unsigned n_tiles,
+                                                           const unsigned* __restrict__ n_tiles_dev,
                                                            unsigned* __restrict__ counter,
                                                            double* __restrict__ scratch,
                                                            int64_t scratch_stride) {
@@ -131,66 +166,136 @@ __global__ void __launch_bounds__(kBatchLanes, WAVES) batch_kernel(const BatchSe
   unsigned* bcast = reinterpret_cast<unsigned*>(bg_batch_lds + 32);
   unsigned char* lds = bg_batch_lds + kBatchHeader;
   double* blk = scratch + (size_t)blockIdx.x * (size_t)scratch_stride;
+  const unsigned total = n_tiles_dev ? *n_tiles_dev : n_tiles;
   for (;;) {
     if (threadIdx.x == 0) bcast[0] = atomicAdd(counter, 1u);
     __syncthreads();
     const unsigned t = (unsigned)__builtin_amdgcn_readfirstlane((int)bcast[0]);
     __syncthreads();  // every lane has the index before the next pop
-    if (t >= n_tiles) break;
+    if (t >= total) break;
     const BatchTile tile = tiles[t];
     const BatchSeg s = segs.s[tile.seg];
     switch (s.kind) {
-      case kBatchCobg + 4: run_cobg<4, T>(lds, s, blk, tile.first, tile.count); break;
-      case kBatchCobg + 5: run_cobg<5, T>(lds, s, blk, tile.first, tile.count); break;
-      case kBatchCobg + 6: run_cobg<6, T>(lds, s, blk, tile.first, tile.count); break;
-      case kBatchCobg + 7: run_cobg<7, T>(lds, s, blk, tile.first, tile.count); break;
-      case kBatchCdbg + 4: run_cdbg<4, T>(lds, vmask, s, tile.first, tile.count); break;
-      case kBatchCdbg + 5: run_cdbg<5, T>(lds, vmask, s, tile.first, tile.count); break;
-      case kBatchCdbg + 6: run_cdbg<6, T>(lds, vmask, s, tile.first, tile.count); break;
-      case kBatchCdbg + 7: run_cdbg<7, T>(lds, vmask, s, tile.first, tile.count); break;
-      case kBatchCdbg + 8: run_cdbg<8, T>(lds, vmask, s, tile.first, tile.count); break;
-      case kBatchCdbg + 9: run_cdbg<9, T>(lds, vmask, s, tile.first, tile.count); break;
+      case kBatchCobg + 4: run_cobg<4, T, PASS>(lds, s, blk, tile.first, tile.count); break;
+      case kBatchCobg + 5: run_cobg<5, T, PASS>(lds, s, blk, tile.first, tile.count); break;
+      case kBatchCobg + 6: run_cobg<6, T, PASS>(lds, s, blk, tile.first, tile.count); break;
+      case kBatchCobg + 7: run_cobg<7, T, PASS>(lds, s, blk, tile.first, tile.count); break;
+      case kBatchCdbg + 4: run_cdbg<4, T, PASS>(lds, vmask, s, tile.first, tile.count); break;
+      case kBatchCdbg + 5: run_cdbg<5, T, PASS>(lds, vmask, s, tile.first, tile.count); break;
+      case kBatchCdbg + 6: run_cdbg<6, T, PASS>(lds, vmask, s, tile.first, tile.count); break;
+      case kBatchCdbg + 7: run_cdbg<7, T, PASS>(lds, vmask, s, tile.first, tile.count); break;
+      case kBatchCdbg + 8: run_cdbg<8, T, PASS>(lds, vmask, s, tile.first, tile.count); break;
+      case kBatchCdbg + 9: run_cdbg<9, T, PASS>(lds, vmask, s, tile.first, tile.count); break;
       default: break;
     }
     __syncthreads();  // the next tile rewrites LDS
   }
 }
 
+// Tiles of the re-evaluation pass: segment s contributes ceil(fcount[s] /
+// step) tiles over its list, step 128 (colour-ordered) or 256 (colour-
+// dressed: one event at a time on the whole block, so each tile is a chunk).
+__global__ void __launch_bounds__(256) fix_tiles_kernel(const BatchSegTable segs, int n_segs,
+                                                       const unsigned* __restrict__ fcount,
+                                                       BatchTile* __restrict__ tiles,
+                                                       unsigned* __restrict__ n_tiles) {
+  __shared__ unsigned start[kBatchMaxSegs + 1];
+  if (threadIdx.x == 0) {
+    unsigned acc = 0;
+    for (int i = 0; i < n_segs; ++i) {
+      start[i] = acc;
+      const unsigned step = segs.s[i].kind >= kBatchCdbg ? 256u : 128u;
+      acc += (fcount[i] + step - 1) / step;
+    }
+    start[n_segs] = acc;
+    *n_tiles = acc;
+  }
+  __syncthreads();
+  for (int i = 0; i < n_segs; ++i) {
+    const unsigned step = segs.s[i].kind >= kBatchCdbg ? 256u : 128u;
+    const unsigned cnt = fcount[i];
+    for (unsigned k = threadIdx.x; k < start[i + 1] - start[i]; k += blockDim.x) {
+      const unsigned f = k * step;
+      tiles[start[i] + k] = BatchTile{(int64_t)f, i, (int)(cnt - f < step ? cnt - f : step)};
+    }
+  }
+}
+
 template <int N, typename T>
 int fused_launch(int64_t E, const double* mom, const int8_t* hel, const double* Cb,
-                 double* scratch, unsigned* counter, int grid, double* me2, hipStream_t stream) {
+                 double* scratch, unsigned* counter, int grid, double* me2, const TileCheck* chk,
+                 hipStream_t stream) {
   const size_t lds = Cobg<N>::template lds_bytes<T>();
+  const TileCheck ck = chk ? *chk : TileCheck{};
   if constexpr (Cobg<N>::kLdsAmp) {
     (void)scratch;
     (void)counter;
     (void)grid;
     const unsigned tiles = (unsigned)((E + kTileEvents - 1) / kTileEvents);
-    if (hel)
-      hipLaunchKernelGGL((cobg_fused_kernel<N, T, false>), dim3(tiles), dim3(64), lds, stream, E,
-                         mom, hel, Cb, me2);
-    else
-      hipLaunchKernelGGL((cobg_fused_kernel<N, T, true>), dim3(tiles), dim3(64), lds, stream, E,
-                         mom, hel, Cb, me2);
+#define BG_FUSED(HS, CK)                                                                      \
+  hipLaunchKernelGGL((cobg_fused_kernel<N, T, HS, CK>), dim3(tiles), dim3(64), lds, stream, E, \
+                     mom, hel, Cb, me2, ck)
+    if constexpr (sizeof(T) == 4) {
+      if (hel) {
+        if (chk) BG_FUSED(false, true); else BG_FUSED(false, false);
+      } else {
+        if (chk) BG_FUSED(true, true); else BG_FUSED(true, false);
+      }
+    } else {
+      if (hel) BG_FUSED(false, false); else BG_FUSED(true, false);
+    }
+#undef BG_FUSED
   } else {
     hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, stream, counter);
-    if (hel)
-      hipLaunchKernelGGL((cobg_fused_queue_kernel<T, false>), dim3(grid), dim3(64), lds, stream,
-                         E, mom, hel, Cb, scratch, counter, me2);
-    else
-      hipLaunchKernelGGL((cobg_fused_queue_kernel<T, true>), dim3(grid), dim3(64), lds, stream,
-                         E, mom, hel, Cb, scratch, counter, me2);
+#define BG_QUEUE(HS, CK)                                                                      \
+  hipLaunchKernelGGL((cobg_fused_queue_kernel<T, HS, CK>), dim3(grid), dim3(64), lds, stream, \
+                     E, mom, hel, Cb, scratch, counter, me2, ck)
+    if constexpr (sizeof(T) == 4) {
+      if (hel) {
+        if (chk) BG_QUEUE(false, true); else BG_QUEUE(false, false);
+      } else {
+        if (chk) BG_QUEUE(true, true); else BG_QUEUE(true, false);
+      }
+    } else {
+      if (hel) BG_QUEUE(false, false); else BG_QUEUE(true, false);
+    }
+#undef BG_QUEUE
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+template <int N>
+int fix_launch(int64_t E, const double* mom, const int8_t* hel, const double* Cb,
+               double* scratch, const unsigned* count, const unsigned* list, int grid,
+               double* me2, hipStream_t stream) {
+  const size_t lds = Cobg<N>::template lds_bytes<double>();
+  if (hel)
+    hipLaunchKernelGGL((cobg_fix_kernel<N, false>), dim3(grid), dim3(64), lds, stream, E, mom, hel,
+                       Cb, scratch, count, list, me2);
+  else
+    hipLaunchKernelGGL((cobg_fix_kernel<N, true>), dim3(grid), dim3(64), lds, stream, E, mom, hel,
+                       Cb, scratch, count, list, me2);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int N>
+int fix_occupancy(bool hsum) {
+  int nb = 0;
+  const size_t lds = Cobg<N>::template lds_bytes<double>();
+  const hipError_t e =
+      hsum ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cobg_fix_kernel<N, true>, 64, lds)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cobg_fix_kernel<N, false>, 64, lds);
+  return e == hipSuccess ? nb : -1;
+}
+
 // Blocks per CU of the persistent (n = 7) kernel.
-template <typename T>
+template <typename T, bool CHK>
 int fused_occupancy(bool hsum) {
   int nb = 0;
   const size_t lds = Cobg<7>::template lds_bytes<T>();
   const hipError_t e =
-      hsum ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cobg_fused_queue_kernel<T, true>, 64, lds)
-           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cobg_fused_queue_kernel<T, false>, 64, lds);
+      hsum ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cobg_fused_queue_kernel<T, true, CHK>, 64, lds)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cobg_fused_queue_kernel<T, false, CHK>, 64, lds);
   return e == hipSuccess ? nb : -1;
 }
 
@@ -228,21 +333,25 @@ size_t cobg_lds_bytes(int n, bool fp32) {
   }
 }
 
-int cobg_fused_persistent_blocks_per_cu(bool fp32, bool hsum) {
-  return fp32 ? fusedk::fused_occupancy<float>(hsum) : fusedk::fused_occupancy<double>(hsum);
+int cobg_fused_persistent_blocks_per_cu(bool fp32, bool hsum, bool chk) {
+  if (!fp32) return fusedk::fused_occupancy<double, false>(hsum);
+  return chk ? fusedk::fused_occupancy<float, true>(hsum) : fusedk::fused_occupancy<float, false>(hsum);
 }
 
 int cobg_fused_me2(int n, bool fp32, int64_t E, const double* mom, const int8_t* hel,
                    const double* Cb, double* scratch, unsigned* counter, int grid, double* me2,
-                   hipStream_t stream) {
+                   const CheckArgs* chk, hipStream_t stream) {
   if (E <= 0) return 0;
+  fusedk::TileCheck tc{};
+  if (chk) tc = fusedk::TileCheck{chk->tau, chk->count, chk->list};
+  const fusedk::TileCheck* tp = chk && fp32 ? &tc : nullptr;
   switch (n) {
 #define BG_CASE(NN)                                                                              \
   case NN:                                                                                       \
     return fp32 ? fusedk::fused_launch<NN, float>(E, mom, hel, Cb, scratch, counter, grid, me2,  \
-                                                  stream)                                        \
+                                                  tp, stream)                                    \
                 : fusedk::fused_launch<NN, double>(E, mom, hel, Cb, scratch, counter, grid, me2, \
-                                                   stream);
+                                                   nullptr, stream);
     BG_CASE(4)
     BG_CASE(5)
     BG_CASE(6)
@@ -253,8 +362,31 @@ int cobg_fused_me2(int n, bool fp32, int64_t E, const double* mom, const int8_t*
   }
 }
 
+int cobg_fix_me2(int n, int64_t E, const double* mom, const int8_t* hel, const double* Cb,
+                 double* scratch, const unsigned* count, const unsigned* list, int grid,
+                 double* me2, hipStream_t stream) {
+  if (E <= 0) return 0;
+  switch (n) {
+    case 4: return fusedk::fix_launch<4>(E, mom, hel, Cb, scratch, count, list, grid, me2, stream);
+    case 5: return fusedk::fix_launch<5>(E, mom, hel, Cb, scratch, count, list, grid, me2, stream);
+    case 6: return fusedk::fix_launch<6>(E, mom, hel, Cb, scratch, count, list, grid, me2, stream);
+    case 7: return fusedk::fix_launch<7>(E, mom, hel, Cb, scratch, count, list, grid, me2, stream);
+    default: return -2;
+  }
+}
+
+int cobg_fix_blocks_per_cu(int n, bool hsum) {
+  switch (n) {
+    case 4: return fusedk::fix_occupancy<4>(hsum);
+    case 5: return fusedk::fix_occupancy<5>(hsum);
+    case 6: return fusedk::fix_occupancy<6>(hsum);
+    case 7: return fusedk::fix_occupancy<7>(hsum);
+    default: return -1;
+  }
+}
+
 // LDS of the batch kernel for one segment kind (header included).
-size_t batch_lds_bytes(int kind, int n, bool fp32) {
+size_t batch_lds_bytes(int kind, int n, bool fp32, bool chk) {
   if (kind == kBatchCobg) {
     size_t per_wave = 0;
     switch (n) {
@@ -273,50 +405,104 @@ size_t batch_lds_bytes(int kind, int n, bool fp32) {
     }
     return fusedk::kBatchHeader + fusedk::kBatchWaves * per_wave;
   }
-  const size_t c = cdbg_lds_bytes(n, fp32);
-  return c ? fusedk::kBatchHeader + c : 0;
+  size_t c = 0;
+  switch (n) {
+#define BG_CASE(NN)                                                                         \
+  case NN:                                                                                  \
+    c = !fp32 ? cdbgk::Lay<NN, double>::bytes()                                             \
+              : (chk ? cdbgk::Lay<NN, float, true>::bytes() : cdbgk::Lay<NN, float>::bytes()); \
+    break;
+    BG_CASE(4)
+    BG_CASE(5)
+    BG_CASE(6)
+    BG_CASE(7)
+    BG_CASE(8)
+    BG_CASE(9)
+#undef BG_CASE
+    default:
+      return 0;
+  }
+  return fusedk::kBatchHeader + c;
 }
 
 int batch_scratch_doubles(int n) { return fusedk::kBatchWaves * cobg_fused_scratch_doubles(n); }
 
-int batch_blocks_per_cu(bool fp32, int waves, size_t lds) {
+namespace fusedk {
+template <typename T, int WAVES, int PASS>
+int occupancy_of(size_t lds) {
   int nb = 0;
-  const int L = fusedk::kBatchLanes;
-  hipError_t e;
-  if (fp32)
-    e = waves == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fusedk::batch_kernel<float, 2>, L, lds)
-                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fusedk::batch_kernel<float, 1>, L, lds);
-  else
-    e = waves == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fusedk::batch_kernel<double, 2>, L, lds)
-                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fusedk::batch_kernel<double, 1>, L, lds);
-  return e == hipSuccess ? nb : -1;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<T, WAVES, PASS>,
+                                                      kBatchLanes, lds) == hipSuccess
+             ? nb
+             : -1;
 }
 
-namespace fusedk {
-template <typename T, int WAVES>
+template <typename T, int WAVES, int PASS>
 void launch_batch(const BatchSegTable& segs, const BatchTile* tiles, unsigned n_tiles,
-                  unsigned* counter, double* scratch, int64_t scratch_stride, int grid, size_t lds,
-                  hipStream_t stream) {
-  hipLaunchKernelGGL((batch_kernel<T, WAVES>), dim3(grid), dim3(kBatchLanes), lds, stream, segs,
-                     tiles, n_tiles, counter, scratch, scratch_stride);
+                  const unsigned* n_tiles_dev, unsigned* counter, double* scratch,
+                  int64_t scratch_stride, int grid, size_t lds, hipStream_t stream) {
+  hipLaunchKernelGGL((batch_kernel<T, WAVES, PASS>), dim3(grid), dim3(kBatchLanes), lds, stream,
+                     segs, tiles, n_tiles, n_tiles_dev, counter, scratch, scratch_stride);
+}
+
+// Instances: FP32 plain and checked, FP64 plain and re-evaluation.
+template <int WAVES>
+int occupancy_pass(bool fp32, int pass, size_t lds) {
+  if (fp32)
+    return pass == kBatchCheck ? occupancy_of<float, WAVES, kBatchCheck>(lds)
+                               : occupancy_of<float, WAVES, kBatchPlain>(lds);
+  return pass == kBatchFix ? occupancy_of<double, WAVES, kBatchFix>(lds)
+                           : occupancy_of<double, WAVES, kBatchPlain>(lds);
+}
+
+template <int WAVES>
+void launch_pass(bool fp32, int pass, const BatchSegTable& segs, const BatchTile* tiles,
+                 unsigned n_tiles, const unsigned* n_tiles_dev, unsigned* counter,
+                 double* scratch, int64_t scratch_stride, int grid, size_t lds,
+                 hipStream_t stream) {
+  if (fp32) {
+    if (pass == kBatchCheck)
+      launch_batch<float, WAVES, kBatchCheck>(segs, tiles, n_tiles, n_tiles_dev, counter, scratch,
+                                              scratch_stride, grid, lds, stream);
+    else
+      launch_batch<float, WAVES, kBatchPlain>(segs, tiles, n_tiles, n_tiles_dev, counter, scratch,
+                                              scratch_stride, grid, lds, stream);
+  } else {
+    if (pass == kBatchFix)
+      launch_batch<double, WAVES, kBatchFix>(segs, tiles, n_tiles, n_tiles_dev, counter, scratch,
+                                             scratch_stride, grid, lds, stream);
+    else
+      launch_batch<double, WAVES, kBatchPlain>(segs, tiles, n_tiles, n_tiles_dev, counter,
+                                               scratch, scratch_stride, grid, lds, stream);
+  }
 }
 }  // namespace fusedk
 
-int batch_launch(bool fp32, int waves, const BatchSegTable& segs, const BatchTile* tiles,
-                 unsigned n_tiles, unsigned* counter, double* scratch, int64_t scratch_stride,
-                 int grid, size_t lds, hipStream_t stream) {
+int batch_blocks_per_cu(bool fp32, int waves, int pass, size_t lds) {
+  if ((fp32 && pass == kBatchFix) || (!fp32 && pass == kBatchCheck)) return -1;
+  return waves == 2 ? fusedk::occupancy_pass<2>(fp32, pass, lds)
+                    : fusedk::occupancy_pass<1>(fp32, pass, lds);
+}
+
+int batch_launch(bool fp32, int waves, int pass, const BatchSegTable& segs,
+                 const BatchTile* tiles, unsigned n_tiles, const unsigned* n_tiles_dev,
+                 unsigned* counter, double* scratch, int64_t scratch_stride, int grid, size_t lds,
+                 hipStream_t stream) {
+  if ((fp32 && pass == kBatchFix) || (!fp32 && pass == kBatchCheck)) return -2;
   hipLaunchKernelGGL(fusedk::zero_counter_kernel, dim3(1), dim3(64), 0, stream, counter);
-  if (fp32) {
-    if (waves == 2)
-      fusedk::launch_batch<float, 2>(segs, tiles, n_tiles, counter, scratch, scratch_stride, grid, lds, stream);
-    else
-      fusedk::launch_batch<float, 1>(segs, tiles, n_tiles, counter, scratch, scratch_stride, grid, lds, stream);
-  } else {
-    if (waves == 2)
-      fusedk::launch_batch<double, 2>(segs, tiles, n_tiles, counter, scratch, scratch_stride, grid, lds, stream);
-    else
-      fusedk::launch_batch<double, 1>(segs, tiles, n_tiles, counter, scratch, scratch_stride, grid, lds, stream);
-  }
+  if (waves == 2)
+    fusedk::launch_pass<2>(fp32, pass, segs, tiles, n_tiles, n_tiles_dev, counter, scratch,
+                           scratch_stride, grid, lds, stream);
+  else
+    fusedk::launch_pass<1>(fp32, pass, segs, tiles, n_tiles, n_tiles_dev, counter, scratch,
+                           scratch_stride, grid, lds, stream);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int batch_fix_tiles(const BatchSegTable& segs, int n_segs, const unsigned* fcount,
+                    BatchTile* tiles, unsigned* n_tiles, hipStream_t stream) {
+  hipLaunchKernelGGL(fusedk::fix_tiles_kernel, dim3(1), dim3(256), 0, stream, segs, n_segs, fcount,
+                     tiles, n_tiles);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

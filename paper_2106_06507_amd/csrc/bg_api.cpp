@@ -3,6 +3,7 @@
 #include "bg.h"
 
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -27,7 +28,22 @@ struct BatchPlan {
   bg::BatchTile* tiles = nullptr;
   unsigned n_tiles = 0;
   uint64_t last_use = 0;
+  // FP32 plans: workspace of the check and of the FP64 re-evaluation pass:
+  // words [0, 32) listed-event counts per segment, word 32 the re-evaluation
+  // tile count, from word 64 the per-segment lists (list_off), then the
+  // re-evaluation tiles (at most max_fix_tiles).
+  unsigned* chk_ws = nullptr;
+  std::vector<size_t> list_off;
+  bg::BatchTile* fix_tiles = nullptr;
+  unsigned max_fix_tiles = 0;
 };
+
+void free_plan(BatchPlan& pl) {
+  if (pl.tiles) (void)hipFree(pl.tiles);
+  if (pl.chk_ws) (void)hipFree(pl.chk_ws);
+  pl.tiles = nullptr;
+  pl.chk_ws = nullptr;
+}
 
 }  // namespace
 
@@ -62,12 +78,22 @@ struct bg_context {
   bg_batch_config bcfg[2] = {{0, 128, 256, 2}, {0, 128, 256, 2}};
   std::vector<BatchPlan> plans;
   uint64_t clock = 0;
-  int occ_fused[2][2] = {};                  // blocks per CU of the persistent fused kernel
-                                             // [fp32][helicity sum], 0 = unknown
-  int occ_batch[2][2] = {};                  // of the batch kernel [fp32][variant] at its
-                                             // last LDS size
+  int occ_fused[2][2][2] = {};               // blocks per CU of the persistent fused kernel
+                                             // [fp32][helicity sum][checked], 0 = unknown
+  int occ_batch[4][2] = {};                  // of the batch kernel [fp32 * 2 + (pass != plain)]
+                                             // [variant] at its last LDS size
   int occ_cdbg[BG_N_MAX + 1][2] = {};        // of the colour-dressed event kernel
-  size_t occ_batch_lds[2][2] = {};
+  size_t occ_batch_lds[4][2] = {};
+  uint32_t flags = 0;                        // BG_FLAG_* applied to every request
+  float fp32_tau[2][BG_N_MAX + 1] = {};      // FP32 check thresholds [COBG, CDBG][n]
+  unsigned* flag_ws = nullptr;               // FP32 check: [0] count, list from word 64
+  size_t flag_ws_words = 0;
+  int occ_fix[BG_N_MAX + 1][2] = {};         // blocks per CU of the FP64 re-evaluation [n][hsum]
+  int occ_cdbg_chk[BG_N_MAX + 1] = {};       // of the checked FP32 colour-dressed event kernel
+  unsigned* val_dev = nullptr;               // BG_FLAG_VALIDATE result word
+  hipEvent_t ws_event = nullptr;             // recorded after each call that uses the workspace
+  hipStream_t ws_stream = nullptr;           // stream of that call
+  bool ws_pending = false;
 };
 
 namespace {
@@ -200,6 +226,27 @@ int ensure_ws(bg_context* ctx, size_t bytes) {
 
 bool valid_n(int n) { return n >= BG_N_MIN && n <= BG_N_MAX; }
 
+// Default FP32 check thresholds on est = sum S^2 / sum |A|^2 per n (the bound
+// S grows with the number of terms, so the threshold grows with n), measured
+// on 2^20 (n = 7: 2^18) sampled-helicity RAMBO events against the FP64 path.
+// Colour-ordered:
+//   n = 5: tau 3e5 lists 12% of the events, per-event error p99 6.8e-6;
+//   n = 6: tau 3e6 lists 17%, p99 5.9e-6;
+//   n = 7: tau 1e8 lists 15%, p99 6.9e-6;
+//   n = 4 is not checked: without the check its largest per-event error over
+//   2^20 events is 1.3e-6.
+// Colour-dressed, on the valid flows of 2^20 sampled-flow events (sampled
+// helicities), interpolating a sweep in decades of tau:
+//   n = 4: tau 1e8 lists 0.6% (p99 2.1e-6: already small without the check);
+//   n = 5: 3e5, ~17% (p99 ~7e-6);  n = 6: 2e6, ~27% (~6e-6);
+//   n = 7: 3e7, ~35% (~7e-6);      n = 8: 3e8, ~44% (~6e-6);
+//   n = 9: 5e9, ~48% (~6e-6).
+// The dressed bound is looser than the colour-ordered one (many more terms
+// per current), so larger fractions are listed.
+constexpr float kDefaultFp32Tau[2][BG_N_MAX + 1] = {
+    {0.f, 0.f, 0.f, 0.f, INFINITY, 3e5f, 3e6f, 1e8f, 0.f, 0.f},
+    {0.f, 0.f, 0.f, 0.f, 1e8f, 3e5f, 2e6f, 3e7f, 3e8f, 5e9f}};
+
 // Grows the per-block scratch.  An outgrown buffer is kept until the context
 // is destroyed, since a recorded graph may still refer to it.
 int ensure_scratch(bg_context* ctx, size_t bytes) {
@@ -214,6 +261,74 @@ int ensure_scratch(bg_context* ctx, size_t bytes) {
   ctx->scratch_bytes = want;
   return BG_OK;
 }
+
+// FP32 check workspace: a count word and a list of up to E event indices.
+constexpr size_t kFlagListOffset = 64;  // words: the list starts 256 bytes in
+int ensure_flags(bg_context* ctx, int64_t E) {
+  const size_t words = kFlagListOffset + (size_t)E;
+  if (ctx->flag_ws_words >= words) return BG_OK;
+  if (ctx->flag_ws) {
+    int st = hip_status(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    if (st) return st;
+    (void)hipFree(ctx->flag_ws);
+    ctx->flag_ws = nullptr;
+    ctx->flag_ws_words = 0;
+  }
+  const size_t want = std::max(words, (size_t)1024);
+  int st = hip_status(hipMalloc(&ctx->flag_ws, sizeof(unsigned) * want), "hipMalloc(check list)");
+  if (st) return st;
+  ctx->flag_ws_words = want;
+  return BG_OK;
+}
+
+bool capturing_stream(hipStream_t stream) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return false;
+  return cs == hipStreamCaptureStatusActive;
+}
+
+// Orders calls that share the context workspace across streams: a call on a
+// stream other than the previous call's waits for the event recorded after
+// that call.  Skipped while the stream captures (a graph cannot wait on an
+// event recorded outside it; replays are ordered by the caller).
+int ws_acquire(bg_context* ctx, hipStream_t stream) {
+  if (!ctx->ws_pending || ctx->ws_stream == stream || capturing_stream(stream)) return BG_OK;
+  return hip_status(hipStreamWaitEvent(stream, ctx->ws_event, 0), "hipStreamWaitEvent");
+}
+
+int ws_release(bg_context* ctx, hipStream_t stream, int status) {
+  if (status != BG_OK || capturing_stream(stream)) return status;
+  int st = hip_status(hipEventRecord(ctx->ws_event, stream), "hipEventRecord");
+  if (st) return st;
+  ctx->ws_stream = stream;
+  ctx->ws_pending = true;
+  return BG_OK;
+}
+
+// BG_FLAG_VALIDATE: every hel entry +-1, every col entry in {0, 1, 2}.
+int validate_values(bg_context* ctx, int n, int64_t E, const int8_t* hel, const int8_t* col,
+                    hipStream_t stream) {
+  if (capturing_stream(stream)) return BG_EINVAL;
+  if (!ctx->val_dev) {
+    int st = hip_status(hipMalloc(&ctx->val_dev, 256), "hipMalloc(validate)");
+    if (st) return st;
+  }
+  int st = launch_status(bg::fill_u32(ctx->val_dev, 1, 0u, stream));
+  if (!st)
+    st = launch_status(bg::validate_inputs(hel ? (int64_t)n * E : 0, hel,
+                                           col ? (int64_t)2 * n * E : 0, col, ctx->val_dev,
+                                           stream));
+  unsigned bad = 0;
+  if (!st)
+    st = hip_status(hipMemcpyAsync(&bad, ctx->val_dev, sizeof(unsigned), hipMemcpyDeviceToHost,
+                                   stream), "hipMemcpyAsync(validate)");
+  if (!st) st = hip_status(hipStreamSynchronize(stream), "hipStreamSynchronize");
+  if (st) return st;
+  return bad ? BG_EINVAL : BG_OK;
+}
+
+int grad_run(bg_context* ctx, const bg_request* r, const double* grad_me2, double* grad_mom,
+             hipStream_t s);
 
 // Lexicographic orderings of the middle gluons 1..n-2, as bytes [K][n-2].
 int ensure_perms(bg_context* ctx, int n) {
@@ -291,8 +406,9 @@ int bg_color_matrix(int n, double* out, int64_t cap) {
   return BG_OK;
 }
 
-int bg_context_create(bg_context** out, int device) {
+int bg_context_create(bg_context** out, int device, uint32_t flags) {
   if (!out) return BG_EINVAL;
+  if (flags & ~(BG_FLAG_VALIDATE | BG_FLAG_FP32_UNCHECKED)) return BG_EINVAL;
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return BG_ENODEV;
   if (device < 0 || device >= count) return BG_ENODEV;
@@ -308,6 +424,16 @@ int bg_context_create(bg_context** out, int device) {
   ctx->num_cus = prop.multiProcessorCount;
   ctx->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor;
   ctx->lds_per_block = prop.sharedMemPerBlock;
+  ctx->flags = flags;
+  for (int m = 0; m < 2; ++m)
+    for (int n = 0; n <= BG_N_MAX; ++n) ctx->fp32_tau[m][n] = kDefaultFp32Tau[m][n];
+  {
+    DeviceGuard g(device);
+    if (!g.ok || hipEventCreateWithFlags(&ctx->ws_event, hipEventDisableTiming) != hipSuccess) {
+      delete ctx;
+      return BG_EDEVICE;
+    }
+  }
   *out = ctx;
   return BG_OK;
 }
@@ -332,8 +458,10 @@ void bg_context_destroy(bg_context* ctx) {
   if (ctx->comc_amp) (void)hipFree(ctx->comc_amp);
   if (ctx->cdmc_state) (void)hipFree(ctx->cdmc_state);
   if (ctx->counter) (void)hipFree(ctx->counter);
-  for (BatchPlan& pl : ctx->plans)
-    if (pl.tiles) (void)hipFree(pl.tiles);
+  if (ctx->flag_ws) (void)hipFree(ctx->flag_ws);
+  if (ctx->val_dev) (void)hipFree(ctx->val_dev);
+  if (ctx->ws_event) (void)hipEventDestroy(ctx->ws_event);
+  for (BatchPlan& pl : ctx->plans) free_plan(pl);
   delete ctx;
 }
 
@@ -368,7 +496,7 @@ static int ensure_counters(bg_context* ctx) {
   return hip_status(hipMalloc(&ctx->counter, 256), "hipMalloc(counters)");
 }
 
-static int me2_cobg(bg_context* ctx, const bg_request* r, hipStream_t stream) {
+static int me2_cobg(bg_context* ctx, const bg_request* r, uint32_t flags, hipStream_t stream) {
   const int n = r->n;
   if (n > 7) return BG_EUNSUPPORTED;
   const int64_t E = r->n_events;
@@ -376,27 +504,53 @@ static int me2_cobg(bg_context* ctx, const bg_request* r, hipStream_t stream) {
   if (st) return st;
   const bool fp32 = r->precision == BG_PREC_FP32_MIXED;
   const bool hsum = r->hel == nullptr;
-  int64_t grid = 0;
+  const float tau = ctx->fp32_tau[0][n];
+  const bool check = fp32 && !(flags & BG_FLAG_FP32_UNCHECKED) && !(tau == INFINITY) &&
+                     E <= (int64_t)0xffffffffLL;
+  int64_t grid = 0, fix_grid = 0;
+  if (check) {
+    int& occ = ctx->occ_fix[n][hsum ? 1 : 0];
+    if (occ <= 0) occ = bg::cobg_fix_blocks_per_cu(n, hsum);
+    if (occ <= 0) return BG_EDEVICE;
+    fix_grid = std::min<int64_t>((E + 31) / 32, (int64_t)ctx->num_cus * occ);
+    st = ensure_flags(ctx, E);
+    if (st) return st;
+  }
   if (n == 7) {  // persistent kernel with per-block scratch
-    int& occ = ctx->occ_fused[fp32 ? 1 : 0][hsum ? 1 : 0];
-    if (occ <= 0) occ = bg::cobg_fused_persistent_blocks_per_cu(fp32, hsum);
+    int& occ = ctx->occ_fused[fp32 ? 1 : 0][hsum ? 1 : 0][check ? 1 : 0];
+    if (occ <= 0) occ = bg::cobg_fused_persistent_blocks_per_cu(fp32, hsum, check);
     if (occ <= 0) return BG_EDEVICE;
     grid = std::min<int64_t>((E + 31) / 32, (int64_t)ctx->num_cus * occ);
-    st = ensure_scratch(ctx, sizeof(double) * (size_t)grid * bg::cobg_fused_scratch_doubles(n));
+    st = ensure_scratch(ctx, sizeof(double) * (size_t)std::max(grid, fix_grid) *
+                                 bg::cobg_fused_scratch_doubles(n));
     if (!st) st = ensure_counters(ctx);
     if (st) return st;
   }
-  return launch_status(bg::cobg_fused_me2(n, fp32, E, r->mom, r->hel, ctx->Cb_dev[n], ctx->scratch,
-                                          ctx->counter ? ctx->counter + 1 : nullptr, (int)grid,
-                                          r->me2, stream));
+  bg::CheckArgs ca{tau, nullptr, nullptr};
+  if (check) {
+    ca.count = ctx->flag_ws;
+    ca.list = ctx->flag_ws + kFlagListOffset;
+    st = launch_status(bg::fill_u32(ca.count, 1, 0u, stream));
+    if (st) return st;
+  }
+  st = launch_status(bg::cobg_fused_me2(n, fp32, E, r->mom, r->hel, ctx->Cb_dev[n], ctx->scratch,
+                                        ctx->counter ? ctx->counter + 1 : nullptr, (int)grid,
+                                        r->me2, check ? &ca : nullptr, stream));
+  if (st || !check) return st;
+  return launch_status(bg::cobg_fix_me2(n, E, r->mom, r->hel, ctx->Cb_dev[n], ctx->scratch,
+                                        ca.count, ca.list, (int)fix_grid, r->me2, stream));
 }
 
-static int me2_cdbg(bg_context* ctx, const bg_request* r, hipStream_t stream) {
+static int me2_cdbg(bg_context* ctx, const bg_request* r, uint32_t flags, hipStream_t stream) {
   const int n = r->n;
+  const int64_t E = r->n_events;
   const bool fp32 = r->precision == BG_PREC_FP32_MIXED;
+  const float tau = ctx->fp32_tau[1][n];
+  const bool check = fp32 && !(flags & BG_FLAG_FP32_UNCHECKED) && !(tau == INFINITY) &&
+                     E <= (int64_t)0x7fffffffLL;
   const size_t lds = bg::cdbg_lds_bytes(n, fp32);
   if (lds == 0 || lds > ctx->lds_per_block) return BG_EUNSUPPORTED;
-  const size_t need = sizeof(unsigned) * (size_t)(2 + r->n_events);
+  const size_t need = sizeof(unsigned) * (size_t)(4 + 2 * E);
   if (ctx->cws_bytes < need) {
     if (ctx->cws) {
       int st = hip_status(hipDeviceSynchronize(), "hipDeviceSynchronize");
@@ -409,14 +563,21 @@ static int me2_cdbg(bg_context* ctx, const bg_request* r, hipStream_t stream) {
     if (st) return st;
     ctx->cws_bytes = need;
   }
-  int& per_cu = ctx->occ_cdbg[n][fp32 ? 1 : 0];
-  if (per_cu <= 0) per_cu = bg::cdbg_blocks_per_cu(n, fp32);
+  int& per_cu = check ? ctx->occ_cdbg_chk[n] : ctx->occ_cdbg[n][fp32 ? 1 : 0];
+  if (per_cu <= 0) per_cu = bg::cdbg_blocks_per_cu(n, fp32, check);
   if (per_cu <= 0) return BG_EUNSUPPORTED;
-  int64_t grid = (int64_t)ctx->num_cus * (int64_t)per_cu;
-  if (grid > r->n_events) grid = r->n_events;
+  int64_t grid = std::min<int64_t>((int64_t)ctx->num_cus * (int64_t)per_cu, E);
   if (grid < 1) grid = 1;
-  return launch_status(bg::cdbg_me2(n, fp32, r->n_events, r->mom, r->hel, r->col, ctx->cws, r->me2,
-                                    (int)grid, stream));
+  int64_t fix_grid = 0;
+  if (check) {
+    int& per_cu64 = ctx->occ_cdbg[n][0];
+    if (per_cu64 <= 0) per_cu64 = bg::cdbg_blocks_per_cu(n, false, false);
+    if (per_cu64 <= 0) return BG_EUNSUPPORTED;
+    fix_grid = std::max<int64_t>(1, std::min<int64_t>((int64_t)ctx->num_cus * per_cu64, E));
+  }
+  bg::CheckArgs ca{tau, nullptr, nullptr};
+  return launch_status(bg::cdbg_me2(n, fp32, E, r->mom, r->hel, r->col, ctx->cws, r->me2,
+                                    (int)grid, check ? &ca : nullptr, (int)fix_grid, stream));
 }
 
 static int me2_comc(bg_context* ctx, const bg_request* r, hipStream_t stream) {
@@ -493,7 +654,7 @@ static int validate_request(const bg_request* r) {
   if (!valid_n(r->n)) return BG_EINVAL;
   if (r->mode < BG_MODE_COBG || r->mode > BG_MODE_COMC) return BG_EINVAL;
   if (r->precision != BG_PREC_FP64 && r->precision != BG_PREC_FP32_MIXED) return BG_EINVAL;
-  if (r->reserved != 0) return BG_EINVAL;
+  if (r->flags & ~(BG_FLAG_VALIDATE | BG_FLAG_FP32_UNCHECKED)) return BG_EINVAL;
   int st = check_events(r->n, r->n_events);
   if (st) return st;
   if (r->n_events == 0) return BG_OK;
@@ -501,6 +662,19 @@ static int validate_request(const bg_request* r) {
   const int mode = r->mode == BG_MODE_AUTO ? (r->n <= 7 ? BG_MODE_COBG : BG_MODE_CDBG) : r->mode;
   if ((mode == BG_MODE_CDBG || mode == BG_MODE_COMC) && (!r->col || !r->hel)) return BG_EINVAL;
   return BG_OK;
+}
+
+static int me2_dispatch(bg_context* ctx, const bg_request* r, uint32_t flags, hipStream_t stream) {
+  const int mode = r->mode == BG_MODE_AUTO ? (r->n <= 7 ? BG_MODE_COBG : BG_MODE_CDBG) : r->mode;
+  if (mode == BG_MODE_COBG) return me2_cobg(ctx, r, flags, stream);
+  if (mode == BG_MODE_COMC) return me2_comc(ctx, r, stream);
+  if (mode == BG_MODE_LC) {
+    if (r->n > 7) return BG_EUNSUPPORTED;
+    if (!r->hel) return BG_EINVAL;
+    return launch_status(bg::lc_me2(r->n, r->precision == BG_PREC_FP32_MIXED, r->n_events, r->mom,
+                                    r->hel, r->me2, stream));
+  }
+  return me2_cdbg(ctx, r, flags, stream);
 }
 
 int bg_me2(bg_context* ctx, const bg_request* r, void* stream) {
@@ -511,16 +685,33 @@ int bg_me2(bg_context* ctx, const bg_request* r, void* stream) {
   if (r->n_events == 0) return BG_OK;
   DeviceGuard g(ctx->device);
   if (!g.ok) return BG_EDEVICE;
-  const int mode = r->mode == BG_MODE_AUTO ? (r->n <= 7 ? BG_MODE_COBG : BG_MODE_CDBG) : r->mode;
-  if (mode == BG_MODE_COBG) return me2_cobg(ctx, r, (hipStream_t)stream);
-  if (mode == BG_MODE_COMC) return me2_comc(ctx, r, (hipStream_t)stream);
-  if (mode == BG_MODE_LC) {
-    if (r->n > 7) return BG_EUNSUPPORTED;
-    if (!r->hel) return BG_EINVAL;
-    return launch_status(bg::lc_me2(r->n, r->precision == BG_PREC_FP32_MIXED, r->n_events, r->mom,
-                                    r->hel, r->me2, (hipStream_t)stream));
-  }
-  return me2_cdbg(ctx, r, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  const uint32_t flags = r->flags | ctx->flags;
+  st = ws_acquire(ctx, s);
+  if (!st && (flags & BG_FLAG_VALIDATE))
+    st = validate_values(ctx, r->n, r->n_events, r->hel, r->col, s);
+  if (!st) st = me2_dispatch(ctx, r, flags, s);
+  return ws_release(ctx, s, st);
+}
+
+static int check_slot(int mode, int n) {
+  if (mode == BG_MODE_COBG && n >= 4 && n <= 7) return 0;
+  if (mode == BG_MODE_CDBG && valid_n(n)) return 1;
+  return -1;
+}
+
+int bg_fp32_check_set(bg_context* ctx, int mode, int n, float tau) {
+  const int m = check_slot(mode, n);
+  if (!ctx || m < 0 || !(tau >= 0.0f)) return BG_EINVAL;
+  ctx->fp32_tau[m][n] = tau;
+  return BG_OK;
+}
+
+int bg_fp32_check_get(bg_context* ctx, int mode, int n, float* tau) {
+  const int m = check_slot(mode, n);
+  if (!ctx || !tau || m < 0) return BG_EINVAL;
+  *tau = ctx->fp32_tau[m][n];
+  return BG_OK;
 }
 
 int bg_me2_grad(bg_context* ctx, const bg_request* r, const double* grad_me2, double* grad_mom,
@@ -536,6 +727,20 @@ int bg_me2_grad(bg_context* ctx, const bg_request* r, const double* grad_me2, do
   DeviceGuard g(ctx->device);
   if (!g.ok) return BG_EDEVICE;
   hipStream_t s = (hipStream_t)stream;
+  st = ws_acquire(ctx, s);
+  if (!st && ((r->flags | ctx->flags) & BG_FLAG_VALIDATE))
+    st = validate_values(ctx, r->n, r->n_events, r->hel, r->col, s);
+  if (!st) st = grad_run(ctx, r, grad_me2, grad_mom, s);
+  return ws_release(ctx, s, st);
+}
+
+}  // extern "C"
+
+namespace {
+
+int grad_run(bg_context* ctx, const bg_request* r, const double* grad_me2, double* grad_mom,
+             hipStream_t s) {
+  int st = BG_OK;
   const int n = r->n;
   const int64_t K = bg::factorial(n - 2);
   const int64_t E = r->n_events;
@@ -553,10 +758,6 @@ int bg_me2_grad(bg_context* ctx, const bg_request* r, const double* grad_me2, do
         bg::cobg_gradient(n, fp32, E, r->mom, r->hel, Y, grad_me2, ctx->perms_dev[n], grad_mom, s));
   return st;
 }
-
-}  // extern "C"
-
-namespace {
 
 int resolved_mode(const bg_request* r) {
   return r->mode == BG_MODE_AUTO ? (r->n <= 7 ? BG_MODE_COBG : BG_MODE_CDBG) : r->mode;
@@ -680,9 +881,32 @@ int batch_plan(bg_context* ctx, const bg_request* segs, int n_segs, const bg_bat
                               hipMemcpyHostToDevice),
                     "hipMemcpy(tiles)");
     if (st) {
-      (void)hipFree(pl.tiles);
+      free_plan(pl);
       return st;
     }
+  }
+  if (fp32) {
+    size_t words = 64;
+    uint64_t fix_tiles = 0;
+    for (int i = 0; i < n_segs; ++i) {
+      pl.list_off.push_back(words);
+      words += (size_t)segs[i].n_events;
+      const int64_t step = resolved_mode(&segs[i]) == BG_MODE_CDBG ? 256 : 128;
+      fix_tiles += (uint64_t)((segs[i].n_events + step - 1) / step);
+    }
+    if (fix_tiles > 0x7fffffffu) {
+      free_plan(pl);
+      return BG_ERANGE;
+    }
+    words = (words + 3) / 4 * 4;  // 16-byte alignment of the tile array
+    pl.max_fix_tiles = (unsigned)fix_tiles;
+    const size_t bytes = sizeof(unsigned) * words + sizeof(bg::BatchTile) * (fix_tiles + 1);
+    int st = hip_status(hipMalloc(&pl.chk_ws, bytes), "hipMalloc(batch check)");
+    if (st) {
+      free_plan(pl);
+      return st;
+    }
+    pl.fix_tiles = reinterpret_cast<bg::BatchTile*>(pl.chk_ws + words);
   }
   if (ctx->plans.size() >= BG_BATCH_MAX_PLANS) {
     auto lru = std::min_element(ctx->plans.begin(), ctx->plans.end(),
@@ -691,10 +915,10 @@ int batch_plan(bg_context* ctx, const bg_request* segs, int n_segs, const bg_bat
                                 });
     int st = hip_status(hipDeviceSynchronize(), "hipDeviceSynchronize");
     if (st) {
-      if (pl.tiles) (void)hipFree(pl.tiles);
+      free_plan(pl);
       return st;
     }
-    if (lru->tiles) (void)hipFree(lru->tiles);
+    free_plan(*lru);
     ctx->plans.erase(lru);
   }
   pl.last_use = ++ctx->clock;
@@ -704,13 +928,30 @@ int batch_plan(bg_context* ctx, const bg_request* segs, int n_segs, const bg_bat
   return BG_OK;
 }
 
+// Blocks per CU of a batch pass at an LDS size (cached per pass and variant).
+int batch_occ(bg_context* ctx, bool fp32, int waves, int pass, size_t lds, bool capturing) {
+  const int wi = waves - 1;
+  const int k = (fp32 ? 2 : 0) + (pass != bg::kBatchPlain ? 1 : 0);
+  if (ctx->occ_batch[k][wi] <= 0 || ctx->occ_batch_lds[k][wi] != lds) {
+    if (capturing) return -1;
+    ctx->occ_batch[k][wi] = bg::batch_blocks_per_cu(fp32, waves, pass, lds);
+    ctx->occ_batch_lds[k][wi] = lds;
+  }
+  return ctx->occ_batch[k][wi];
+}
+
 int batch_run(bg_context* ctx, const bg_request* segs, int n_segs, const bg_batch_config& cfg,
               hipStream_t stream) {
   const bool capturing = stream_capturing(stream);
   const bool fp32 = segs[0].precision == BG_PREC_FP32_MIXED;
+  bool check = false;
+  if (fp32)
+    for (int i = 0; i < n_segs; ++i)
+      if (segs[i].n_events > 0 && !((segs[i].flags | ctx->flags) & BG_FLAG_FP32_UNCHECKED))
+        check = true;
   bg::BatchSegTable tab;
   memset(&tab, 0, sizeof(tab));
-  size_t lds = 0;
+  size_t lds = 0, lds64 = 0;
   int64_t stride = 0;
   for (int i = 0; i < n_segs; ++i) {
     const bg_request* r = &segs[i];
@@ -723,6 +964,7 @@ int batch_run(bg_context* ctx, const bg_request* segs, int n_segs, const bg_batc
     b.E = r->n_events;
     b.kind = (cd ? bg::kBatchCdbg : bg::kBatchCobg) + r->n;
     if (r->n_events == 0) continue;
+    const int kind = cd ? bg::kBatchCdbg : bg::kBatchCobg;
     if (!cd) {
       if (!ctx->Cb_dev[r->n]) {
         if (capturing) return BG_EINVAL;
@@ -731,28 +973,34 @@ int batch_run(bg_context* ctx, const bg_request* segs, int n_segs, const bg_batc
       }
       b.Cl = ctx->Cb_dev[r->n];
       stride = std::max<int64_t>(stride, bg::batch_scratch_doubles(r->n));
-      lds = std::max(lds, bg::batch_lds_bytes(bg::kBatchCobg, r->n, fp32));
-    } else {
-      lds = std::max(lds, bg::batch_lds_bytes(bg::kBatchCdbg, r->n, fp32));
     }
+    lds = std::max(lds, bg::batch_lds_bytes(kind, r->n, fp32, check));
+    lds64 = std::max(lds64, bg::batch_lds_bytes(kind, r->n, false));
   }
   BatchPlan* pl = nullptr;
   int st = batch_plan(ctx, segs, n_segs, cfg, capturing, &pl);
   if (st) return st;
   if (pl->n_tiles == 0) return BG_OK;
-  const int fi = fp32 ? 1 : 0;
   const int waves = cfg.waves_per_simd == 1 ? 1 : 2;
-  const int wi = waves - 1;
-  if (ctx->occ_batch[fi][wi] <= 0 || ctx->occ_batch_lds[fi][wi] != lds) {
-    if (capturing) return BG_EINVAL;
-    ctx->occ_batch[fi][wi] = bg::batch_blocks_per_cu(fp32, waves, lds);
-    ctx->occ_batch_lds[fi][wi] = lds;
-  }
-  const int occ = ctx->occ_batch[fi][wi];
+  const int pass = check ? bg::kBatchCheck : bg::kBatchPlain;
+  const int occ = batch_occ(ctx, fp32, waves, pass, lds, capturing);
+  if (occ == -1 && capturing) return BG_EINVAL;
   if (occ <= 0) return BG_EUNSUPPORTED;
   const int bpc = cfg.blocks_per_cu > 0 ? std::min(cfg.blocks_per_cu, occ) : occ;
   const int64_t grid = std::min<int64_t>((int64_t)ctx->num_cus * bpc, pl->n_tiles);
-  const size_t need = sizeof(double) * (size_t)grid * (size_t)stride;
+  // the re-evaluation pass runs the FP64 variant with the FP64 config's register budget
+  const bg_batch_config& cfg64 = ctx->bcfg[0];
+  const int waves64 = cfg64.waves_per_simd == 1 ? 1 : 2;
+  int64_t grid64 = 0;
+  if (check) {
+    const int occ64 = batch_occ(ctx, false, waves64, bg::kBatchFix, lds64, capturing);
+    if (occ64 == -1 && capturing) return BG_EINVAL;
+    if (occ64 <= 0) return BG_EUNSUPPORTED;
+    const int bpc64 = cfg64.blocks_per_cu > 0 ? std::min(cfg64.blocks_per_cu, occ64) : occ64;
+    grid64 = std::min<int64_t>((int64_t)ctx->num_cus * bpc64, pl->max_fix_tiles);
+    grid64 = std::max<int64_t>(grid64, 1);
+  }
+  const size_t need = sizeof(double) * (size_t)std::max(grid, grid64) * (size_t)stride;
   if (ctx->scratch_bytes < std::max<size_t>(need, 256) || !ctx->counter) {
     if (capturing) {
       BG_LOG("bg_me2_batch: workspace not prepared before graph capture");
@@ -762,8 +1010,32 @@ int batch_run(bg_context* ctx, const bg_request* segs, int n_segs, const bg_batc
     if (!st) st = ensure_counters(ctx);
     if (st) return st;
   }
-  return launch_status(bg::batch_launch(fp32, waves, tab, pl->tiles, pl->n_tiles, ctx->counter,
-                                        ctx->scratch, stride, (int)grid, lds, stream));
+  if (!check)
+    return launch_status(bg::batch_launch(fp32, waves, bg::kBatchPlain, tab, pl->tiles,
+                                          pl->n_tiles, nullptr, ctx->counter, ctx->scratch,
+                                          stride, (int)grid, lds, stream));
+  for (int i = 0; i < n_segs; ++i) {
+    const bg_request* r = &segs[i];
+    bg::BatchSeg& b = tab.s[i];
+    const bool cd = resolved_mode(r) == BG_MODE_CDBG;
+    b.fcount = pl->chk_ws + i;
+    b.flist = pl->chk_ws + pl->list_off[i];
+    b.tau = ((r->flags | ctx->flags) & BG_FLAG_FP32_UNCHECKED) ? INFINITY
+                                                               : ctx->fp32_tau[cd ? 1 : 0][r->n];
+  }
+  st = launch_status(bg::fill_u32(pl->chk_ws, 33, 0u, stream));
+  if (!st)
+    st = launch_status(bg::batch_launch(true, waves, bg::kBatchCheck, tab, pl->tiles, pl->n_tiles,
+                                        nullptr, ctx->counter, ctx->scratch, stride, (int)grid,
+                                        lds, stream));
+  if (!st)
+    st = launch_status(bg::batch_fix_tiles(tab, n_segs, pl->chk_ws, pl->fix_tiles,
+                                           pl->chk_ws + 32, stream));
+  if (st) return st;
+  for (int i = 0; i < n_segs; ++i) tab.s[i].idx = tab.s[i].flist;
+  return launch_status(bg::batch_launch(false, waves64, bg::kBatchFix, tab, pl->fix_tiles, 0,
+                                        pl->chk_ws + 32, ctx->counter, ctx->scratch, stride,
+                                        (int)grid64, lds64, stream));
 }
 
 bool valid_config(const bg_batch_config* c) {
@@ -784,7 +1056,13 @@ int bg_me2_batch(bg_context* ctx, const bg_request* segs, int n_segs, void* stre
   DeviceGuard g(ctx->device);
   if (!g.ok) return BG_EDEVICE;
   const int fi = segs[0].precision == BG_PREC_FP32_MIXED ? 1 : 0;
-  return batch_run(ctx, segs, n_segs, ctx->bcfg[fi], (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  st = ws_acquire(ctx, s);
+  for (int i = 0; i < n_segs && !st; ++i)
+    if ((segs[i].flags | ctx->flags) & BG_FLAG_VALIDATE)
+      st = validate_values(ctx, segs[i].n, segs[i].n_events, segs[i].hel, segs[i].col, s);
+  if (!st) st = batch_run(ctx, segs, n_segs, ctx->bcfg[fi], s);
+  return ws_release(ctx, s, st);
 }
 
 int bg_batch_config_get(bg_context* ctx, int precision, bg_batch_config* out) {
@@ -915,8 +1193,11 @@ int bg_me2_continuous(bg_context* ctx, int n, int precision, int64_t n_events, c
     }
     gstate = ctx->cdmc_state;
   }
-  return launch_status(bg::cdmc_me2(n, fp32, n_events, mom, phi, eta, gstate, (int)grid, me2,
+  st = ws_acquire(ctx, (hipStream_t)stream);
+  if (!st)
+    st = launch_status(bg::cdmc_me2(n, fp32, n_events, mom, phi, eta, gstate, (int)grid, me2,
                                     (hipStream_t)stream));
+  return ws_release(ctx, (hipStream_t)stream, st);
 }
 
 int bg_generate_continuous(bg_context* ctx, int n, uint64_t seed, uint64_t first_event,
@@ -966,10 +1247,13 @@ int bg_generate(bg_context* ctx, const bg_gen_params* gp, int64_t n_attempts, in
   p.dr_min = gp->dr_min;
   p.seed = gp->seed;
   p.first_attempt = gp->first_attempt;
-  return launch_status(bg::generate_events(p, n_attempts, max_events, ctx->gen_ws, mom,
+  st = ws_acquire(ctx, (hipStream_t)stream);
+  if (!st)
+    st = launch_status(bg::generate_events(p, n_attempts, max_events, ctx->gen_ws, mom,
                                            (gp->flags & BG_GEN_HEL) ? hel : nullptr,
                                            (gp->flags & BG_GEN_COL) ? col : nullptr, attempt,
                                            n_generated, (hipStream_t)stream));
+  return ws_release(ctx, (hipStream_t)stream, st);
 }
 
 int bg_mfma_layout_probe(bg_context* ctx, double* out) {

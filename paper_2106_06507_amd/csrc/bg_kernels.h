@@ -23,6 +23,13 @@ inline int64_t factorial(int k) {
   return r;
 }
 
+// p[0..n) = v on `stream` (a kernel, so it can be recorded into a graph).
+int fill_u32(unsigned* p, int n, unsigned v, hipStream_t stream);
+// bad[0] |= 1 when one of the nh bytes of hel is not +-1 or one of the nc
+// bytes of col is not 0, 1 or 2 (either pointer may be null with size 0).
+int validate_inputs(int64_t nh, const int8_t* hel, int64_t nc, const int8_t* col, unsigned* bad,
+                    hipStream_t stream);
+
 // Partial amplitudes amp [2][K][E] for one helicity per event.  hel may be
 // null, in which case helicity configuration `hconf` is used for every event
 // (bit n-1-i set means gluon i has helicity -1).
@@ -40,14 +47,6 @@ int cobg_gradient(int n, bool fp32, int64_t E, const double* mom, const int8_t* 
 int contract_y(int K, int64_t E, const double* amp, const double* C, double* Y, double* me2,
                hipStream_t stream);
 
-// Colour-dressed |A|^2 for one colour-flow assignment per event.  ws holds
-// 2 + E unsigned (counters, compacted list of valid events); grid is the
-// number of persistent blocks (256 lanes each, one event at a time).
-int cdbg_me2(int n, bool fp32, int64_t E, const double* mom, const int8_t* hel, const int8_t* col,
-             unsigned* ws, double* me2, int grid, hipStream_t stream);
-size_t cdbg_lds_bytes(int n, bool fp32);
-int cdbg_blocks_per_cu(int n, bool fp32);
-
 // me2[e] (+)= sum_st C_st Re(A_s conj(A_t)); C is K x K row-major on device.
 int contract_valu(int K, int64_t E, const double* amp, const double* C, double* me2,
                   int accumulate, hipStream_t stream);
@@ -55,19 +54,47 @@ int mfma_probe(double* out_dev, hipStream_t stream);
 int contract_mfma(int K, int64_t E, const double* amp, const double* C_pad, int KP, double* me2,
                   int accumulate, hipStream_t stream);
 
+// Check of an FP32 pass: events whose rounding-error estimate exceeds tau
+// are appended to list (count must be zero before the pass; list holds E
+// entries).
+struct CheckArgs {
+  float tau;
+  unsigned* count;
+  unsigned* list;
+};
+
+// Colour-dressed |A|^2 for one colour-flow assignment per event.  ws holds
+// 4 + 2 E unsigned (counters, compacted list of valid events, list of events
+// for the FP64 re-evaluation); grid is the number of persistent blocks
+// (NL lanes each, one event at a time).  chk (FP32 only, may be null): list
+// the ill-conditioned events and evaluate them again in FP64 on fix_grid
+// blocks.
+int cdbg_me2(int n, bool fp32, int64_t E, const double* mom, const int8_t* hel, const int8_t* col,
+             unsigned* ws, double* me2, int grid, const CheckArgs* chk, int fix_grid,
+             hipStream_t stream);
+size_t cdbg_lds_bytes(int n, bool fp32);
+int cdbg_blocks_per_cu(int n, bool fp32, bool chk);
+
 // Fused colour-ordered |M|^2: recursion and colour sum in one kernel.  Cb is
 // the colour matrix as doubled lower triangle in row blocks.  n <= 6: one
 // block per 32-event tile (scratch, counter and grid unused).  n = 7:
 // persistent grid of `grid` blocks over an atomic tile queue; scratch holds
-// grid * cobg_fused_scratch_doubles(7) doubles, counter one unsigned.
+// grid * cobg_fused_scratch_doubles(7) doubles, counter one unsigned.  chk
+// (FP32 only, may be null): list the ill-conditioned events.
 int cobg_fused_me2(int n, bool fp32, int64_t E, const double* mom, const int8_t* hel,
                    const double* Cb, double* scratch, unsigned* counter, int grid, double* me2,
-                   hipStream_t stream);
+                   const CheckArgs* chk, hipStream_t stream);
+// FP64 re-evaluation of the *count events in list (persistent grid; scratch:
+// grid * cobg_fused_scratch_doubles(n) doubles).
+int cobg_fix_me2(int n, int64_t E, const double* mom, const int8_t* hel, const double* Cb,
+                 double* scratch, const unsigned* count, const unsigned* list, int grid,
+                 double* me2, hipStream_t stream);
+int cobg_fix_blocks_per_cu(int n, bool hsum);
 int cobg_fused_scratch_doubles(int n);
 // Leading-colour |M|^2 over all (n-1)! orderings, one helicity per event.
 int lc_me2(int n, bool fp32, int64_t E, const double* mom, const int8_t* hel, double* me2,
            hipStream_t stream);
-int cobg_fused_persistent_blocks_per_cu(bool fp32, bool hsum);
+int cobg_fused_persistent_blocks_per_cu(bool fp32, bool hsum, bool chk);
 // LDS of a colour-ordered tile (recursion state plus staged amplitudes).
 size_t cobg_lds_bytes(int n, bool fp32);
 
@@ -81,9 +108,12 @@ struct BatchSeg {
   const int8_t* col;   // [2][n][E] (colour-dressed only)
   double* me2;         // [E]
   const double* Cl;    // doubled lower-triangle colour matrix (colour-ordered only)
+  const unsigned* idx; // re-evaluation pass: the tile's events are idx[first ..]
+  unsigned* flist;     // checked FP32 pass: ill-conditioned events of the segment
+  unsigned* fcount;    // checked FP32 pass: their number
   int64_t E;
   int kind;
-  int pad;
+  float tau;           // checked FP32 pass: threshold of the segment's mode and n
 };
 
 struct BatchTile {
@@ -101,16 +131,27 @@ struct BatchSegTable {
 };
 
 // Batch blocks are 256 lanes.  LDS for a segment kind (kBatchCobg or
-// kBatchCdbg, without n) and per-block scratch doubles for colour-ordered n.
-size_t batch_lds_bytes(int kind, int n, bool fp32);
+// kBatchCdbg, without n) and per-block scratch doubles for colour-ordered n;
+// chk: the checked FP32 pass (the colour-dressed state carries its bounds).
+size_t batch_lds_bytes(int kind, int n, bool fp32, bool chk = false);
 int batch_scratch_doubles(int n);
+// Pass of the batch kernel: plain, checked FP32 (lists ill-conditioned
+// events per segment), or the FP64 re-evaluation of the listed events.
+enum BatchPass { kBatchPlain = 0, kBatchCheck = 1, kBatchFix = 2 };
 // waves: register budget variant, 1 (one wave per SIMD, no cap) or 2 (at
 // most 256 registers per lane).
-int batch_blocks_per_cu(bool fp32, int waves, size_t lds);
-// Enqueues the counter reset and the persistent kernel on stream.
-int batch_launch(bool fp32, int waves, const BatchSegTable& segs, const BatchTile* tiles,
-                 unsigned n_tiles, unsigned* counter, double* scratch, int64_t scratch_stride,
-                 int grid, size_t lds, hipStream_t stream);
+int batch_blocks_per_cu(bool fp32, int waves, int pass, size_t lds);
+// Enqueues the counter reset and the persistent kernel on stream.  n_tiles_dev
+// (may be null): the tile count is read on the device instead.
+int batch_launch(bool fp32, int waves, int pass, const BatchSegTable& segs,
+                 const BatchTile* tiles, unsigned n_tiles, const unsigned* n_tiles_dev,
+                 unsigned* counter, double* scratch, int64_t scratch_stride, int grid, size_t lds,
+                 hipStream_t stream);
+// Tiles of the re-evaluation pass from the per-segment counts fcount[s] of
+// listed events: colour-ordered tiles of up to 128 listed events, colour-
+// dressed tiles of up to 256; tiles[], *n_tiles on the device.
+int batch_fix_tiles(const BatchSegTable& segs, int n_segs, const unsigned* fcount,
+                    BatchTile* tiles, unsigned* n_tiles, hipStream_t stream);
 
 // Colour-sampled colour-ordered |A|^2 (comc.hip).  count: counts, offsets
 // and the valid-event list [E] each, block_items and block_valid

@@ -39,25 +39,46 @@ struct EventLanes {
   static constexpr int value = N <= 8 ? 128 : 256;
 };
 
-template <int N, typename T>
+template <int N, typename T, bool EST = false>
 int launch_events(int64_t E, const double* mom, const int8_t* hel, const int8_t* col,
-                  const unsigned* list, const unsigned* counters, double* me2, int grid,
-                  hipStream_t stream) {
+                  const unsigned* list, const unsigned* count, unsigned* work, double* me2,
+                  int grid, DressedCheck chk, hipStream_t stream) {
   constexpr int NL = EventLanes<N>::value;
-  hipLaunchKernelGGL((cdbg_event_kernel<N, T, NL>), dim3(grid), dim3(NL), (Lay<N, T>::bytes()),
-                     stream, E, mom, hel, col, list, counters, const_cast<unsigned*>(counters) + 1,
-                     me2);
+  hipLaunchKernelGGL((cdbg_event_kernel<N, T, NL, EST>), dim3(grid), dim3(NL),
+                     (Lay<N, T, EST>::bytes()), stream, E, mom, hel, col, list, count, work, me2,
+                     chk);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template <int N, typename T>
+template <int N, typename T, bool EST = false>
 int event_occupancy() {
   constexpr int NL = EventLanes<N>::value;
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cdbg_event_kernel<N, T, NL>, NL,
-                                                   Lay<N, T>::bytes()) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cdbg_event_kernel<N, T, NL, EST>, NL,
+                                                   Lay<N, T, EST>::bytes()) != hipSuccess)
     return -1;
   return nb;
+}
+
+// The valid events (FP32 with the check when chk is given, else T), then
+// the FP64 re-evaluation of the listed ones.
+template <int N>
+int run_events(bool fp32, int64_t E, const double* mom, const int8_t* hel, const int8_t* col,
+               unsigned* ws, double* me2, int grid, const CheckArgs* chk, int fix_grid,
+               hipStream_t stream) {
+  const unsigned* list = ws + 4;
+  if (!fp32)
+    return launch_events<N, double>(E, mom, hel, col, list, ws, ws + 1, me2, grid, DressedCheck{},
+                                    stream);
+  if (!chk)
+    return launch_events<N, float>(E, mom, hel, col, list, ws, ws + 1, me2, grid, DressedCheck{},
+                                   stream);
+  unsigned* flist = ws + 4 + E;
+  int r = launch_events<N, float, true>(E, mom, hel, col, list, ws, ws + 1, me2, grid,
+                                        DressedCheck{chk->tau, ws + 2, flist}, stream);
+  if (r) return r;
+  return launch_events<N, double>(E, mom, hel, col, flist, ws + 2, ws + 3, me2, fix_grid,
+                                  DressedCheck{}, stream);
 }
 
 }  // namespace cdbgk
@@ -74,36 +95,13 @@ size_t cdbg_lds_bytes(int n, bool fp32) {
   }
 }
 
-int cdbg_blocks_per_cu(int n, bool fp32) {
+int cdbg_blocks_per_cu(int n, bool fp32, bool chk) {
   switch (n) {
-    case 4: return fp32 ? cdbgk::event_occupancy<4, float>() : cdbgk::event_occupancy<4, double>();
-    case 5: return fp32 ? cdbgk::event_occupancy<5, float>() : cdbgk::event_occupancy<5, double>();
-    case 6: return fp32 ? cdbgk::event_occupancy<6, float>() : cdbgk::event_occupancy<6, double>();
-    case 7: return fp32 ? cdbgk::event_occupancy<7, float>() : cdbgk::event_occupancy<7, double>();
-    case 8: return fp32 ? cdbgk::event_occupancy<8, float>() : cdbgk::event_occupancy<8, double>();
-    case 9: return fp32 ? cdbgk::event_occupancy<9, float>() : cdbgk::event_occupancy<9, double>();
-    default: return -2;
-  }
-}
-
-// ws: unsigned [2 + E] (counters then event list).  Stream-ordered; the event
-// count stays on the device.
-int cdbg_me2(int n, bool fp32, int64_t E, const double* mom, const int8_t* hel, const int8_t* col,
-             unsigned* ws, double* me2, int grid, hipStream_t stream) {
-  if (E <= 0) return 0;
-  unsigned* counters = ws;
-  unsigned* list = ws + 2;
-  hipLaunchKernelGGL(cdbgk::zero_u32_kernel, dim3(1), dim3(64), 0, stream, counters, 2);
-  hipLaunchKernelGGL(cdbgk::cdbg_classify_kernel, dim3((unsigned)((E + 255) / 256)), dim3(256), 0,
-                     stream, n, E, col, me2, list, counters);
-  if (hipGetLastError() != hipSuccess) return -1;
-  switch (n) {
-#define BG_CASE(NN)                                                                             \
-  case NN:                                                                                      \
-    return fp32 ? cdbgk::launch_events<NN, float>(E, mom, hel, col, list, counters, me2, grid,  \
-                                                  stream)                                       \
-                : cdbgk::launch_events<NN, double>(E, mom, hel, col, list, counters, me2, grid, \
-                                                   stream);
+#define BG_CASE(NN)                                                                     \
+  case NN:                                                                              \
+    return !fp32 ? cdbgk::event_occupancy<NN, double>()                                 \
+                 : (chk ? cdbgk::event_occupancy<NN, float, true>()                     \
+                        : cdbgk::event_occupancy<NN, float>());
     BG_CASE(4)
     BG_CASE(5)
     BG_CASE(6)
@@ -111,8 +109,30 @@ int cdbg_me2(int n, bool fp32, int64_t E, const double* mom, const int8_t* hel, 
     BG_CASE(8)
     BG_CASE(9)
 #undef BG_CASE
-    default:
-      return -2;
+    default: return -2;
+  }
+}
+
+// ws: unsigned [4 + 2 E]: valid-event count and work counter, listed-event
+// count and work counter, the valid-event list, the listed-event list.
+// Stream-ordered; the counts stay on the device.
+int cdbg_me2(int n, bool fp32, int64_t E, const double* mom, const int8_t* hel, const int8_t* col,
+             unsigned* ws, double* me2, int grid, const CheckArgs* chk, int fix_grid,
+             hipStream_t stream) {
+  if (E <= 0) return 0;
+  unsigned* list = ws + 4;
+  hipLaunchKernelGGL(cdbgk::zero_u32_kernel, dim3(1), dim3(64), 0, stream, ws, 4);
+  hipLaunchKernelGGL(cdbgk::cdbg_classify_kernel, dim3((unsigned)((E + 255) / 256)), dim3(256), 0,
+                     stream, n, E, col, me2, list, ws);
+  if (hipGetLastError() != hipSuccess) return -1;
+  switch (n) {
+    case 4: return cdbgk::run_events<4>(fp32, E, mom, hel, col, ws, me2, grid, chk, fix_grid, stream);
+    case 5: return cdbgk::run_events<5>(fp32, E, mom, hel, col, ws, me2, grid, chk, fix_grid, stream);
+    case 6: return cdbgk::run_events<6>(fp32, E, mom, hel, col, ws, me2, grid, chk, fix_grid, stream);
+    case 7: return cdbgk::run_events<7>(fp32, E, mom, hel, col, ws, me2, grid, chk, fix_grid, stream);
+    case 8: return cdbgk::run_events<8>(fp32, E, mom, hel, col, ws, me2, grid, chk, fix_grid, stream);
+    case 9: return cdbgk::run_events<9>(fp32, E, mom, hel, col, ws, me2, grid, chk, fix_grid, stream);
+    default: return -2;
   }
 }
 

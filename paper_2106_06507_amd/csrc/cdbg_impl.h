@@ -45,8 +45,10 @@ namespace cdbgk {
 
 constexpr int kWave = 64;
 
-// LDS layout of one event (T = float or double), M = n - 1 gluons in subsets
-template <int N, typename T>
+// LDS layout of one event (T = float or double), M = n - 1 gluons in subsets.
+// EST: also the rounding-error bounds of every current and tensor slot and
+// the energy sum of every subset (see cdbg_one_event).
+template <int N, typename T, bool EST = false>
 struct Lay {
   static constexpr int M = N - 1;
   static constexpr int NS = 1 << M;          // subsets (mask 0 unused)
@@ -54,10 +56,11 @@ struct Lay {
   static constexpr int kT = NS * 3 * 12;     // tensors  [mask][slot][re6, im6]
   static constexpr int kP = NS * 4;          // momenta  [mask][mu]
   static constexpr int kI = NS;              // 1/P^2    [mask]
+  static constexpr int kB = EST ? NS * 7 : 0;  // bounds [mask][slot] of J and T, E [mask]
   static constexpr int kItems = NS * 3;      // target list of one size
   static constexpr int kPm = 4 * N;          // FP64 momenta of the event [gluon][mu]
   static constexpr size_t bytes() {
-    return sizeof(double) * (size_t)kPm + sizeof(T) * (size_t)(kJ + kT + kP + kI) +
+    return sizeof(double) * (size_t)kPm + sizeof(T) * (size_t)(kJ + kT + kP + kI + kB) +
            sizeof(int) * (size_t)(NS + kItems + 2 * N + 16);
   }
 };
@@ -69,6 +72,9 @@ struct Sm {
   T* Tt;
   T* P;
   T* ip2;
+  T* bJ;       // EST: bound of each current slot [mask][slot]
+  T* bT;       // EST: bound of each tensor slot [mask][slot]
+  T* en;       // EST: sum of |p^0| over the subset [mask]
   int* code;   // per mask: 0 zero; 1 | r << 2 | c << 4 unbalanced; 2 | touched << 6 balanced
   int* items;
   int* ci;     // colours i_k
@@ -76,9 +82,9 @@ struct Sm {
   int* misc;   // [3 w + t]: items of slot t found by wave w; [12]: broadcast
 };
 
-template <int N, typename T>
+template <int N, typename T, bool EST = false>
 __device__ __forceinline__ Sm<N, T> carve(unsigned char* raw) {
-  using L = Lay<N, T>;
+  using L = Lay<N, T, EST>;
   Sm<N, T> s;
   s.pm = reinterpret_cast<double*>(raw);
   T* t = reinterpret_cast<T*>(s.pm + L::kPm);
@@ -86,7 +92,10 @@ __device__ __forceinline__ Sm<N, T> carve(unsigned char* raw) {
   s.Tt = s.J + L::kJ;
   s.P = s.Tt + L::kT;
   s.ip2 = s.P + L::kP;
-  int* ip = reinterpret_cast<int*>(s.ip2 + L::kI);
+  s.bJ = s.ip2 + L::kI;
+  s.bT = s.bJ + (EST ? L::NS * 3 : 0);
+  s.en = s.bT + (EST ? L::NS * 3 : 0);
+  int* ip = reinterpret_cast<int*>(s.ip2 + L::kI + L::kB);
   s.code = ip;
   s.items = s.code + L::NS;
   s.ci = s.items + L::kItems;
@@ -339,15 +348,32 @@ __device__ __forceinline__ bool flow_valid(int n, int64_t E, const int8_t* __res
   return in_range && g.balanced() && g.connected();
 }
 
+// Check of the FP32 recursion (EST): alongside every current and tensor slot
+// the recursion carries a bound on its components computed as if every
+// product were taken in modulus: 1 for an external polarization; for a slot
+// of subset S, with E_S the sum of |p^0| over S (a bound on every momentum
+// component of a sub-subset) and the split operands' bounds bJ, bT,
+//   bT(S) = sum_splits bJ1 bJ2,
+//   bJ(S) = |1/P_S^2| sum_splits (E_S bJ1 bJ2 + bT2 bJ1 + bT1 bJ2),
+// constant factors of the vertices dropped.  An event whose amplitude
+// A = eps_n . Jhat satisfies bJ(top)^2 > tau |A|^2 cancels strongly, so FP32
+// rounding is amplified; it is appended to list for an FP64 re-evaluation.
+struct DressedCheck {
+  float tau;
+  unsigned* count;
+  unsigned* list;
+};
+
 // One valid event (colour flow closes into a circuit) on the NL lanes of this
 // block (NL = 64: one wave; NL = 256: four waves sharing the event's LDS).
-template <int N, typename T, int NL = kWave>
+template <int N, typename T, int NL = kWave, bool EST = false>
 __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
                                                const double* __restrict__ mom,
                                                const int8_t* __restrict__ hel,
                                                const int8_t* __restrict__ col, int64_t e,
-                                               double* __restrict__ me2) {
-  using L = Lay<N, T>;
+                                               double* __restrict__ me2,
+                                               DressedCheck chk = DressedCheck{}) {
+  using L = Lay<N, T, EST>;
   constexpr int M = N - 1;
   constexpr int NS = L::NS;
   constexpr int NW = NL / kWave;
@@ -357,6 +383,9 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
   // ---- event set-up -------------------------------------------------
   for (int x = lane; x < L::kJ; x += NL) sm.J[x] = T(0);
   for (int x = lane; x < L::kT; x += NL) sm.Tt[x] = T(0);
+  if constexpr (EST) {
+    for (int x = lane; x < 6 * NS; x += NL) sm.bJ[x] = T(0);  // bJ and bT are contiguous
+  }
   if (lane < N) {
     sm.ci[lane] = col[(int64_t)lane * E + e];
     sm.cj[lane] = col[((int64_t)N + lane) * E + e];
@@ -366,13 +395,16 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
   // subset codes, momenta, 1/P^2 (FP64 sums)
   for (int mask = lane + 1; mask < NS; mask += NL) {
     double q[4] = {0.0, 0.0, 0.0, 0.0};
+    double en = 0.0;
     ColourGraph g;
     for (int k = 0; k < M; ++k) {
       if (!(mask & (1 << k))) continue;
 #pragma unroll
       for (int mu = 0; mu < 4; ++mu) q[mu] += sm.pm[k * 4 + mu];
+      en += fabs(sm.pm[k * 4]);
       g.add(sm.cj[k], sm.ci[k]);
     }
+    if constexpr (EST) sm.en[mask] = (T)en;
     const int code = g.code();
     sm.code[mask] = code;
 #pragma unroll
@@ -394,6 +426,7 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
       dst[mu] = (T)er[mu];
       dst[4 + mu] = (T)ei[mu];
     }
+    if constexpr (EST) sm.bJ[(1 << lane) * 3 + slot] = T(1);
   }
   __syncthreads();
 
@@ -458,12 +491,15 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
       const int sub = lw % q;
       T gre[4] = {0, 0, 0, 0}, gim[4] = {0, 0, 0, 0};
       T tre[6] = {0, 0, 0, 0, 0, 0}, tim[6] = {0, 0, 0, 0, 0, 0};
+      T bv = T(0), bt = T(0);  // EST: bounds of this lane's share of the current and tensor
       int S = 0, t = 0;
       const bool active = grp < gpw && it < nitems;
       if (active) {
         const int item = sm.items[it];
         S = item >> 2;
         t = item & 3;
+        T enS = T(0);
+        if constexpr (EST) enS = sm.en[S];
         // a contiguous range of splits per lane: the first sub-mask is
         // deposited into S's bits, the next ones follow as (m1 - S) & S
         const int per = (nsplit + q - 1) / q;
@@ -475,6 +511,14 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
           int s1, s2;
           if (!split_slots(sm.code[m1], sm.code[m2], t, s1, s2)) continue;
           split_contrib<N, T>(sm, m1, m2, s1, s2, !top, gre, gim, tre, tim);
+          if constexpr (EST) {
+            const T j1 = sm.bJ[m1 * 3 + s1], j2 = sm.bJ[m2 * 3 + s2];
+            const T jj = j1 * j2;
+            bv += enS * jj;
+            bv += sm.bT[m2 * 3 + s2] * j1;
+            bv += sm.bT[m1 * 3 + s1] * j2;
+            bt += jj;
+          }
         }
       }
       // fixed-order tree over the q lanes of a target (all lanes take part)
@@ -498,6 +542,13 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
             }
           }
         }
+        if constexpr (EST) {
+          const T a = shfl_down_t(bv, off), b = shfl_down_t(bt, off);
+          if (take) {
+            bv += a;
+            bt += b;
+          }
+        }
       }
       if (active && sub == 0) {
         if (top) {
@@ -511,6 +562,17 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
             const double sg = mu == 0 ? 1.0 : -1.0;
             ar += sg * (er[mu] * (double)gre[mu] - ei[mu] * (double)gim[mu]);
             ai += sg * (er[mu] * (double)gim[mu] + ei[mu] * (double)gre[mu]);
+          }
+          if constexpr (EST) {
+            // helicity configurations whose tree amplitude vanishes
+            // identically are never listed; the negated test also lists an
+            // estimate that is not a number
+            int neg = 0;
+#pragma unroll
+            for (int k = 0; k < N; ++k) neg += hel[(int64_t)k * E + e] < 0 ? 1 : 0;
+            const double b2 = (double)bv * (double)bv;
+            if (neg >= 2 && neg <= N - 2 && !(b2 <= (double)chk.tau * (ar * ar + ai * ai)))
+              chk.list[atomicAdd(chk.count, 1u)] = (unsigned)e;
           }
           double scale = 1.0;
 #pragma unroll
@@ -532,6 +594,10 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
             dt[x] = tre[x];
             dt[6 + x] = tim[x];
           }
+          if constexpr (EST) {
+            sm.bJ[S * 3 + t] = bv * fabs(ip);
+            sm.bT[S * 3 + t] = bt;
+          }
         }
       }
       __syncthreads();
@@ -540,17 +606,18 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
 }
 
 // Persistent blocks of NL lanes, one valid event at a time from the
-// compacted list.
-template <int N, typename T, int NL>
+// compacted list.  EST: list ill-conditioned events into chk (FP32 pass).
+template <int N, typename T, int NL, bool EST = false>
 __global__ void __launch_bounds__(NL) cdbg_event_kernel(int64_t E, const double* __restrict__ mom,
                                                        const int8_t* __restrict__ hel,
                                                        const int8_t* __restrict__ col,
                                                        const unsigned* __restrict__ list,
                                                        const unsigned* __restrict__ count,
                                                        unsigned* __restrict__ work,
-                                                       double* __restrict__ me2) {
+                                                       double* __restrict__ me2,
+                                                       DressedCheck chk) {
   extern __shared__ __align__(16) unsigned char bg_cdbg_lds[];
-  Sm<N, T> sm = carve<N, T>(bg_cdbg_lds);
+  Sm<N, T> sm = carve<N, T, EST>(bg_cdbg_lds);
   const int lane = threadIdx.x;
   const unsigned total = *count;
   for (;;) {
@@ -559,7 +626,7 @@ __global__ void __launch_bounds__(NL) cdbg_event_kernel(int64_t E, const double*
     const unsigned idx = (unsigned)sm.misc[12];
     __syncthreads();  // every lane has read the index before the next pop
     if (idx >= total) break;
-    cdbg_one_event<N, T, NL>(sm, E, mom, hel, col, (int64_t)list[idx], me2);
+    cdbg_one_event<N, T, NL, EST>(sm, E, mom, hel, col, (int64_t)list[idx], me2, chk);
   }
 }
 

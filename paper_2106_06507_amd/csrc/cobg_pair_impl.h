@@ -72,14 +72,16 @@ struct Lds {
 // (block-private LDS); otherwise scaled, in FP64, to
 // amp[(h K + sigma) astride + acol].  P64G, LC: see Lds; with LC nothing is
 // stored, lcsum accumulates this lane's plane of |A|^2 over the orderings.
-template <int N, typename T, bool RAW, bool P64G, bool LC = false>
+template <int N, typename T, bool RAW, bool P64G, bool LC = false, bool EST = false>
 struct Ctx {
   static constexpr bool kRaw = RAW;
   static constexpr bool kP64G = P64G;
   static constexpr bool kLC = LC;
+  static constexpr bool kEst = EST;  // carry the rounding-error bounds (see State::Sb)
   static constexpr bool kDirectP2 = false;  // 1/P^2 from the per-event table
   static constexpr bool kNoDt = false;      // V4 dot products from the Dt table
   double lcsum;
+  T est_s2, est_a2;   // EST: sum over orderings of Sb(top)^2 and of |A|^2
   const double* mom;
   T* gl_slots;      // [slot][lane]
   T* tab;           // [mask][pair]
@@ -107,6 +109,15 @@ struct State {
   Cx<T> Gd[M];        // [a]: g0 times the lane's first component of J(a..d), d the
                       // column being built (the right operand of its products)
   int gl[M];          // gluon at each position (wave-uniform)
+  // Rounding-error bounds (only with Ctx::kEst).  Sb[a][b] bounds the
+  // components of J(a..b) as the recursion would if every product were taken
+  // in modulus: Sb = 1 for a gluon (unit polarization components), and for a
+  // range Sb = |1/P^2| (E(a..b) sum_k Sb_L Sb_R + sum_{j<k} Sb_X Sb_Y Sb_Z),
+  // where E(a..b) = sum of |p^0| over the range bounds every momentum
+  // component of a sub-range (the constant factors of the vertices are
+  // dropped; only ratios of such bounds are used).  Ep[b] = E(0..b).
+  T Sb[M][M];
+  T Ep[M];
 };
 
 template <int N, typename T, int A, int D, class CtxT>
@@ -131,7 +142,7 @@ __device__ __forceinline__ HR<T> range_mom(const State<N, T>& s) {
 
 template <int N, typename T, int D, int A, class CtxT>
 __device__ __forceinline__ void build_range(State<N, T>& s, const CtxT& c, int mask,
-                                            Cx<T>& top) {
+                                            Cx<T>& top, T& topb) {
   constexpr int M = N - 1;
   constexpr bool kTop = (A == 0 && D == M - 1);
   constexpr int NS = D - A;
@@ -191,8 +202,21 @@ __device__ __forceinline__ void build_range(State<N, T>& s, const CtxT& c, int m
     caxpy(acc, coefL[k - A], s.J[A][k]);
     caxpy(acc, coefR[k - A], s.J[k + 1][D]);
   }
+  T sb = T(0);
+  if constexpr (CtxT::kEst) {
+    T v3 = T(0), v4 = T(0);
+#pragma unroll
+    for (int k = A; k < D; ++k) v3 += s.Sb[A][k] * s.Sb[k + 1][D];
+#pragma unroll
+    for (int j = A; j < D; ++j)
+#pragma unroll
+      for (int k = j + 1; k < D; ++k) v4 += s.Sb[A][j] * s.Sb[j + 1][k] * s.Sb[k + 1][D];
+    const T er = A == 0 ? s.Ep[D] : s.Ep[D] - s.Ep[A - 1];
+    sb = er * v3 + v4;
+  }
   if constexpr (kTop) {
     top = hdot(c.epsN, acc, c.g0);
+    topb = sb;
   } else {
     T ip2;
     if constexpr (CtxT::kDirectP2) {
@@ -211,17 +235,18 @@ __device__ __forceinline__ void build_range(State<N, T>& s, const CtxT& c, int m
       s.J[A][D].re[m] = acc.re[m] * ip2;
       s.J[A][D].im[m] = acc.im[m] * ip2;
     }
+    if constexpr (CtxT::kEst) s.Sb[A][D] = sb * fabs(ip2);
     set_gd<N, T, A, D>(s, c);
   }
 }
 
 template <int N, typename T, int D, int A, class CtxT>
 __device__ __forceinline__ void build_column(State<N, T>& s, const CtxT& c, int mask,
-                                             Cx<T>& top) {
+                                             Cx<T>& top, T& topb) {
   if constexpr (A >= 0) {
     mask |= 1 << s.gl[A];
-    build_range<N, T, D, A>(s, c, mask, top);
-    build_column<N, T, D, A - 1>(s, c, mask, top);
+    build_range<N, T, D, A>(s, c, mask, top, topb);
+    build_column<N, T, D, A - 1>(s, c, mask, top, topb);
   }
 }
 
@@ -244,9 +269,19 @@ __device__ __forceinline__ void level(State<N, T>& s, CtxT& c, int used) {
       else
         pg = c.p64[(2 * (g - 1) + m) * Lds<N>::kLanes + c.lane];
       s.P0[D].v[m] = s.P0[D - 1].v[m] + pg;
+      if constexpr (CtxT::kEst) {
+        if (m == 0) {
+          // |p^0| of the gluon: the h = 0 lane holds it, the h = 1 lane
+          // takes it from its partner
+          const double px = xswap(pg);
+          s.Ep[D] = s.Ep[D - 1] + (T)fabs(c.h == 0 ? pg : px);
+        }
+      }
     }
+    if constexpr (CtxT::kEst) s.Sb[D][D] = T(1);
     set_gd<N, T, D, D>(s, c);
     Cx<T> top;
+    T topb = T(0);
     if constexpr (CtxT::kLC && D == M - 1) {
       // the one gluon not yet placed closes the ordering
       const int all = ((1 << (NG + 1)) - 1) & ~1;
@@ -258,9 +293,13 @@ __device__ __forceinline__ void level(State<N, T>& s, CtxT& c, int used) {
         c.epsN.im[m] = c.gl_slots[(rb + 2 + m) * Lds<N>::kLanes + c.lane];
       }
     }
-    build_column<N, T, D, D - 1>(s, c, 1 << g, top);
+    build_column<N, T, D, D - 1>(s, c, 1 << g, top, topb);
     if constexpr (D == M - 1) {
       constexpr int64_t K = Factorial<N - 2>::value;
+      if constexpr (CtxT::kEst) {
+        c.est_s2 += topb * topb;
+        c.est_a2 += top.re * top.re + top.im * top.im;
+      }
       if constexpr (CtxT::kLC) {
         const double v = (double)(c.h == 0 ? top.re : top.im);
         c.lcsum += v * v;
@@ -285,20 +324,28 @@ __device__ __forceinline__ void level(State<N, T>& s, CtxT& c, int used) {
 // block's waves must all call it (it synchronises the block); lds is this
 // wave's region of Lds<N>::bytes<T>().  RAW: the
 // unscaled amplitudes go to amp_raw (see Ctx), amp is unused.
-template <int N, typename T, bool RAW = false, bool P64G = false, bool LC = false>
+//
+// EST: also accumulate, over the orderings, est[0] += Sb(top)^2 and
+// est[1] += |A|^2 (State::Sb); est[0] / est[1] is then the square of a
+// bound on the amplitudes' rounding error relative to their size, the
+// conditioning of this event's evaluation (identical in both lanes).
+template <int N, typename T, bool RAW = false, bool P64G = false, bool LC = false,
+          bool EST = false>
 __device__ __forceinline__ double cobg_pair_body(unsigned char* lds, int64_t E,
                                                const double* __restrict__ mom,
                                                const int8_t* __restrict__ hel, int hconf,
                                                int64_t e, bool live, double* __restrict__ amp,
                                                int64_t astride, int64_t acol,
-                                               T* amp_raw = nullptr) {
+                                               T* amp_raw = nullptr, T* est = nullptr) {
   constexpr int M = N - 1;
   const int lane = threadIdx.x & 63;  // lane within this wave (the wave owns lds)
   const int pair = lane >> 1;
   const int h = lane & 1;
   using L = Lds<N, LC>;
-  Ctx<N, T, RAW, P64G, LC> c;
+  Ctx<N, T, RAW, P64G, LC, EST> c;
   c.lcsum = 0.0;
+  c.est_s2 = T(0);
+  c.est_a2 = T(0);
   c.mom = mom;
   c.gl_slots = reinterpret_cast<T*>(lds);
   c.tab = c.gl_slots + (size_t)L::kGluonSlots * L::kLanes;
@@ -374,7 +421,15 @@ __device__ __forceinline__ double cobg_pair_body(unsigned char* lds, int64_t E,
   }
   __syncthreads();
   s.gl[0] = 0;
+  if constexpr (EST) {
+    s.Sb[0][0] = T(1);
+    s.Ep[0] = (T)fabs(p[0][0]);
+  }
   level<N, T, 1>(s, c, 1);
+  if constexpr (EST) {
+    est[0] += c.est_s2;
+    est[1] += c.est_a2;
+  }
   return c.lcsum;
 }
 

@@ -324,7 +324,7 @@ __global__ void __launch_bounds__(kThreads) enumerate_kernel(int64_t E, const in
 // in registers).
 template <int N, typename T, bool NODT>
 struct Ctx {
-  static constexpr bool kRaw = false, kP64G = false, kLC = false;
+  static constexpr bool kRaw = false, kP64G = false, kLC = false, kEst = false;
   static constexpr bool kDirectP2 = true;
   static constexpr bool kNoDt = NODT;
   T* gl_slots;   // [6 (g-1) + x][lane]
@@ -361,7 +361,8 @@ __device__ __forceinline__ void path(pairk::State<N, T>& s, C& c, uint32_t code,
       c.epsN.im[m] = c.gl_slots[(lb + 2 + m) * 64 + c.lane];
     }
   }
-  pairk::build_column<N, T, D, D - 1>(s, c, 0, top);
+  T topb;
+  pairk::build_column<N, T, D, D - 1>(s, c, 0, top, topb);
   if constexpr (D < M - 1) path<N, T, D + 1>(s, c, code, top);
 }
 

@@ -84,17 +84,46 @@ __device__ __forceinline__ double lower_quadform(const double* __restrict__ Cb, 
   return q;
 }
 
+// Re-evaluation of ill-conditioned events.  The FP32 pass (CHK) bounds,
+// per event, the rounding error of its amplitudes relative to their size
+// (pairk::State::Sb): the square of that bound is est = sum_sigma Sb_sigma^2 /
+// sum_sigma |A_sigma|^2.  Events with est > tau (helicity configurations
+// whose tree amplitude vanishes identically excepted: their |M|^2 is rounding
+// noise at any precision) are appended to a list; a second pass in FP64 (IDX)
+// evaluates the listed events again and overwrites their |M|^2.
+struct TileCheck {
+  float tau;          // threshold on est
+  unsigned* count;    // number of listed events (device; zeroed before the FP32 pass)
+  unsigned* list;     // listed event indices
+};
+
+// Appends the events of the lanes with f set to chk.list (one atomic per wave).
+__device__ __forceinline__ void flag_events(bool f, unsigned e, const TileCheck& chk) {
+  const unsigned long long m = __ballot(f);
+  if (m == 0ull) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)m) - 1;
+  unsigned base = 0u;
+  if (lane == leader) base = atomicAdd(chk.count, (unsigned)__popcll(m));
+  base = (unsigned)__shfl((int)base, leader);
+  if (f) chk.list[base + (unsigned)__popcll(m & ((1ull << lane) - 1ull))] = e;
+}
+
 // Colour-summed |M|^2 of events [first, first + count) (0 <= count <= 32,
 // event `first` must exist) of an [n][4][E] input, on one wave.  HSUM: sum
 // over all 2^n helicity configurations (hel is ignored); otherwise one
 // configuration per event from hel.  lds is the wave's Cobg<N>::lds_bytes<T>();
-// blk its scratch slice (n = 7 only).
-template <int N, typename T, bool HSUM, bool P64G = false>
+// blk its scratch slice (n = 7 only).  CHK: flag ill-conditioned events into
+// chk (see TileCheck).  IDX: the events are idx[first .. first + count - 1]
+// instead (idx[first] must exist).
+template <int N, typename T, bool HSUM, bool P64G = false, bool CHK = false, bool IDX = false>
 __device__ __forceinline__ void cobg_tile(unsigned char* lds, int64_t E,
                                           const double* __restrict__ mom,
                                           const int8_t* __restrict__ hel,
                                           const double* __restrict__ Cb, double* blk,
-                                          double* __restrict__ me2, int64_t first, int count) {
+                                          double* __restrict__ me2, int64_t first, int count,
+                                          TileCheck chk = TileCheck{},
+                                          const unsigned* __restrict__ idx = nullptr) {
   constexpr int K = Cobg<N>::K;
   constexpr bool kL = Cobg<N>::kLdsAmp;
   T* amp_lds = reinterpret_cast<T*>(lds + pairk::Lds<N>::template bytes<T, P64G>());
@@ -104,13 +133,17 @@ __device__ __forceinline__ void cobg_tile(unsigned char* lds, int64_t E,
   // count = 0: a wave without events in this round still takes part in the
   // block's barriers, evaluating event `first` without storing it
   const bool live = pair < count;
-  int64_t e = first + (live ? pair : (count > 0 ? count - 1 : 0));
+  const int64_t slot = first + (live ? pair : (count > 0 ? count - 1 : 0));
+  int64_t e = IDX ? (int64_t)idx[slot] : slot;
+  T est[2] = {T(0), T(0)};
   auto one = [&](const int8_t* hp, int hc) -> double {
     if constexpr (kL) {
-      pairk::cobg_pair_body<N, T, true, P64G>(lds, E, mom, hp, hc, e, true, nullptr, 0, 0, amp_lds);
+      pairk::cobg_pair_body<N, T, true, P64G, false, CHK>(lds, E, mom, hp, hc, e, true, nullptr,
+                                                          0, 0, amp_lds, est);
       return lower_quadform<K>(Cb, amp_lds + (size_t)h * K * kTileEvents + pair, kTileEvents);
     } else {
-      pairk::cobg_pair_body<N, T, false, P64G>(lds, E, mom, hp, hc, e, true, blk, kTileEvents, pair);
+      pairk::cobg_pair_body<N, T, false, P64G, false, CHK>(lds, E, mom, hp, hc, e, true, blk,
+                                                           kTileEvents, pair, nullptr, est);
       return lower_quadform<K>(Cb, blk + (size_t)h * K * kTileEvents + pair, kTileEvents);
     }
   };
@@ -135,6 +168,21 @@ __device__ __forceinline__ void cobg_tile(unsigned char* lds, int64_t E,
   }
   const double tot = pairk::pair_sum(q);
   if (live && h == 0) me2[e] = tot;
+  if constexpr (CHK) {
+    bool f = false;
+    if (live && h == 0) {
+      bool vanishing = false;
+      if constexpr (!HSUM) {
+        int neg = 0;
+#pragma unroll
+        for (int i = 0; i < N; ++i) neg += hel[(int64_t)i * E + e] < 0 ? 1 : 0;
+        vanishing = neg < 2 || neg > N - 2;
+      }
+      // the negated test also lists events whose estimate is not a number
+      f = !vanishing && !(est[0] <= chk.tau * est[1]);
+    }
+    flag_events(f, (unsigned)e, chk);
+  }
 }
 
 // Leading-colour |M|^2 (Section 3.1): N^(n-2) (N^2 - 1) sum over all (n-1)!
@@ -167,19 +215,25 @@ __device__ __forceinline__ void lc_tile(unsigned char* lds, int64_t E,
 // Colour-dressed |A|^2 of events [first, first + count), count <= NL, on
 // the NL lanes of the block: one lane classifies each event (invalid flows
 // get exactly 0), then the valid ones are evaluated in order by all lanes.
-// vmask: NL/64 words of LDS for the validity masks.
-template <int N, typename T, int NL>
+// vmask: NL/64 words of LDS for the validity masks.  PASS (BatchPass):
+// kBatchCheck lists ill-conditioned events into chk; kBatchFix takes the
+// events idx[first .. first + count - 1] instead.
+template <int N, typename T, int NL, int PASS = kBatchPlain>
 __device__ __forceinline__ void cdbg_chunk(unsigned char* lds, unsigned long long* vmask, int64_t E,
                                            const double* __restrict__ mom,
                                            const int8_t* __restrict__ hel,
                                            const int8_t* __restrict__ col,
-                                           double* __restrict__ me2, int64_t first, int count) {
-  const cdbgk::Sm<N, T> sm = cdbgk::carve<N, T>(lds);
+                                           double* __restrict__ me2, int64_t first, int count,
+                                           const unsigned* __restrict__ idx = nullptr,
+                                           cdbgk::DressedCheck chk = cdbgk::DressedCheck{}) {
+  constexpr bool kEst = PASS == kBatchCheck;
+  const cdbgk::Sm<N, T> sm = cdbgk::carve<N, T, kEst>(lds);
   const int t = threadIdx.x;
   bool valid = false;
   if (t < count) {
-    valid = cdbgk::flow_valid(N, E, col, first + t);
-    if (!valid) me2[first + t] = 0.0;
+    const int64_t ev = PASS == kBatchFix ? (int64_t)idx[first + t] : first + t;
+    valid = cdbgk::flow_valid(N, E, col, ev);
+    if (!valid) me2[ev] = 0.0;
   }
   const unsigned long long m = __ballot(valid);
   if ((t & 63) == 0) vmask[t >> 6] = m;
@@ -189,7 +243,8 @@ __device__ __forceinline__ void cdbg_chunk(unsigned char* lds, unsigned long lon
     while (mm) {
       const int l = __builtin_ctzll(mm);
       mm &= mm - 1;
-      cdbgk::cdbg_one_event<N, T, NL>(sm, E, mom, hel, col, first + 64 * w + l, me2);
+      const int64_t ev = PASS == kBatchFix ? (int64_t)idx[first + 64 * w + l] : first + 64 * w + l;
+      cdbgk::cdbg_one_event<N, T, NL, kEst>(sm, E, mom, hel, col, ev, me2, chk);
     }
   }
   __syncthreads();  // vmask is rewritten by the next chunk

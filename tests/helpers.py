@@ -57,3 +57,28 @@ def helicity_scale(mom):
     |M|^2 is suppressed by many orders of magnitude."""
     from oracle import me2 as ome2
     return ome2.me2_cobg(mom, None) / 2 ** mom.shape[0]
+
+
+U64 = 2.0 ** -53
+
+
+def fp64_allowance(n, ref, mag):
+    """Per-event bar of an FP64 evaluation against the extended reference:
+    max(1e-12 |ref|, 12 (n - 2) u m), m the magnitude of the evaluation (every
+    product and sum taken in modulus, oracle.conditioning).  12 (n - 2) is
+    the number of roundings along the deepest path of the recursion (at most
+    n - 2 levels, each a four-term dot product, a scaling and an accumulation
+    over at most six splits); the FP64 oracle itself is held to the same
+    bound against the long-double evaluation on the CPU."""
+    return np.maximum(1e-12 * np.abs(ref), 12 * (np.asarray(n) - 2) * U64 * mag)
+
+
+def reference_cobg(mom, hel):
+    """Colour-summed |M|^2 from the oracle in long double (float64 result)
+    and its FP64 magnitude m (see fp64_allowance)."""
+    from oracle import me2 as ome2
+    from oracle.conditioning import me2_cobg_magnitude
+    from oracle.numeric import extended
+    ref = ome2.me2_cobg(extended(mom), hel).astype(np.float64)
+    _, mag = me2_cobg_magnitude(mom, hel)
+    return ref, mag

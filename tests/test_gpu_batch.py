@@ -3,10 +3,10 @@
 The batch kernel evaluates every event with the same device routines as the
 single-request entry point (fused colour-ordered tiles for n <= 7,
 colour-dressed chunks for n >= 8).  Colour-ordered segments in FP64 equal
-bg_me2 on each segment alone bit for bit; otherwise the two agree to rounding
-(see _same).  Within the batch kernel the result does not depend on tile or
-grid shape (bit for bit).  A few events of each segment are also checked
-against the oracle directly.
+bg_me2 on each segment alone bit for bit; otherwise the two agree within the
+sum of their error bars (see _same).  Within the batch kernel the result does
+not depend on tile or grid shape (bit for bit).  A few events of each segment
+are also checked against the oracle directly.
 """
 import numpy as np
 import pytest
@@ -14,7 +14,9 @@ import pytest
 from bg_inputs import make_events, mixed_workload
 from oracle import cdbg as ocdbg
 from oracle import me2 as ome2
-from tests.helpers import nonvanishing
+from oracle.conditioning import flow_amplitude_magnitude
+from oracle.numeric import extended
+from tests.helpers import U64, fp64_allowance, nonvanishing, reference_cobg
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -49,35 +51,54 @@ def _single(api, segs, precision):
     return [api.me2(s["mom"], s["hel"], s["col"], mode="auto", precision=precision) for s in segs]
 
 
+FP32_MAX = 3e-4
+
+
 def _same(segs, got, ref, precision, label=""):
     """Colour-ordered segments in FP64: bit-identical.  Otherwise the two
-    kernels may round differently (FP32: multiply-add contraction; colour-
-    dressed: the batch evaluates an event on 256 lanes, the single request on
-    128 or 256, which splits the vertex sums differently): per-event relative
-    difference median <= 1e-13 / max <= 1e-9 (FP64) or median <= 1e-6 /
-    max <= 1e-2 (FP32, the conditioning tail of the FP32 parity tests) on
-    events with a non-vanishing tree amplitude; for the colour-dressed segments
-    the zeros of invalid colour flows coincide."""
+    kernels may round differently (FP32: multiply-add contraction, and an
+    event near the check's threshold may be re-evaluated in FP64 by one path
+    only; colour-dressed: the batch evaluates an event on 256 lanes, the
+    single request on 128 or 256, which splits the vertex sums differently).
+    Both sides meet their per-event bars, so they differ by at most twice a
+    bar: FP32 2 FP32_MAX = 6e-4 (median 1e-6); FP64 colour-dressed 2e-12
+    relative, or for events above that twice the running error bound
+    12 (n - 2) u m of the oracle's magnitude (median 1e-13).  For colour-
+    dressed segments the zeros of invalid colour flows coincide."""
     for s, g, r in zip(segs, got, ref):
         g, r = g.cpu().numpy(), r.cpu().numpy()
-        if precision == "fp64" and s["n"] <= 7:
-            assert np.array_equal(g, r), f"{label} n={s['n']}"
+        n = s["n"]
+        if precision == "fp64" and n <= 7:
+            assert np.array_equal(g, r), f"{label} n={n}"
             continue
         keep = nonvanishing(s["hel"].cpu().numpy())
-        if s["n"] >= 8:
+        if n >= 8:
             # flows whose amplitude cancels to rounding may give an exact 0 on
             # one side only
             typical = np.median(np.abs(r[r != 0.0])) if (r != 0.0).any() else 0.0
             noise = (np.abs(r) < 1e-8 * typical) & (np.abs(g) < 1e-8 * typical)
-            assert np.array_equal((g == 0.0) | noise, (r == 0.0) | noise), f"{label} n={s['n']}"
+            assert np.array_equal((g == 0.0) | noise, (r == 0.0) | noise), f"{label} n={n}"
             keep &= (np.abs(r) >= 1e-8 * typical) & (r != 0.0)
         if not keep.any():
             continue
-        rel = np.abs(g - r)[keep] / np.abs(r[keep])
-        _say(f"  {label} n={s['n']}: events differing {(g != r).sum()} of {g.size}, "
+        d = np.abs(g - r)
+        rel = d[keep] / np.abs(r[keep])
+        _say(f"  {label} n={n}: events differing {(g != r).sum()} of {g.size}, "
              f"rel diff median {np.median(rel):.1e} max {rel.max():.1e}")
-        med, mx = (1e-13, 1e-9) if precision == "fp64" else (1e-6, 1e-2)
-        assert np.median(rel) <= med and rel.max() <= mx, f"{label} n={s['n']}"
+        if precision == "fp32":
+            assert np.median(rel) <= 1e-6 and rel.max() <= 2 * FP32_MAX, f"{label} n={n}"
+            continue
+        assert np.median(rel) <= 1e-13, f"{label} n={n}"
+        over = np.nonzero(keep & (d > 2e-12 * np.abs(r)))[0][:40]
+        if over.size:
+            mom = s["mom"].cpu().numpy()[:, :, over]
+            hel = s["hel"].cpu().numpy()[:, over]
+            col = s["col"].cpu().numpy()[:, :, over]
+            _, mA = flow_amplitude_magnitude(mom, hel, col)
+            allow = 2 * 12 * (n - 2) * U64 * 2.0 * np.sqrt(np.abs(r[over])) * mA
+            _say(f"  {over.size} events above 2e-12: max |d| / allowance "
+                 f"{np.max(d[over] / allow):.2e}")
+            assert np.all(d[over] <= allow), f"{label} n={n}"
 
 
 def _small_mix():
@@ -97,6 +118,8 @@ def test_batch_equals_single_requests(api, precision):
 
 
 def test_batch_spot_checks_against_oracle(api):
+    """FP64 batch against the long-double oracle, per event: within
+    max(1e-12 |ref|, 12 (n - 2) u m) (helpers.fp64_allowance)."""
     ev = _small_mix()
     segs = _segments(ev)
     got = [g.cpu().numpy() for g in api.me2_batch(segs, "fp64")]
@@ -105,16 +128,18 @@ def test_batch_spot_checks_against_oracle(api):
         e = ev[n]
         if n <= 7:
             idx = np.nonzero(nonvanishing(e["hel"]))[0][:4]
-            ref = ome2.me2_cobg(e["mom"][:, :, idx], e["hel"][:, idx])
+            ref, mag = reference_cobg(e["mom"][:, :, idx], e["hel"][:, idx])
         else:
             valid = ocdbg.is_valid_flow(e["col"])
             assert np.all(g[~valid] == 0.0)
             idx = np.nonzero(valid & nonvanishing(e["hel"]))[0][:3]
-            ref = np.abs(ocdbg.flow_amplitude(e["mom"][:, :, idx], e["hel"][:, idx],
-                                              e["col"][:, :, idx])) ** 2
-        rel = np.abs(g[idx] - ref) / np.abs(ref)
-        _say(f"  n={n} oracle spot check max rel {rel.max():.2e}")
-        assert rel.max() < 1e-9
+            m, h, c = e["mom"][:, :, idx], e["hel"][:, idx], e["col"][:, :, idx]
+            ref = (np.abs(ocdbg.flow_amplitude(extended(m), h, c)) ** 2).astype(np.float64)
+            _, mA = flow_amplitude_magnitude(m, h, c)
+            mag = 2.0 * np.sqrt(ref) * mA
+        d = np.abs(g[idx] - ref)
+        _say(f"  n={n} oracle spot check max rel {np.max(d / np.abs(ref)):.2e}")
+        assert np.all(d <= fp64_allowance(n, ref, mag))
 
 
 @pytest.mark.parametrize("cfg", [
@@ -161,8 +186,9 @@ def test_batch_rejects_bad_requests(api):
 
 
 def test_batch_fp32_against_oracle(api):
-    """FP32 recursion in the batch kernel against the FP64 oracle on a few
-    events per segment (per-event relative error, non-vanishing helicities)."""
+    """FP32 recursion in the batch kernel (with the FP64 re-evaluation of the
+    listed events) against the FP64 oracle on a few events per segment
+    (per-event relative error, non-vanishing helicities): within FP32_MAX."""
     ev = _small_mix()
     segs = _segments(ev)
     got = [g.cpu().numpy() for g in api.me2_batch(segs, "fp32")]
@@ -178,7 +204,7 @@ def test_batch_fp32_against_oracle(api):
                                               e["col"][:, :, idx])) ** 2
         rel = np.abs(g[idx] - ref) / np.abs(ref)
         _say(f"  n={n} fp32 oracle spot check median {np.median(rel):.1e} max {rel.max():.1e}")
-        assert np.median(rel) < 1e-5 and rel.max() < 1e-2
+        assert np.median(rel) < 1e-6 and rel.max() <= FP32_MAX
 
 
 def test_batch_empty_and_tiny_segments(api):

@@ -1,27 +1,34 @@
-"""GPU parity of the colour-dressed path against the FP64 oracle.
+"""GPU parity of the colour-dressed path against the oracle.
 
 For one colour-flow assignment and helicity configuration per event the GPU
 returns |A|^2 of eq. color_decomposition_colorflow computed with the
 dressed recursion; the oracle evaluates the same amplitude with its own
-dressed recursion (itself pinned to the brute-force sum over orderings).
-Assignments whose edges j_k -> i_k do not close into one circuit must give
-exactly 0.  Error statistic: per-event relative error on events whose
-helicity configuration does not vanish identically; FP64 bar 1e-12 at the
-median and 1e-9 at the maximum, FP32 bar 1e-5 at the median and 1e-2 at the
-maximum.  The maxima are set by the problem's conditioning (the same tail as
-the colour-ordered path: suppressed configurations amplify input rounding).
+dressed recursion (itself pinned to the brute-force sum over orderings), in
+long double for the reference.  Assignments whose edges j_k -> i_k do not
+close into one circuit must give exactly 0.  Per event, on events whose
+helicity configuration does not vanish identically:
+  * FP64: |got - ref| <= max(1e-12 |ref|, 12 (n - 2) u m) with m = 2 |A| m_A
+    and m_A the magnitude of the flow amplitude written as the sum of the
+    colour-ordered amplitudes whose chain closes (oracle.conditioning; the
+    same running error bound as the colour-ordered path), and the median
+    relative error below 1e-13;
+  * FP32 (checked, FP64 re-evaluation of listed events): every event within
+    FP32_MAX = 3e-4 and the median below 1e-6; p99 <= 1e-5 is asserted on
+    2^18-event samples in test_gpu_fp32_check.
 """
 import numpy as np
 import pytest
 
 from bg_inputs import make_events, workload
 from oracle import cdbg as ocdbg
-from tests.helpers import valid_colours, nonvanishing, mhv_helicities
+from oracle.conditioning import flow_amplitude_magnitude
+from oracle.numeric import extended
+from tests.helpers import U64, mhv_helicities, nonvanishing, valid_colours
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-BARS = {"fp64": (1e-12, 1e-9), "fp32": (1e-5, 1e-2)}
+FP32_MAX = 3e-4
 
 
 @pytest.fixture(scope="module")
@@ -40,32 +47,49 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def _check(got, ref, hel, precision, label):
+def _reference(mom, hel, col):
+    """|A|^2 from the oracle's dressed recursion in long double (float64)."""
+    return (np.abs(ocdbg.flow_amplitude(extended(mom), hel, col)) ** 2).astype(np.float64)
+
+
+def _check(got, ref, mom, hel, col, precision, label):
+    """Per-event bars of the module docstring; ref is the long-double |A|^2."""
+    n = mom.shape[0]
     # exclude identically vanishing helicity configurations and flows whose
     # amplitude cancels exactly (e.g. all gluons of one colour: U(1) decoupling);
     # both sides return rounding noise there
     typical = np.median(np.abs(ref[nonvanishing(hel)])) if nonvanishing(hel).any() else 0.0
     nz = nonvanishing(hel) & (np.abs(ref) > 1e-8 * typical)
     assert np.all(np.abs(got[~nz]) < 1e-6 * typical + 1e-300)
-    rel = np.abs(got - ref)[nz] / np.abs(ref[nz])
+    d = np.abs(got - ref)
+    rel = d[nz] / np.abs(ref[nz])
     _say(f"  {label} {precision}: events {nz.sum()} rel err median {np.median(rel):.2e} "
          f"p99 {np.percentile(rel, 99):.2e} max {rel.max():.2e}")
-    med, mx = BARS[precision]
-    assert np.median(rel) < med
-    assert rel.max() < mx
+    if precision == "fp64":
+        assert np.median(rel) < 1e-13
+        # the conditioning term only for the events above 1e-12 (it is costly)
+        over = np.nonzero(nz & (d > 1e-12 * np.abs(ref)))[0]
+        if over.size:
+            _, mA = flow_amplitude_magnitude(mom[:, :, over], hel[:, over], col[:, :, over])
+            allow = 12 * (n - 2) * U64 * 2.0 * np.sqrt(ref[over]) * mA
+            _say(f"  {over.size} events above 1e-12: max |d| / allowance {np.max(d[over] / allow):.2e}")
+            assert np.all(d[over] <= allow)
+    else:
+        assert np.median(rel) < 1e-6
+        assert rel.max() <= FP32_MAX
 
 
-@pytest.mark.parametrize("n", [4, 5, 6, 7, 8])
+@pytest.mark.parametrize("n", [4, 5, 6, 7, 8, 9])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_valid_flows_match_oracle(api, n, precision):
-    E = {4: 130, 5: 130, 6: 100, 7: 40, 8: 12}[n]
+    E = {4: 130, 5: 130, 6: 100, 7: 40, 8: 12, 9: 8}[n]
     ev = make_events(n, E, seed=5000 + n, cuts=True)
     col = valid_colours(n, E, np.random.default_rng(50 + n))
     _say(f"bg_me2 cdbg {precision} n={n} E={E}")
     got = api.me2(_dev(ev["mom"]), _dev(ev["hel"]), _dev(col), mode="cdbg",
                   precision=precision).cpu().numpy()
-    ref = np.abs(ocdbg.flow_amplitude(ev["mom"], ev["hel"], col)) ** 2
-    _check(got, ref, ev["hel"], precision, f"n={n}")
+    ref = _reference(ev["mom"], ev["hel"], col)
+    _check(got, ref, ev["mom"], ev["hel"], col, precision, f"n={n}")
 
 
 def test_sampled_flows_zero_when_invalid(api):
@@ -77,8 +101,8 @@ def test_sampled_flows_zero_when_invalid(api):
     got = api.me2(_dev(ev["mom"]), _dev(ev["hel"]), _dev(ev["col"]), mode="cdbg").cpu().numpy()
     assert np.all(got[~valid] == 0.0)
     idx = np.nonzero(valid)[0]
-    ref = np.abs(ocdbg.flow_amplitude(ev["mom"][:, :, idx], ev["hel"][:, idx], ev["col"][:, :, idx])) ** 2
-    _check(got[idx], ref, ev["hel"][:, idx], "fp64", "sampled")
+    m, h, c = ev["mom"][:, :, idx], ev["hel"][:, idx], ev["col"][:, :, idx]
+    _check(got[idx], _reference(m, h, c), m, h, c, "fp64", "sampled")
 
 
 def test_auto_mode_and_determinism(api):
@@ -118,9 +142,10 @@ def test_full_size_gg_6g_sampled(api):
     assert (g64[smp][valid] != 0.0).mean() > 0.99
     nonzero = g64 != 0.0
     idx = np.sort(rng.choice(np.nonzero(nonzero)[0], 10, replace=False))
-    ref = np.abs(ocdbg.flow_amplitude(mom[:, :, idx], hel[:, idx], col[:, :, idx])) ** 2
-    _check(g64[idx], ref, hel[:, idx], "fp64", "full")
-    _check(g32[idx], ref, hel[:, idx], "fp32", "full")
+    m, h, c = mom[:, :, idx], hel[:, idx], col[:, :, idx]
+    ref = _reference(m, h, c)
+    _check(g64[idx], ref, m, h, c, "fp64", "full")
+    _check(g32[idx], ref, m, h, c, "fp32", "full")
 
 
 @pytest.mark.parametrize("n", [4, 6, 8, 9])
@@ -129,7 +154,7 @@ def test_single_event(api, n):
     ev = make_events(n, 1, seed=5300 + n, cuts=True)
     col = valid_colours(n, 1, np.random.default_rng(53 + n))
     hel = mhv_helicities(n, 1, np.random.default_rng(54 + n))
-    ref = np.abs(ocdbg.flow_amplitude(ev["mom"], hel, col)) ** 2
-    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-3)):
+    ref = _reference(ev["mom"], hel, col)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
         got = api.me2(_dev(ev["mom"]), _dev(hel), _dev(col), mode="cdbg", precision=prec).cpu().numpy()
         assert abs(got[0] - ref[0]) <= tol * abs(ref[0]), (prec, got[0], ref[0])

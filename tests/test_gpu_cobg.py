@@ -1,15 +1,15 @@
-"""GPU parity of the colour-ordered path against the FP64 oracle.
+"""GPU parity of the colour-ordered path against the oracle.
 
-Error statistics.  For one sampled helicity configuration per event two
-relative errors are used:
-  * per-event:      |got - ref| / |ref|;
-  * scale-relative: |got - ref| / S_e, S_e = helicity-averaged |M|^2 of the
-    event (the scale of the sampled estimator 2^n |M|^2_h).
-Configurations whose |M|^2 is suppressed by 1e-8..1e-11 against S_e amplify
-input rounding (the problem's conditioning, ~1e3 at the 99th percentile for
-n = 6), so the per-event error of any FP32 evaluation has a long tail.
-Bars: FP64 path scale-relative max <= 1e-12 and per-event median <= 1e-13;
-FP32 path scale-relative max <= 1e-5 and per-event median <= 1e-5.
+Reference: the oracle evaluated in long double (64-bit significand), whose
+agreement with a 40-digit evaluation is pinned on the CPU.  Per event:
+  * FP64 path: |got - ref| <= max(1e-12 |ref|, 12 (n - 2) u m) for every
+    event (helpers.fp64_allowance: m is the event's magnitude, so the second
+    term is the running error bound of any FP64 evaluation order), and the
+    median relative error below 1e-14;
+  * FP32 path (FP32 recursion, FP64 re-evaluation of the events its error
+    bound lists): every event within FP32_MAX = 3e-4 and the median below
+    1e-6 here; the p99 <= 1e-5 bar is asserted on 2^18-event samples in
+    test_gpu_fp32_check.
 Configurations that vanish identically at tree level (all helicities equal
 but at most one) are checked against rounding level instead.
 """
@@ -19,13 +19,14 @@ import pytest
 from bg_inputs import make_events, workload
 from oracle import cobg as ocobg
 from oracle import me2 as ome2
-from tests.helpers import nonvanishing, helicity_scale, mhv_helicities
+from tests.helpers import (fp64_allowance, mhv_helicities, nonvanishing,
+                           reference_cobg)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 FP64_ME2_RTOL = 1e-12
-FP32_ME2_RTOL = 1e-5
+FP32_MAX = 3e-4
 
 
 @pytest.fixture(scope="module")
@@ -66,17 +67,26 @@ def test_amplitudes_fp64_match_oracle(api, n):
     assert np.max(np.abs(got[:, ~nz]), initial=0.0) < 1e-10 * typical
 
 
-def _check_sampled(got, ref, scale, nz, precision):
-    rel = (np.abs(got - ref) / np.abs(ref))[nz]
-    srel = (np.abs(got - ref) / scale)[nz]
+def _check_sampled(got, mom, hel, precision):
+    """Per-event bars against the long-double reference (module docstring)."""
+    n = mom.shape[0]
+    ref, mag = reference_cobg(mom, hel)
+    nz = nonvanishing(hel)
+    d = np.abs(got - ref)
+    rel = (d / np.abs(ref))[nz]
     _say(f"  per-event rel err median {np.median(rel):.2e} p99 {np.percentile(rel, 99):.2e} "
-         f"max {rel.max():.2e}; scale-relative max {srel.max():.2e}")
+         f"max {rel.max():.2e}")
     if precision == "fp64":
-        assert srel.max() < FP64_ME2_RTOL
-        assert np.median(rel) < 1e-13
+        allow = fp64_allowance(n, ref, mag)
+        worst = np.max((d / allow)[nz])
+        _say(f"  max |d| / allowance {worst:.2f}; events needing the conditioning term: "
+             f"{np.mean((d > 1e-12 * np.abs(ref))[nz]):.1%}")
+        assert worst <= 1.0
+        assert np.median(rel) < 1e-14
     else:
-        assert srel.max() < FP32_ME2_RTOL
-        assert np.median(rel) < FP32_ME2_RTOL
+        assert rel.max() <= FP32_MAX
+        assert np.median(rel) < 1e-6
+    return ref
 
 
 @pytest.mark.parametrize("n", [4, 5, 6, 7])
@@ -86,11 +96,10 @@ def test_me2_match_oracle(api, n, precision):
     mom, hel = _events(n, E, 3100 + n)
     _say(f"bg_me2 {precision} n={n} E={E}")
     got = api.me2(_dev(mom), _dev(hel), precision=precision).cpu().numpy()
-    ref = ome2.me2_cobg(mom, hel)
+    ref = _check_sampled(got, mom, hel, precision)
     nz = nonvanishing(hel)
     zero_tol = 1e-20 if precision == "fp64" else 1e-8
     assert np.max(np.abs(got[~nz]), initial=0.0) < zero_tol * np.median(np.abs(ref[nz]))
-    _check_sampled(got, ref, helicity_scale(mom), nz, precision)
 
 
 def test_helicity_sum_gg_gg(api):
@@ -127,7 +136,9 @@ def test_fused_equals_two_stage(api, n, precision):
     mom, hel = _events(n, E, 3180 + n)
     dm, dh = _dev(mom), _dev(hel)
     _say(f"fused vs two-stage {precision} n={n} E={E}")
-    fused = api.me2(dm, dh, precision=precision).cpu().numpy()
+    # the two-stage path has no FP32 check: compare the plain FP32 recursions
+    fprec = "fp32_unchecked" if precision == "fp32" else precision
+    fused = api.me2(dm, dh, precision=fprec).cpu().numpy()
     two = api.color_contract(api.currents(dm, dh, precision), n).cpu().numpy()
     nz = nonvanishing(hel)
     rel = np.abs(fused - two)[nz] / np.abs(two[nz])
@@ -168,10 +179,9 @@ def test_single_event_and_tail(api):
     for E in (1, 63, 65):
         mom, hel = _events(6, E, 3300 + E)
         got = api.me2(_dev(mom), _dev(hel)).cpu().numpy()
-        ref = ome2.me2_cobg(mom, hel)
+        ref, mag = reference_cobg(mom, hel)
         nz = nonvanishing(hel)
-        srel = (np.abs(got - ref) / helicity_scale(mom))[nz]
-        assert np.max(srel, initial=0.0) < FP64_ME2_RTOL
+        assert np.all((np.abs(got - ref) <= fp64_allowance(6, ref, mag))[nz])
 
 
 def test_bitwise_deterministic(api):
@@ -194,12 +204,15 @@ def test_full_size_gg_4g_sampled(api):
     idx = np.sort(np.random.default_rng(5).choice(E, 126, replace=False))
     idx = np.concatenate([idx, [0, E - 1]])
     m, h = mom[:, :, idx], hel[:, idx]
-    ref = ome2.me2_cobg(m, h)
-    nz = nonvanishing(h)
-    scale = helicity_scale(m)
-    _check_sampled(g64[idx], ref, scale, nz, "fp64")
-    _check_sampled(g32[idx], ref, scale, nz, "fp32")
+    _check_sampled(g64[idx], m, h, "fp64")
+    _check_sampled(g32[idx], m, h, "fp32")
     assert np.all(np.isfinite(g64)) and np.all(np.isfinite(g32))
+    # FP32 against FP64 on every event of the launch
+    nz = nonvanishing(hel)
+    rel = np.abs(g32 - g64)[nz] / np.abs(g64[nz])
+    _say(f"  fp32 vs fp64, all {nz.sum()} non-vanishing events: median {np.median(rel):.2e} "
+         f"p99 {np.percentile(rel, 99):.2e} max {rel.max():.2e}")
+    assert np.percentile(rel, 99) <= 1e-5 and rel.max() <= FP32_MAX
 
 
 @pytest.mark.parametrize("n", [4, 5, 6, 7])
@@ -211,6 +224,6 @@ def test_single_event(api, n):
     dm = _dev(mom)
     for h in (hel, None):
         ref = ome2.me2_cobg(mom, h)
-        for prec, tol in (("fp64", 1e-12), ("fp32", 1e-4)):
+        for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
             got = api.me2(dm, None if h is None else _dev(h), precision=prec).cpu().numpy()
             assert abs(got[0] - ref[0]) <= tol * abs(ref[0]), (prec, h is None, got[0], ref[0])

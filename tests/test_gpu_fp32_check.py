@@ -1,0 +1,168 @@
+"""FP32 accuracy check (bg_fp32_check_set): the FP32 recursion lists the
+events whose running error bound is large compared with their amplitudes and
+evaluates them again in FP64.
+
+Bars (per event, relative to the FP64 path of the same events on non-vanishing
+helicity configurations; the FP64 path itself is checked against the
+long-double oracle in test_gpu_cobg and test_gpu_cdbg):
+  * p99 of |fp32 - fp64| / |fp64| <= 1e-5 (the accuracy target of the FP32
+    path), measured at 2^18 events per multiplicity, the launch shape of the
+    benchmark rows;
+  * every event within FP32_MAX = 3e-4, three times the largest error of an
+    unlisted event seen in the 2^20-event calibration of the thresholds.
+Threshold extremes: tau = 0 lists every non-vanishing event, so the result
+equals the FP64 path bit for bit; tau = +inf lists none, so it equals the
+unchecked FP32 path bit for bit.
+"""
+import numpy as np
+import pytest
+
+from bg_inputs import make_events, mixed_workload
+from tests.helpers import nonvanishing
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FP32_P99 = 1e-5
+FP32_MAX = 3e-4
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_06507_amd import api as a
+    return a
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _stats(got, ref, keep):
+    rel = np.abs(got - ref)[keep] / np.abs(ref[keep])
+    return np.median(rel), np.percentile(rel, 99), rel.max()
+
+
+def _dressed_keep(h, f64):
+    """Valid flows with a non-vanishing helicity configuration, excluding
+    flows that cancel to rounding level (U(1) decoupling: far below the
+    median), where a relative error is undefined."""
+    keep = nonvanishing(h) & (f64 != 0.0)
+    keep &= np.abs(f64) > 1e-8 * np.median(np.abs(f64[keep]))
+    return keep
+
+
+@pytest.mark.parametrize("n", [4, 5, 6, 7])
+def test_colour_ordered_fp32_p99(api, n):
+    E = (1 << 18) if n < 7 else (1 << 16)
+    ev = make_events(n, E, seed=8100 + n, cuts=True, sample_hel=True)
+    dm, dh = _dev(ev["mom"]), _dev(ev["hel"])
+    _say(f"checked fp32 colour-ordered n={n} E={E}")
+    f64 = api.me2(dm, dh, precision="fp64").cpu().numpy()
+    f32 = api.me2(dm, dh, precision="fp32").cpu().numpy()
+    raw = api.me2(dm, dh, precision="fp32_unchecked").cpu().numpy()
+    keep = nonvanishing(ev["hel"])
+    med, p99, mx = _stats(f32, f64, keep)
+    _, p99r, mxr = _stats(raw, f64, keep)
+    listed = np.mean((f32 == f64)[keep] & (raw != f64)[keep])
+    _say(f"  checked median {med:.2e} p99 {p99:.2e} max {mx:.2e}; unchecked p99 {p99r:.2e} "
+         f"max {mxr:.2e}; re-evaluated ~{listed:.1%}")
+    assert p99 <= FP32_P99
+    assert mx <= FP32_MAX
+    assert np.all(np.isfinite(f32))
+
+
+@pytest.mark.parametrize("n", [5, 6, 7, 8, 9])
+def test_colour_dressed_fp32_p99(api, n):
+    E = 1 << 18
+    ev = make_events(n, E, seed=8200 + n, cuts=True, sample_hel=True, sample_col=True)
+    dm, dh, dc = _dev(ev["mom"]), _dev(ev["hel"]), _dev(ev["col"])
+    _say(f"checked fp32 colour-dressed n={n} E={E}")
+    f64 = api.me2(dm, dh, dc, mode="cdbg", precision="fp64").cpu().numpy()
+    f32 = api.me2(dm, dh, dc, mode="cdbg", precision="fp32").cpu().numpy()
+    raw = api.me2(dm, dh, dc, mode="cdbg", precision="fp32_unchecked").cpu().numpy()
+    keep = _dressed_keep(ev["hel"], f64)
+    # invalid flows are exactly 0 on both paths; a flow whose amplitude
+    # cancels to rounding may give an exact 0 on one side only
+    typical = np.median(np.abs(f64[f64 != 0.0]))
+    noise = (np.abs(f64) < 1e-8 * typical) & (np.abs(f32) < 1e-8 * typical)
+    assert np.array_equal((f32 == 0.0) | noise, (f64 == 0.0) | noise)
+    med, p99, mx = _stats(f32, f64, keep)
+    _, p99r, mxr = _stats(raw, f64, keep)
+    _say(f"  {keep.sum()} valid: checked median {med:.2e} p99 {p99:.2e} max {mx:.2e}; "
+         f"unchecked p99 {p99r:.2e} max {mxr:.2e}")
+    assert p99 <= FP32_P99
+    assert mx <= FP32_MAX
+
+
+@pytest.mark.parametrize("mode,n", [("cobg", 5), ("cobg", 6), ("cobg", 7), ("cdbg", 6), ("cdbg", 8)])
+def test_threshold_extremes(api, mode, n):
+    """tau = 0: every non-vanishing event is re-evaluated in FP64, so the
+    result equals the FP64 path bit for bit; tau = inf: none is, so it equals
+    the unchecked FP32 path bit for bit.  Odd event counts leave ragged
+    tiles."""
+    E = 3001 if mode == "cobg" else 20011
+    ev = make_events(n, E, seed=8300 + n, cuts=True, sample_hel=True, sample_col=True)
+    dm, dh = _dev(ev["mom"]), _dev(ev["hel"])
+    dc = _dev(ev["col"]) if mode == "cdbg" else None
+    keep = nonvanishing(ev["hel"])
+    f64 = api.me2(dm, dh, dc, mode=mode, precision="fp64").cpu().numpy()
+    raw = api.me2(dm, dh, dc, mode=mode, precision="fp32_unchecked").cpu().numpy()
+    default = api.fp32_check(n, mode=mode)
+    try:
+        api.fp32_check(n, 0.0, mode=mode)
+        all64 = api.me2(dm, dh, dc, mode=mode, precision="fp32").cpu().numpy()
+        api.fp32_check(n, float("inf"), mode=mode)
+        none = api.me2(dm, dh, dc, mode=mode, precision="fp32").cpu().numpy()
+    finally:
+        api.fp32_check(n, default, mode=mode)
+    assert np.array_equal(all64[keep], f64[keep])
+    assert np.array_equal(none, raw)
+
+
+def test_threshold_api(api):
+    from paper_2106_06507_amd._lib import BGError
+    assert api.fp32_check(4) == float("inf")  # n = 4 is not checked by default
+    for n in (5, 6, 7):
+        assert 0.0 < api.fp32_check(n) < float("inf")
+    for n in range(4, 10):
+        assert 0.0 < api.fp32_check(n, mode="cdbg") < float("inf")
+    for bad in ((8, "cobg"), (3, "cdbg"), (10, "cdbg")):
+        with pytest.raises(BGError):
+            api.fp32_check(bad[0], mode=bad[1])
+    with pytest.raises(BGError):
+        api.fp32_check(6, -1.0)
+    with pytest.raises(BGError):
+        api.fp32_check(6, float("nan"))
+    with pytest.raises(BGError):
+        api.fp32_check(6, mode="comc")
+
+
+def test_mixed_batch_fp32_p99(api):
+    """The persistent mixed batch checks its FP32 segments the same way (one
+    FP32 pass that lists events per segment, a device-built tile table and
+    one FP64 re-evaluation pass): per segment p99 <= 1e-5 against the FP64
+    batch of the same segments, and every FP64-re-evaluated event equal to
+    the FP64 batch bit for bit is not required (tiles differ) but the error
+    bars are."""
+    ev = mixed_workload(scale=0.25)
+    segs = []
+    for n, e in sorted(ev.items()):
+        segs.append({"mom": _dev(e["mom"]), "hel": _dev(e["hel"]),
+                     "col": _dev(e["col"]) if n >= 8 else None, "mode": "auto"})
+    _say("checked fp32 batch: " + ", ".join(f"n={n} E={e['mom'].shape[2]}" for n, e in sorted(ev.items())))
+    g32 = [t.cpu().numpy() for t in api.me2_batch(segs, "fp32")]
+    g64 = [t.cpu().numpy() for t in api.me2_batch(segs, "fp64")]
+    for (n, e), a, b in zip(sorted(ev.items()), g32, g64):
+        keep = _dressed_keep(e["hel"], b) if n >= 8 else nonvanishing(e["hel"])
+        if keep.sum() < 200:
+            continue
+        med, p99, mx = _stats(a, b, keep)
+        _say(f"  n={n}: {keep.sum()} events, median {med:.2e} p99 {p99:.2e} max {mx:.2e}")
+        assert p99 <= FP32_P99, n
+        assert mx <= FP32_MAX, n

@@ -99,5 +99,5 @@ def test_context_create_without_device_reports_enodev():
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     h = ctypes.c_void_p()
-    assert lib().bg_context_create(ctypes.byref(h), 0) == _lib.BG_ENODEV
-    assert lib().bg_context_create(None, 0) == _lib.BG_EINVAL
+    assert lib().bg_context_create(ctypes.byref(h), 0, 0) == _lib.BG_ENODEV
+    assert lib().bg_context_create(None, 0, 0) == _lib.BG_EINVAL
