@@ -101,3 +101,5 @@ def test_context_create_without_device_reports_enodev():
     h = ctypes.c_void_p()
     assert lib().bg_context_create(ctypes.byref(h), 0, 0) == _lib.BG_ENODEV
     assert lib().bg_context_create(None, 0, 0) == _lib.BG_EINVAL
+    # unknown context flags are rejected before any device is touched
+    assert lib().bg_context_create(ctypes.byref(h), 0, 1 << 10) == _lib.BG_EINVAL
