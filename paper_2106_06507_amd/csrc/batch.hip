@@ -193,28 +193,36 @@ __global__ void __launch_bounds__(kBatchLanes, WAVES) batch_kernel(const BatchSe
 }
 
 // Tiles of the re-evaluation pass: segment s contributes ceil(fcount[s] /
-// step) tiles over its list, step 128 (colour-ordered) or 256 (colour-
-// dressed: one event at a time on the whole block, so each tile is a chunk).
+// step) tiles over its list.  Colour-dressed segments come first and take one
+// event per tile (a listed event is valid and costs a whole block for tens
+// of microseconds, so the queue must spread them over all blocks);
+// colour-ordered segments follow with tiles of 128 events (four 32-event
+// sub-tiles, one per wave).
 __global__ void __launch_bounds__(256) fix_tiles_kernel(const BatchSegTable segs, int n_segs,
                                                        const unsigned* __restrict__ fcount,
                                                        BatchTile* __restrict__ tiles,
                                                        unsigned* __restrict__ n_tiles) {
-  __shared__ unsigned start[kBatchMaxSegs + 1];
+  __shared__ unsigned start[kBatchMaxSegs];
+  __shared__ unsigned ntile[kBatchMaxSegs];
   if (threadIdx.x == 0) {
     unsigned acc = 0;
-    for (int i = 0; i < n_segs; ++i) {
-      start[i] = acc;
-      const unsigned step = segs.s[i].kind >= kBatchCdbg ? 256u : 128u;
-      acc += (fcount[i] + step - 1) / step;
+    for (int pass = 0; pass < 2; ++pass) {  // dressed segments first
+      for (int i = 0; i < n_segs; ++i) {
+        const bool cd = segs.s[i].kind >= kBatchCdbg;
+        if (cd != (pass == 0)) continue;
+        const unsigned step = cd ? 1u : 128u;
+        start[i] = acc;
+        ntile[i] = (fcount[i] + step - 1) / step;
+        acc += ntile[i];
+      }
     }
-    start[n_segs] = acc;
     *n_tiles = acc;
   }
   __syncthreads();
   for (int i = 0; i < n_segs; ++i) {
-    const unsigned step = segs.s[i].kind >= kBatchCdbg ? 256u : 128u;
+    const unsigned step = segs.s[i].kind >= kBatchCdbg ? 1u : 128u;
     const unsigned cnt = fcount[i];
-    for (unsigned k = threadIdx.x; k < start[i + 1] - start[i]; k += blockDim.x) {
+    for (unsigned k = threadIdx.x; k < ntile[i]; k += blockDim.x) {
       const unsigned f = k * step;
       tiles[start[i] + k] = BatchTile{(int64_t)f, i, (int)(cnt - f < step ? cnt - f : step)};
     }

@@ -891,7 +891,7 @@ int batch_plan(bg_context* ctx, const bg_request* segs, int n_segs, const bg_bat
     for (int i = 0; i < n_segs; ++i) {
       pl.list_off.push_back(words);
       words += (size_t)segs[i].n_events;
-      const int64_t step = resolved_mode(&segs[i]) == BG_MODE_CDBG ? 256 : 128;
+      const int64_t step = resolved_mode(&segs[i]) == BG_MODE_CDBG ? 1 : 128;
       fix_tiles += (uint64_t)((segs[i].n_events + step - 1) / step);
     }
     if (fix_tiles > 0x7fffffffu) {

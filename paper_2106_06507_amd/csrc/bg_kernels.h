@@ -148,8 +148,8 @@ int batch_launch(bool fp32, int waves, int pass, const BatchSegTable& segs,
                  unsigned* counter, double* scratch, int64_t scratch_stride, int grid, size_t lds,
                  hipStream_t stream);
 // Tiles of the re-evaluation pass from the per-segment counts fcount[s] of
-// listed events: colour-ordered tiles of up to 128 listed events, colour-
-// dressed tiles of up to 256; tiles[], *n_tiles on the device.
+// listed events: colour-dressed tiles of one listed event (queued first),
+// colour-ordered tiles of up to 128; tiles[], *n_tiles on the device.
 int batch_fix_tiles(const BatchSegTable& segs, int n_segs, const unsigned* fcount,
                     BatchTile* tiles, unsigned* n_tiles, hipStream_t stream);
 
