@@ -158,6 +158,26 @@ typedef struct bg_request {
  * give exactly 0.  May allocate context workspace on first use of a size. */
 int bg_me2(bg_context* ctx, const bg_request* req, void* stream);
 
+/* bg_me2 for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * request, kernels and results (bit for bit) as bg_me2, but every piece of
+ * device memory beyond the caller's inputs and outputs (check lists,
+ * counters, colour-dressed event lists, per-block scratch of the n = 7
+ * kernels) comes from a file-scope device array of BG_NOALLOC_SCRATCH_BYTES
+ * that each GPU holds until the process ends; its address is looked up once
+ * per device when the first context on it is created, and the colour
+ * matrices it needs are uploaded then.  The call itself calls no hipMalloc
+ * or hipFree.  Modes: BG_MODE_COBG, BG_MODE_CDBG, BG_MODE_AUTO, BG_MODE_LC
+ * (BG_MODE_COMC needs growing buffers: BG_EUNSUPPORTED).  At most
+ * BG_NOALLOC_MAX_EVENTS events (BG_ERANGE beyond).  Every call on a GPU
+ * shares that GPU's array, whatever its context: calls that overlap in time
+ * on one GPU (other streams, other contexts, other host threads) race and
+ * must be ordered by the caller.  Counters are cleared on the stream at the
+ * start of each call. */
+#define BG_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define BG_NOALLOC_MAX_EVENTS ((int64_t)1 << 22)
+int bg_me2_noalloc(bg_context* ctx, const bg_request* req, void* stream);
+
 /* FP32 accuracy control (BG_PREC_FP32_MIXED).  While the FP32 recursion runs
  * it also carries, per current, a bound on its components computed as if
  * every product were taken in modulus (the classical running error bound, up

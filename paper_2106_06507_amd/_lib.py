@@ -78,6 +78,7 @@ _SIGNATURES = {
     "bg_currents": (_I, [_P, _I, _I64, _P, _P, _I, _P, _P]),
     "bg_color_contract": (_I, [_P, _I, _I64, _P, _P, _I, _P]),
     "bg_me2": (_I, [_P, ctypes.POINTER(bg_request), _P]),
+    "bg_me2_noalloc": (_I, [_P, ctypes.POINTER(bg_request), _P]),
     "bg_me2_grad": (_I, [_P, ctypes.POINTER(bg_request), _P, _P, _P]),
     "bg_me2_batch": (_I, [_P, ctypes.POINTER(bg_request), _I, _P]),
     "bg_batch_config_get": (_I, [_P, _I, ctypes.POINTER(bg_batch_config)]),

@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <utility>
 #include <vector>
@@ -91,6 +92,7 @@ struct bg_context {
   int occ_fix[BG_N_MAX + 1][2] = {};         // blocks per CU of the FP64 re-evaluation [n][hsum]
   int occ_cdbg_chk[BG_N_MAX + 1] = {};       // of the checked FP32 colour-dressed event kernel
   unsigned* val_dev = nullptr;               // BG_FLAG_VALIDATE result word
+  unsigned char* noalloc = nullptr;          // this device's static workspace (bg_me2_noalloc)
   hipEvent_t ws_event = nullptr;             // recorded after each call that uses the workspace
   hipStream_t ws_stream = nullptr;           // stream of that call
   bool ws_pending = false;
@@ -262,6 +264,29 @@ int ensure_scratch(bg_context* ctx, size_t bytes) {
   return BG_OK;
 }
 
+// Workspace of one call when it must not allocate (bg_me2_noalloc): views
+// into the per-device static array of noalloc.hip (layout in bg_kernels.h).
+struct FixedWs {
+  unsigned* flag_ws;     // check: count at word 0, list from word kFlagListOffset
+  unsigned* counter;     // [0] batch queue (unused), [1] n = 7 tile queue
+  unsigned* cws;         // colour-dressed counters and lists
+  unsigned* val;         // BG_FLAG_VALIDATE result word
+  double* scratch;       // per-block scratch (n = 7)
+  size_t scratch_bytes;
+};
+
+FixedWs fixed_ws(unsigned char* base) {
+  FixedWs w;
+  unsigned* words = reinterpret_cast<unsigned*>(base);
+  w.counter = words + 32;
+  w.val = words + 48;
+  w.flag_ws = words + 64;  // its list starts 64 words further: within the list region
+  w.cws = words + 64;
+  w.scratch = reinterpret_cast<double*>(base + bg::kNoallocBlockOffset);
+  w.scratch_bytes = bg::kNoallocScratchBytes - bg::kNoallocBlockOffset;
+  return w;
+}
+
 // FP32 check workspace: a count word and a list of up to E event indices.
 constexpr size_t kFlagListOffset = 64;  // words: the list starts 256 bytes in
 int ensure_flags(bg_context* ctx, int64_t E) {
@@ -306,21 +331,23 @@ int ws_release(bg_context* ctx, hipStream_t stream, int status) {
 }
 
 // BG_FLAG_VALIDATE: every hel entry +-1, every col entry in {0, 1, 2}.
+// fixed: the result word of the static workspace instead of a context buffer.
 int validate_values(bg_context* ctx, int n, int64_t E, const int8_t* hel, const int8_t* col,
-                    hipStream_t stream) {
+                    hipStream_t stream, const FixedWs* fixed = nullptr) {
   if (capturing_stream(stream)) return BG_EINVAL;
-  if (!ctx->val_dev) {
+  unsigned* word = fixed ? fixed->val : ctx->val_dev;
+  if (!word) {
     int st = hip_status(hipMalloc(&ctx->val_dev, 256), "hipMalloc(validate)");
     if (st) return st;
+    word = ctx->val_dev;
   }
-  int st = launch_status(bg::fill_u32(ctx->val_dev, 1, 0u, stream));
+  int st = launch_status(bg::fill_u32(word, 1, 0u, stream));
   if (!st)
     st = launch_status(bg::validate_inputs(hel ? (int64_t)n * E : 0, hel,
-                                           col ? (int64_t)2 * n * E : 0, col, ctx->val_dev,
-                                           stream));
+                                           col ? (int64_t)2 * n * E : 0, col, word, stream));
   unsigned bad = 0;
   if (!st)
-    st = hip_status(hipMemcpyAsync(&bad, ctx->val_dev, sizeof(unsigned), hipMemcpyDeviceToHost,
+    st = hip_status(hipMemcpyAsync(&bad, word, sizeof(unsigned), hipMemcpyDeviceToHost,
                                    stream), "hipMemcpyAsync(validate)");
   if (!st) st = hip_status(hipStreamSynchronize(stream), "hipStreamSynchronize");
   if (st) return st;
@@ -329,6 +356,27 @@ int validate_values(bg_context* ctx, int n, int64_t E, const int8_t* hel, const 
 
 int grad_run(bg_context* ctx, const bg_request* r, const double* grad_me2, double* grad_mom,
              hipStream_t s);
+
+// Device address of each device's copy of the static workspace of
+// bg_me2_noalloc, looked up once per device (with that device current).
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+unsigned char* g_noalloc_ptr[kMaxDevices] = {};
+
+int noalloc_address(int device, unsigned char** out) {
+  if (device < 0 || device >= kMaxDevices) return BG_ENODEV;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[device]) {
+    void* p = nullptr;
+    if (bg::noalloc_scratch_address(&p) != 0) {
+      BG_LOG("hipGetSymbolAddress of the static workspace failed on device %d", device);
+      return BG_EDEVICE;
+    }
+    g_noalloc_ptr[device] = static_cast<unsigned char*>(p);
+  }
+  *out = g_noalloc_ptr[device];
+  return BG_OK;
+}
 
 // Lexicographic orderings of the middle gluons 1..n-2, as bytes [K][n-2].
 int ensure_perms(bg_context* ctx, int n) {
@@ -433,6 +481,14 @@ int bg_context_create(bg_context** out, int device, uint32_t flags) {
       delete ctx;
       return BG_EDEVICE;
     }
+    int st = noalloc_address(device, &ctx->noalloc);
+    // the colour matrices of the colour-ordered path, so that bg_me2_noalloc
+    // never has to upload one
+    for (int n = 4; n <= 7 && !st; ++n) st = ensure_colour(ctx, n);
+    if (st) {
+      bg_context_destroy(ctx);
+      return st;
+    }
   }
   *out = ctx;
   return BG_OK;
@@ -496,10 +552,14 @@ static int ensure_counters(bg_context* ctx) {
   return hip_status(hipMalloc(&ctx->counter, 256), "hipMalloc(counters)");
 }
 
-static int me2_cobg(bg_context* ctx, const bg_request* r, uint32_t flags, hipStream_t stream) {
+// fixed (may be null): use the static workspace, allocate nothing (the
+// colour matrix must then be uploaded already, see bg_context_create).
+static int me2_cobg(bg_context* ctx, const bg_request* r, uint32_t flags, hipStream_t stream,
+                    const FixedWs* fixed = nullptr) {
   const int n = r->n;
   if (n > 7) return BG_EUNSUPPORTED;
   const int64_t E = r->n_events;
+  if (fixed && !ctx->Cb_dev[n]) return BG_EINVAL;
   int st = ensure_colour(ctx, n);
   if (st) return st;
   const bool fp32 = r->precision == BG_PREC_FP32_MIXED;
@@ -507,41 +567,56 @@ static int me2_cobg(bg_context* ctx, const bg_request* r, uint32_t flags, hipStr
   const float tau = ctx->fp32_tau[0][n];
   const bool check = fp32 && !(flags & BG_FLAG_FP32_UNCHECKED) && !(tau == INFINITY) &&
                      E <= (int64_t)0xffffffffLL;
+  // blocks whose per-block scratch fits the static workspace (n = 7)
+  const int64_t fixed_blocks =
+      fixed ? (int64_t)(fixed->scratch_bytes /
+                        (sizeof(double) * (size_t)std::max(1, bg::cobg_fused_scratch_doubles(n))))
+            : INT64_MAX;
   int64_t grid = 0, fix_grid = 0;
   if (check) {
     int& occ = ctx->occ_fix[n][hsum ? 1 : 0];
     if (occ <= 0) occ = bg::cobg_fix_blocks_per_cu(n, hsum);
     if (occ <= 0) return BG_EDEVICE;
-    fix_grid = std::min<int64_t>((E + 31) / 32, (int64_t)ctx->num_cus * occ);
-    st = ensure_flags(ctx, E);
-    if (st) return st;
+    fix_grid = std::min<int64_t>({(E + 31) / 32, (int64_t)ctx->num_cus * occ, fixed_blocks});
+    if (!fixed) {
+      st = ensure_flags(ctx, E);
+      if (st) return st;
+    }
   }
+  double* scratch = fixed ? fixed->scratch : ctx->scratch;
+  unsigned* counter = fixed ? fixed->counter : ctx->counter;
   if (n == 7) {  // persistent kernel with per-block scratch
     int& occ = ctx->occ_fused[fp32 ? 1 : 0][hsum ? 1 : 0][check ? 1 : 0];
     if (occ <= 0) occ = bg::cobg_fused_persistent_blocks_per_cu(fp32, hsum, check);
     if (occ <= 0) return BG_EDEVICE;
-    grid = std::min<int64_t>((E + 31) / 32, (int64_t)ctx->num_cus * occ);
-    st = ensure_scratch(ctx, sizeof(double) * (size_t)std::max(grid, fix_grid) *
-                                 bg::cobg_fused_scratch_doubles(n));
-    if (!st) st = ensure_counters(ctx);
-    if (st) return st;
+    grid = std::min<int64_t>({(E + 31) / 32, (int64_t)ctx->num_cus * occ, fixed_blocks});
+    if (!fixed) {
+      st = ensure_scratch(ctx, sizeof(double) * (size_t)std::max(grid, fix_grid) *
+                                   bg::cobg_fused_scratch_doubles(n));
+      if (!st) st = ensure_counters(ctx);
+      if (st) return st;
+      scratch = ctx->scratch;
+      counter = ctx->counter;
+    }
   }
   bg::CheckArgs ca{tau, nullptr, nullptr};
   if (check) {
-    ca.count = ctx->flag_ws;
-    ca.list = ctx->flag_ws + kFlagListOffset;
+    unsigned* ws = fixed ? fixed->flag_ws : ctx->flag_ws;
+    ca.count = ws;
+    ca.list = ws + kFlagListOffset;
     st = launch_status(bg::fill_u32(ca.count, 1, 0u, stream));
     if (st) return st;
   }
-  st = launch_status(bg::cobg_fused_me2(n, fp32, E, r->mom, r->hel, ctx->Cb_dev[n], ctx->scratch,
-                                        ctx->counter ? ctx->counter + 1 : nullptr, (int)grid,
-                                        r->me2, check ? &ca : nullptr, stream));
+  st = launch_status(bg::cobg_fused_me2(n, fp32, E, r->mom, r->hel, ctx->Cb_dev[n], scratch,
+                                        counter ? counter + 1 : nullptr, (int)grid, r->me2,
+                                        check ? &ca : nullptr, stream));
   if (st || !check) return st;
-  return launch_status(bg::cobg_fix_me2(n, E, r->mom, r->hel, ctx->Cb_dev[n], ctx->scratch,
-                                        ca.count, ca.list, (int)fix_grid, r->me2, stream));
+  return launch_status(bg::cobg_fix_me2(n, E, r->mom, r->hel, ctx->Cb_dev[n], scratch, ca.count,
+                                        ca.list, (int)fix_grid, r->me2, stream));
 }
 
-static int me2_cdbg(bg_context* ctx, const bg_request* r, uint32_t flags, hipStream_t stream) {
+static int me2_cdbg(bg_context* ctx, const bg_request* r, uint32_t flags, hipStream_t stream,
+                    const FixedWs* fixed = nullptr) {
   const int n = r->n;
   const int64_t E = r->n_events;
   const bool fp32 = r->precision == BG_PREC_FP32_MIXED;
@@ -551,7 +626,7 @@ static int me2_cdbg(bg_context* ctx, const bg_request* r, uint32_t flags, hipStr
   const size_t lds = bg::cdbg_lds_bytes(n, fp32);
   if (lds == 0 || lds > ctx->lds_per_block) return BG_EUNSUPPORTED;
   const size_t need = sizeof(unsigned) * (size_t)(4 + 2 * E);
-  if (ctx->cws_bytes < need) {
+  if (!fixed && ctx->cws_bytes < need) {
     if (ctx->cws) {
       int st = hip_status(hipDeviceSynchronize(), "hipDeviceSynchronize");
       if (st) return st;
@@ -576,8 +651,9 @@ static int me2_cdbg(bg_context* ctx, const bg_request* r, uint32_t flags, hipStr
     fix_grid = std::max<int64_t>(1, std::min<int64_t>((int64_t)ctx->num_cus * per_cu64, E));
   }
   bg::CheckArgs ca{tau, nullptr, nullptr};
-  return launch_status(bg::cdbg_me2(n, fp32, E, r->mom, r->hel, r->col, ctx->cws, r->me2,
-                                    (int)grid, check ? &ca : nullptr, (int)fix_grid, stream));
+  return launch_status(bg::cdbg_me2(n, fp32, E, r->mom, r->hel, r->col,
+                                    fixed ? fixed->cws : ctx->cws, r->me2, (int)grid,
+                                    check ? &ca : nullptr, (int)fix_grid, stream));
 }
 
 static int me2_comc(bg_context* ctx, const bg_request* r, hipStream_t stream) {
@@ -664,17 +740,18 @@ static int validate_request(const bg_request* r) {
   return BG_OK;
 }
 
-static int me2_dispatch(bg_context* ctx, const bg_request* r, uint32_t flags, hipStream_t stream) {
+static int me2_dispatch(bg_context* ctx, const bg_request* r, uint32_t flags, hipStream_t stream,
+                        const FixedWs* fixed = nullptr) {
   const int mode = r->mode == BG_MODE_AUTO ? (r->n <= 7 ? BG_MODE_COBG : BG_MODE_CDBG) : r->mode;
-  if (mode == BG_MODE_COBG) return me2_cobg(ctx, r, flags, stream);
-  if (mode == BG_MODE_COMC) return me2_comc(ctx, r, stream);
+  if (mode == BG_MODE_COBG) return me2_cobg(ctx, r, flags, stream, fixed);
+  if (mode == BG_MODE_COMC) return fixed ? BG_EUNSUPPORTED : me2_comc(ctx, r, stream);
   if (mode == BG_MODE_LC) {
     if (r->n > 7) return BG_EUNSUPPORTED;
     if (!r->hel) return BG_EINVAL;
     return launch_status(bg::lc_me2(r->n, r->precision == BG_PREC_FP32_MIXED, r->n_events, r->mom,
                                     r->hel, r->me2, stream));
   }
-  return me2_cdbg(ctx, r, flags, stream);
+  return me2_cdbg(ctx, r, flags, stream, fixed);
 }
 
 int bg_me2(bg_context* ctx, const bg_request* r, void* stream) {
@@ -692,6 +769,26 @@ int bg_me2(bg_context* ctx, const bg_request* r, void* stream) {
     st = validate_values(ctx, r->n, r->n_events, r->hel, r->col, s);
   if (!st) st = me2_dispatch(ctx, r, flags, s);
   return ws_release(ctx, s, st);
+}
+
+int bg_me2_noalloc(bg_context* ctx, const bg_request* r, void* stream) {
+  if (!ctx) return BG_EINVAL;
+  int st = validate_request(r);
+  if (st) return st;
+  if (r->n_events > 0 && !r->me2) return BG_EINVAL;
+  if (r->n_events > bg::kNoallocMaxEvents) return BG_ERANGE;
+  if (r->n_events == 0) return BG_OK;
+  if (!ctx->noalloc) return BG_EDEVICE;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return BG_EDEVICE;
+  hipStream_t s = (hipStream_t)stream;
+  const FixedWs w = fixed_ws(ctx->noalloc);
+  const uint32_t flags = r->flags | ctx->flags;
+  if (flags & BG_FLAG_VALIDATE) {
+    st = validate_values(ctx, r->n, r->n_events, r->hel, r->col, s, &w);
+    if (st) return st;
+  }
+  return me2_dispatch(ctx, r, flags, s, &w);
 }
 
 static int check_slot(int mode, int n) {

@@ -23,6 +23,16 @@ inline int64_t factorial(int k) {
   return r;
 }
 
+// Allocation-free entry point: size of the per-device static workspace
+// (noalloc.hip) and its layout.  Words [0, 64) counters; from byte 256 the
+// event lists (at most 2 x kNoallocMaxEvents words); from kNoallocBlockOffset
+// the per-block scratch of the persistent n = 7 kernels.
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+constexpr int64_t kNoallocMaxEvents = (int64_t)1 << 22;
+constexpr size_t kNoallocBlockOffset = (size_t)33 << 20;
+// Device address of this device's copy of the array (device must be current).
+int noalloc_scratch_address(void** out);
+
 // p[0..n) = v on `stream` (a kernel, so it can be recorded into a graph).
 int fill_u32(unsigned* p, int n, unsigned v, hipStream_t stream);
 // bad[0] |= 1 when one of the nh bytes of hel is not +-1 or one of the nc
