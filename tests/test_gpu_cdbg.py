@@ -10,8 +10,9 @@ helicity configuration does not vanish identically:
   * FP64: |got - ref| <= max(1e-12 |ref|, 12 (n - 2) u m) with m = 2 |A| m_A
     and m_A the magnitude of the flow amplitude written as the sum of the
     colour-ordered amplitudes whose chain closes (oracle.conditioning; the
-    same running error bound as the colour-ordered path), and the median
-    relative error below 1e-13;
+    same running error bound as the colour-ordered path), the median
+    relative error below 1e-13, and p99 and max within 10x those of the
+    FP64 oracle's own dressed recursion (helpers.fp64_comparable);
   * FP32 (checked, FP64 re-evaluation of listed events): every event within
     FP32_MAX = 3e-4 and the median below 1e-6; p99 <= 1e-5 is asserted on
     2^18-event samples in test_gpu_fp32_check.
@@ -23,7 +24,7 @@ from bg_inputs import make_events, workload
 from oracle import cdbg as ocdbg
 from oracle.conditioning import flow_amplitude_magnitude
 from oracle.numeric import extended
-from tests.helpers import U64, mhv_helicities, nonvanishing, valid_colours
+from tests.helpers import U64, fp64_comparable, mhv_helicities, nonvanishing, valid_colours
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -66,7 +67,11 @@ def _check(got, ref, mom, hel, col, precision, label):
     _say(f"  {label} {precision}: events {nz.sum()} rel err median {np.median(rel):.2e} "
          f"p99 {np.percentile(rel, 99):.2e} max {rel.max():.2e}")
     if precision == "fp64":
+        o64 = np.abs(ocdbg.flow_amplitude(mom, hel, col)) ** 2
+        orel = np.abs(o64 - ref)[nz] / np.abs(ref[nz])
+        _say(f"  FP64 oracle's own error: p99 {np.percentile(orel, 99):.2e} max {orel.max():.2e}")
         assert np.median(rel) < 1e-13
+        assert fp64_comparable(rel, orel)
         # the conditioning term only for the events above 1e-12 (it is costly)
         over = np.nonzero(nz & (d > 1e-12 * np.abs(ref)))[0]
         if over.size:
