@@ -25,6 +25,7 @@ Prints one JSON line.  Only one GPU is used: --gpus above 1 exits.
 import argparse
 import hashlib
 import json
+import math
 import os
 import platform
 import sys
@@ -217,7 +218,7 @@ def section_headline(args, api, wm, torch):
             "value": E / ((rms64 + cms) * 1e-3), "recursion_ms": rms64, "contraction_mfma_ms": cms,
             "rel_diff_vs_fused": two_vs,
             "roofline_contraction": dict(
-                roofline("contract_mfma_kernel<32>", wm.contraction_flops_per_event(n), E, cms,
+                roofline("contract_mfma_kernel<24>", wm.contraction_flops_per_event(n), E, cms,
                          wm.PEAK_FP64_MFMA_TFLOPS, "A^dagger C A, K = 24, 4K^2 + 4K flops"),
                 bound="mfma",
                 hbm_GBs=wm.contraction_bytes_per_event(n) * E / (cms * 1e-3) / 1e9,
@@ -393,6 +394,38 @@ def section_pipeline(args, api, torch):
             "value": E / (pms * 1e-3)}
 
 
+def two_stage_row(api, wm, torch, n, mom, hel, steps):
+    """Colour-ordered FP64 |M|^2 as two calls: the amplitudes of every ordering
+    to memory (bg_currents), then the colour sum A^dagger C A (bg_color_contract:
+    matrix cores with C in LDS for K = 24 and 120; for K = 720 C is rebuilt
+    from its first row by relabelling)."""
+    E = mom.shape[2]
+    K = math.factorial(n - 2)
+    amp = torch.empty((2, K, E), dtype=torch.float64, device="cuda")
+    out = torch.empty(E, dtype=torch.float64, device="cuda")
+    log(f"timing n={n} two-stage: amplitudes, then the colour sum (K = {K})")
+    rms = time_events(lambda: api.currents(mom, hel, "fp64", out=amp), steps, 1)
+    cms = time_events(lambda: api.color_contract(amp, n, out=out), steps, 1)
+    kern = ("relabel_contract_kernel<6> + relabel_reduce_kernel" if K == 720
+            else f"contract_mfma_kernel<{K}>" if K in (24, 120) else f"contract_valu<{K}>")
+    row = {"events": E, "K": K, "value": E / ((rms + cms) * 1e-3), "recursion_ms": rms,
+           "contraction_ms": cms,
+           "roofline_recursion": roofline(f"cobg_pair_kernel<{n},double>", wm.cobg_flops_per_event(n),
+                                          E, rms, wm.PEAK_FP64_VALU_TFLOPS,
+                                          "colour-ordered recursion, FP64 flops per event"),
+           "roofline_contraction": dict(
+               roofline(kern, wm.contraction_flops_per_event(n), E, cms, wm.PEAK_FP64_MFMA_TFLOPS,
+                        f"A^dagger C A, K = {K}, 4K^2 + 4K flops"),
+               bound="mfma",
+               hbm_GBs=wm.contraction_bytes_per_event(n) * E / (cms * 1e-3) / 1e9,
+               hbm_frac=wm.contraction_bytes_per_event(n) * E / (cms * 1e-3) / 1e9 / wm.PEAK_HBM_GBS)}
+    if n == 8:
+        me = torch.empty(E, dtype=torch.float64, device="cuda")
+        row["me2_call_ms"] = time_events(lambda: api.me2(mom, hel, mode="cobg", out=me), steps, 1)
+        row["me2_equals_two_stage"] = bool(torch.equal(me, out))
+    return row
+
+
 def section_per_n(args, api, wm, torch):
     """Events/s and roofline fraction per gluon multiplicity, FP64 and FP32
     (checked), with the FP32 error relative to the FP64 evaluation of the same
@@ -452,6 +485,12 @@ def section_per_n(args, api, wm, torch):
                      "rel_dev_from_dressed_fp64": rel_err_stats(buf.cpu().numpy()[ck], dres[ck])}
         row["colour_sampled_ordered"] = co
         row["valid_fraction"] = float((dres != 0.0).mean())
+        if n in (7, 8):
+            # full colour through memory: K = 120 on matrix cores, and K = 720
+            # with the colour matrix held as its first row
+            E2 = E if n == 7 else 1 << 16
+            row["full_colour_ordered_two_stage_fp64"] = two_stage_row(
+                api, wm, torch, n, mom[:, :, :E2].contiguous(), hel[:, :E2].contiguous(), steps)
         if not cd:
             # leading-colour mode on the same events: all (n-1)! orderings,
             # no colour matrix; its deviation from the full colour sum

@@ -69,7 +69,7 @@ extern "C" {
 #define BG_EUNSUPPORTED -6   /* valid request the library does not implement */
 
 /* evaluation mode */
-#define BG_MODE_COBG 0       /* colour-ordered recursion + colour matrix */
+#define BG_MODE_COBG 0       /* colour-ordered recursion + colour matrix (n <= 8) */
 #define BG_MODE_CDBG 1       /* colour-dressed recursion, colours sampled (col required) */
 #define BG_MODE_AUTO 2       /* COBG for n <= 7, CDBG for n >= 8 */
 #define BG_MODE_LC   3       /* leading colour: N^(n-2)(N^2-1) sum over the (n-1)! orderings
@@ -125,13 +125,21 @@ int bg_color_matrix(int n, double* out, int64_t cap);
  * (Section 2.3 eqs. cobg and cobg_full_amplitude; the printed p^2_{1,n} is read
  * as the inverse propagator of J(1..n-1), i.e. the top current is amputated).
  * One helicity configuration per event (hel required).  precision selects the
- * recursion arithmetic.  Output amp [2][K][E] as above.  n in [4, 7]. */
+ * recursion arithmetic (BG_PREC_FP32_MIXED: plain FP32 recursion, no
+ * accuracy check).  Output amp [2][K][E] as above.  n in [4, 8]
+ * (BG_EUNSUPPORTED for n = 9). */
 int bg_currents(bg_context* ctx, int n, int64_t n_events, const double* mom,
                 const int8_t* hel, int precision, double* amp, void* stream);
 
 /* me2[e] = sum_{s,t} C_st Re(A_s conj(A_t)) (eq. color_summed_analytic) for
- * amp [2][K][E] from bg_currents, in FP64 (matrix cores for K >= 24).
- * If accumulate != 0 the result is added to me2 instead of stored.  n in [4, 7]. */
+ * amp [2][K][E] from bg_currents, in FP64 (matrix cores for K = 24 and 120).
+ * For n = 8 (K = 720) C is held as its first row only, C_st = C_{0, r(s,t)}
+ * with r(s,t) the ordering t after renaming gluons 2..n-1 so that s becomes
+ * the identity (the colour factor is invariant under renaming summed colour
+ * indices); the entries are rebuilt on the fly from K doubles, not the K^2 of
+ * the full matrix.  n = 8 needs context workspace of 96 bytes per event
+ * (allocated on first use of a size, with a device synchronisation).
+ * If accumulate != 0 the result is added to me2 instead of stored.  n in [4, 8]. */
 int bg_color_contract(bg_context* ctx, int n, int64_t n_events, const double* amp,
                       double* me2, int accumulate, void* stream);
 
@@ -148,11 +156,14 @@ typedef struct bg_request {
 } bg_request;
 
 /* |M|^2 per event.  COBG: colour-summed (eq. color_summed_analytic), for one
- * helicity per event or summed over helicities (hel NULL); the recursion and
- * the colour sum run in one kernel and the partial amplitudes never reach
- * device memory outside a small per-block scratch (FP64 colour sum in VALU;
- * bg_currents + bg_color_contract give the same quantity through the
- * matrix-core contraction with the amplitudes exposed).  CDBG: |A|^2 of the
+ * helicity per event or summed over helicities (hel NULL); for n <= 7 the
+ * recursion and the colour sum run in one kernel and the partial amplitudes
+ * never reach device memory outside a small per-block scratch (FP64 colour
+ * sum in VALU; bg_currents + bg_color_contract give the same quantity
+ * through the matrix-core contraction with the amplitudes exposed).  For
+ * n = 8 (BG_PREC_FP64 only, BG_EUNSUPPORTED otherwise) it runs as those two
+ * calls over chunks of 2^17 events, once per helicity configuration
+ * (accumulated) when hel is NULL, with 1.5 GB of context workspace.  CDBG: |A|^2 of the
  * colour-flow amplitude of the given assignment (eq. color_decomposition_colorflow
  * via eq. color_dressed_currents); assignments without a closed colour chain
  * give exactly 0.  May allocate context workspace on first use of a size. */
@@ -167,8 +178,9 @@ int bg_me2(bg_context* ctx, const bg_request* req, void* stream);
  * that each GPU holds until the process ends; its address is looked up once
  * per device when the first context on it is created, and the colour
  * matrices it needs are uploaded then.  The call itself calls no hipMalloc
- * or hipFree.  Modes: BG_MODE_COBG, BG_MODE_CDBG, BG_MODE_AUTO, BG_MODE_LC
- * (BG_MODE_COMC needs growing buffers: BG_EUNSUPPORTED).  At most
+ * or hipFree.  Modes: BG_MODE_COBG (n <= 7), BG_MODE_CDBG, BG_MODE_AUTO,
+ * BG_MODE_LC (BG_MODE_COMC and COBG at n = 8 need growing buffers:
+ * BG_EUNSUPPORTED).  At most
  * BG_NOALLOC_MAX_EVENTS events (BG_ERANGE beyond).  Every call on a GPU
  * shares that GPU's array, whatever its context: calls that overlap in time
  * on one GPU (other streams, other contexts, other host threads) race and

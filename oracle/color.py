@@ -106,7 +106,17 @@ def color_matrix(n, nc=NC, relabel=None):
                 C[i, j] = C[j, i] = color_entry(n, perms[i], perms[j], nc)
         return C
     ident = perms[0]
-    row = {p: color_entry(n, ident, p, nc) for p in perms}
+    return color_matrix_from_row0(n, [color_entry(n, ident, p, nc) for p in perms])
+
+
+def color_matrix_from_row0(n, row0):
+    """C(n) [K, K] from its first row (sigma = identity), by renaming the
+    summed colour labels: C_{sigma sigma'} = C_{id, pi(sigma')} with pi the
+    label map taking sigma to the identity."""
+    perms = middle_permutations(n)
+    ident = perms[0]
+    row = {p: int(v) for p, v in zip(perms, row0)}
+    C = np.zeros((len(perms), len(perms)), dtype=np.int64)
     for i, s in enumerate(perms):
         pi = {lab: ident[pos] for pos, lab in enumerate(s)}
         for j, t in enumerate(perms):

@@ -100,12 +100,15 @@ def colour_matrix(n):
     return out
 
 
-def currents(mom, hel, precision="fp64", ctx=None):
+def currents(mom, hel, precision="fp64", ctx=None, out=None):
     """Partial amplitudes A(1, sigma, n): float64 [2, K, E] (real, imaginary planes)."""
     n, E = _check_mom(mom)
     _check_i8(hel, (n, E), "hel")
     ctx = ctx or default_context(mom.device.index)
-    amp = torch.empty((2, num_orderings(n), E), dtype=torch.float64, device=mom.device)
+    shape = (2, num_orderings(n), E)
+    amp = out if out is not None else torch.empty(shape, dtype=torch.float64, device=mom.device)
+    if not (amp.is_cuda and amp.dtype == torch.float64 and tuple(amp.shape) == shape and amp.is_contiguous()):
+        raise ValueError(f"out must be a contiguous CUDA float64 tensor {shape}")
     check(lib().bg_currents(ctx.handle, n, E, _ptr(mom), _ptr(hel), _PREC[precision], _ptr(amp),
                             _stream(mom.device)), "bg_currents")
     return amp

@@ -29,7 +29,7 @@ COMMON = [
 
 SOURCES = ["bg_api.cpp", "colour_matrix.cpp", "cobg_pair.hip", "cobg_adj.hip", "cdbg.hip",
            "contract.hip", "batch.hip", "rambo.hip", "comc.hip", "cdmc.hip", "util.hip",
-           "noalloc.hip"]
+           "noalloc.hip", "full_colour.hip"]
 
 
 def _compile(src, extra):

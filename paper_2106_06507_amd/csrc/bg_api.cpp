@@ -18,6 +18,7 @@
 
 namespace bg {
 int64_t colour_matrix(int n, double* C);
+int64_t colour_matrix_row0(int n, double* row);
 }
 
 namespace {
@@ -56,11 +57,14 @@ struct bg_context {
   unsigned* cws = nullptr;                   // colour-dressed workspace (counters + event list)
   size_t cws_bytes = 0;
   double* C_dev[BG_N_MAX + 1] = {};          // K x K colour matrix per n (lazy)
-  double* Cpad_dev[BG_N_MAX + 1] = {};       // KP x KP zero-padded copy for the matrix-core path
   double* Cb_dev[BG_N_MAX + 1] = {};         // doubled lower triangle in row blocks (fused path)
-  int KP[BG_N_MAX + 1] = {};
+  float* row0_dev[BG_N_MAX + 1] = {};        // n = 8: row 0 of C (relabelled storage)
+  unsigned char* labels_dev[BG_N_MAX + 1] = {};  // n = 8: [K][n-2] middle gluons per ordering
+  unsigned char* pos_dev[BG_N_MAX + 1] = {};     // n = 8: [K][n-2] position of each label
   double* ws = nullptr;                      // workspace (partial amplitudes)
   size_t ws_bytes = 0;
+  double* part = nullptr;                    // n = 8 colour sum: per-row-block partial sums
+  size_t part_bytes = 0;
   uint8_t* perms_dev[BG_N_MAX + 1] = {};     // [K][n-2] middle gluons of each ordering (gradient)
   double* scratch = nullptr;                 // per-block scratch of the fused and batch kernels
   size_t scratch_bytes = 0;
@@ -180,33 +184,71 @@ int ensure_colour(bg_context* ctx, int n) {
     int st = upload(row_blocked_lower(C, (int)K), &ctx->Cb_dev[n], "colour matrix (row blocks)");
     if (st) return st;
   }
-  int KP = (int)((K + 15) / 16 * 16);
-  std::vector<double> Cp((size_t)KP * KP, 0.0);
-  for (int64_t i = 0; i < K; ++i)
-    for (int64_t j = 0; j < K; ++j) Cp[(size_t)(i * KP + j)] = C[(size_t)(i * K + j)];
-  double* d = nullptr;
-  double* dp = nullptr;
-  int st = hip_status(hipMalloc(&d, sizeof(double) * K * K), "hipMalloc(C)");
+  int st = upload(C, &ctx->C_dev[n], "colour matrix");
   if (st) return st;
-  st = hip_status(hipMalloc(&dp, sizeof(double) * KP * KP), "hipMalloc(Cpad)");
-  if (st) {
-    (void)hipFree(d);
-    return st;
-  }
-  st = hip_status(hipMemcpy(d, C.data(), sizeof(double) * K * K, hipMemcpyHostToDevice),
-                  "hipMemcpy(C)");
-  if (!st)
-    st = hip_status(hipMemcpy(dp, Cp.data(), sizeof(double) * KP * KP, hipMemcpyHostToDevice),
-                    "hipMemcpy(Cpad)");
-  if (st) {
-    (void)hipFree(d);
-    (void)hipFree(dp);
-    return st;
-  }
-  ctx->C_dev[n] = d;
-  ctx->Cpad_dev[n] = dp;
-  ctx->KP[n] = KP;
   BG_LOG("colour matrix n=%d K=%lld uploaded", n, (long long)K);
+  return BG_OK;
+}
+
+// Per-row-block partial sums of the n = 8 colour sum (grown with a device
+// synchronisation, like the other workspaces).
+int ensure_part(bg_context* ctx, int64_t E) {
+  const size_t bytes = sizeof(double) * (size_t)bg::relabel_row_blocks(8) * (size_t)E;
+  if (ctx->part_bytes >= bytes) return BG_OK;
+  if (ctx->part) {
+    int st = hip_status(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    if (st) return st;
+    (void)hipFree(ctx->part);
+    ctx->part = nullptr;
+    ctx->part_bytes = 0;
+  }
+  int st = hip_status(hipMalloc(&ctx->part, bytes), "hipMalloc(colour sum partials)");
+  if (st) return st;
+  ctx->part_bytes = bytes;
+  return BG_OK;
+}
+
+// Relabelled storage of C(n) for n = 8 (K = 720): row 0 and the orderings
+// (labels and, per ordering, the position of each label), K (1 + 2 (n-2))
+// numbers instead of K^2.
+int ensure_relabel(bg_context* ctx, int n) {
+  if (ctx->row0_dev[n]) return BG_OK;
+  const int k = n - 2;
+  const int64_t K = bg::factorial(k);
+  std::vector<double> row((size_t)K);
+  bg::colour_matrix_row0(n, row.data());
+  std::vector<float> rowf(row.begin(), row.end());  // integers below 2^24: exact
+  std::vector<unsigned char> labels((size_t)(K * k)), pos((size_t)(K * k));
+  std::vector<int> p(k);
+  for (int i = 0; i < k; ++i) p[i] = i + 1;
+  for (int64_t s = 0; s < K; ++s) {
+    for (int i = 0; i < k; ++i) {
+      labels[(size_t)(s * k + i)] = (unsigned char)p[i];
+      pos[(size_t)(s * k + p[i] - 1)] = (unsigned char)i;
+    }
+    std::next_permutation(p.begin(), p.end());
+  }
+  float* r = nullptr;
+  unsigned char* lb = nullptr;
+  unsigned char* ps = nullptr;
+  int st = hip_status(hipMalloc(&r, sizeof(float) * K), "hipMalloc(row0)");
+  if (!st) st = hip_status(hipMalloc(&lb, labels.size()), "hipMalloc(labels)");
+  if (!st) st = hip_status(hipMalloc(&ps, pos.size()), "hipMalloc(positions)");
+  if (!st) st = hip_status(hipMemcpy(r, rowf.data(), sizeof(float) * K, hipMemcpyHostToDevice),
+                           "hipMemcpy(row0)");
+  if (!st) st = hip_status(hipMemcpy(lb, labels.data(), labels.size(), hipMemcpyHostToDevice),
+                           "hipMemcpy(labels)");
+  if (!st) st = hip_status(hipMemcpy(ps, pos.data(), pos.size(), hipMemcpyHostToDevice),
+                           "hipMemcpy(positions)");
+  if (st) {
+    if (r) (void)hipFree(r);
+    if (lb) (void)hipFree(lb);
+    if (ps) (void)hipFree(ps);
+    return st;
+  }
+  ctx->row0_dev[n] = r;
+  ctx->labels_dev[n] = lb;
+  ctx->pos_dev[n] = ps;
   return BG_OK;
 }
 
@@ -416,16 +458,27 @@ int check_events(int n, int64_t E) {
   return BG_OK;
 }
 
+// part: workspace of relabel_row_blocks(8) x E doubles for n = 8 (may be null
+// for n <= 7).
 int contract_dispatch(bg_context* ctx, int n, int64_t E, const double* amp, double* me2,
-                      int accumulate, hipStream_t stream) {
+                      int accumulate, hipStream_t stream, double* part = nullptr) {
+  if (n == 8) {
+    int st = ensure_relabel(ctx, n);
+    if (st) return st;
+    return launch_status(bg::relabel_contract(n, E, amp, ctx->row0_dev[n], ctx->labels_dev[n],
+                                              ctx->pos_dev[n], part, me2, accumulate, stream));
+  }
   int st = ensure_colour(ctx, n);
   if (st) return st;
   const int K = (int)bg::factorial(n - 2);
-  if (ctx->KP[n] == 32)
-    return launch_status(
-        bg::contract_mfma(K, E, amp, ctx->Cpad_dev[n], ctx->KP[n], me2, accumulate, stream));
+  if (K == 24 || K == 120)
+    return launch_status(bg::contract_mfma(K, E, amp, ctx->C_dev[n], me2, accumulate, stream));
   return launch_status(bg::contract_valu(K, E, amp, ctx->C_dev[n], me2, accumulate, stream));
 }
+
+// Events per chunk of the two-stage colour-ordered path at n = 8 (amplitudes
+// 11.5 KB per event in FP64 through the context workspace).
+constexpr int64_t kN8Chunk = (int64_t)1 << 17;  // events per two-stage n = 8 chunk (1.5 GB of amplitudes)
 
 }  // namespace
 
@@ -500,11 +553,14 @@ void bg_context_destroy(bg_context* ctx) {
   (void)hipDeviceSynchronize();
   for (int n = 0; n <= BG_N_MAX; ++n) {
     if (ctx->C_dev[n]) (void)hipFree(ctx->C_dev[n]);
-    if (ctx->Cpad_dev[n]) (void)hipFree(ctx->Cpad_dev[n]);
     if (ctx->Cb_dev[n]) (void)hipFree(ctx->Cb_dev[n]);
+    if (ctx->row0_dev[n]) (void)hipFree(ctx->row0_dev[n]);
+    if (ctx->labels_dev[n]) (void)hipFree(ctx->labels_dev[n]);
+    if (ctx->pos_dev[n]) (void)hipFree(ctx->pos_dev[n]);
     if (ctx->perms_dev[n]) (void)hipFree(ctx->perms_dev[n]);
   }
   if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->part) (void)hipFree(ctx->part);
   if (ctx->cws) (void)hipFree(ctx->cws);
   if (ctx->scratch) (void)hipFree(ctx->scratch);
   for (void* p : ctx->retired) (void)hipFree(p);
@@ -523,7 +579,7 @@ void bg_context_destroy(bg_context* ctx) {
 
 int bg_currents(bg_context* ctx, int n, int64_t E, const double* mom, const int8_t* hel,
                 int precision, double* amp, void* stream) {
-  if (!ctx || n < 4 || n > 7) return n > 7 && n <= BG_N_MAX ? BG_EUNSUPPORTED : BG_EINVAL;
+  if (!ctx || n < 4 || n > 8) return n > 8 && n <= BG_N_MAX ? BG_EUNSUPPORTED : BG_EINVAL;
   int st = check_events(n, E);
   if (st) return st;
   if (precision != BG_PREC_FP64 && precision != BG_PREC_FP32_MIXED) return BG_EINVAL;
@@ -537,14 +593,19 @@ int bg_currents(bg_context* ctx, int n, int64_t E, const double* mom, const int8
 
 int bg_color_contract(bg_context* ctx, int n, int64_t E, const double* amp, double* me2,
                       int accumulate, void* stream) {
-  if (!ctx || n < 4 || n > 7) return n > 7 && n <= BG_N_MAX ? BG_EUNSUPPORTED : BG_EINVAL;
+  if (!ctx || n < 4 || n > 8) return n > 8 && n <= BG_N_MAX ? BG_EUNSUPPORTED : BG_EINVAL;
   int st = check_events(n, E);
   if (st) return st;
   if (E == 0) return BG_OK;
   if (!amp || !me2) return BG_EINVAL;
   DeviceGuard g(ctx->device);
   if (!g.ok) return BG_EDEVICE;
-  return contract_dispatch(ctx, n, E, amp, me2, accumulate, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  if (n <= 7) return contract_dispatch(ctx, n, E, amp, me2, accumulate, s);
+  st = ws_acquire(ctx, s);
+  if (!st) st = ensure_part(ctx, E);
+  if (!st) st = contract_dispatch(ctx, n, E, amp, me2, accumulate, s, ctx->part);
+  return ws_release(ctx, s, st);
 }
 
 static int ensure_counters(bg_context* ctx) {
@@ -554,10 +615,39 @@ static int ensure_counters(bg_context* ctx) {
 
 // fixed (may be null): use the static workspace, allocate nothing (the
 // colour matrix must then be uploaded already, see bg_context_create).
+// Colour-ordered n = 8 (K = 720, FP64): amplitudes of a chunk of events into
+// the workspace, then the colour sum through the relabelled storage; over
+// all 2^8 helicity configurations (accumulated) when hel is null.
+static int me2_cobg8(bg_context* ctx, const bg_request* r, hipStream_t stream) {
+  const int n = 8;
+  const int64_t E = r->n_events;
+  const int64_t K = bg::factorial(n - 2);
+  const int64_t chunk = std::min<int64_t>(E, kN8Chunk);
+  int st = ensure_relabel(ctx, n);
+  if (!st) st = ensure_ws(ctx, sizeof(double) * 2 * (size_t)K * (size_t)chunk);
+  if (!st) st = ensure_part(ctx, chunk);
+  if (st) return st;
+  const int nh = r->hel ? 1 : 1 << n;
+  for (int64_t e0 = 0; e0 < E && !st; e0 += chunk) {
+    const int64_t c = std::min<int64_t>(chunk, E - e0);
+    for (int hc = 0; hc < nh && !st; ++hc) {
+      st = launch_status(bg::cobg_amplitudes_range(n, false, E, e0, c, r->mom, r->hel, hc,
+                                                   ctx->ws, stream));
+      if (!st)
+        st = contract_dispatch(ctx, n, c, ctx->ws, r->me2 + e0, hc > 0 ? 1 : 0, stream, ctx->part);
+    }
+  }
+  return st;
+}
+
 static int me2_cobg(bg_context* ctx, const bg_request* r, uint32_t flags, hipStream_t stream,
                     const FixedWs* fixed = nullptr) {
   const int n = r->n;
-  if (n > 7) return BG_EUNSUPPORTED;
+  if (n == 8) {
+    if (fixed || r->precision != BG_PREC_FP64) return BG_EUNSUPPORTED;
+    return me2_cobg8(ctx, r, stream);
+  }
+  if (n > 8) return BG_EUNSUPPORTED;
   const int64_t E = r->n_events;
   if (fixed && !ctx->Cb_dev[n]) return BG_EINVAL;
   int st = ensure_colour(ctx, n);

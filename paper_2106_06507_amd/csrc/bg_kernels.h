@@ -45,6 +45,11 @@ int validate_inputs(int64_t nh, const int8_t* hel, int64_t nc, const int8_t* col
 // (bit n-1-i set means gluon i has helicity -1).
 int cobg_amplitudes(int n, bool fp32, int64_t E, const double* mom, const int8_t* hel, int hconf,
                     double* amp, hipStream_t stream);
+// The same for events e0 .. e0 + count - 1 only, into amp [2][K][count].
+// n in [4, 8].
+int cobg_amplitudes_range(int n, bool fp32, int64_t E, int64_t e0, int64_t count,
+                          const double* mom, const int8_t* hel, int hconf, double* amp,
+                          hipStream_t stream);
 
 // Gradient of sum_st C_st Re(A_s conj(A_t)) scaled by gme2[e] (null = 1),
 // given Y = C A [2][K][E]; perms [K][n-2] lists the middle gluons of each
@@ -61,7 +66,19 @@ int contract_y(int K, int64_t E, const double* amp, const double* C, double* Y, 
 int contract_valu(int K, int64_t E, const double* amp, const double* C, double* me2,
                   int accumulate, hipStream_t stream);
 int mfma_probe(double* out_dev, hipStream_t stream);
-int contract_mfma(int K, int64_t E, const double* amp, const double* C_pad, int KP, double* me2,
+// Colour sum with the colour matrix stored as its first row (n = 8, K = 720;
+// full_colour.hip): row0 [K] (FP32, exact integers), labels [K][n-2] (the
+// middle gluons of each ordering, 1..n-2), pos [K][n-2] (pos[s][x-1] = the
+// position of label x in ordering s), part [relabel_row_blocks(n)][E]
+// workspace; me2 (+)= x^T C x + y^T C y for amp [2][K][E].
+int relabel_row_blocks(int n);
+int relabel_contract(int n, int64_t E, const double* amp, const float* row0,
+                     const unsigned char* labels, const unsigned char* pos, double* part,
+                     double* me2, int accumulate, hipStream_t stream);
+
+// Matrix-core contraction for K in {24, 120} (-2 otherwise); C is K x K
+// row-major on device.
+int contract_mfma(int K, int64_t E, const double* amp, const double* C, double* me2,
                   int accumulate, hipStream_t stream);
 
 // Check of an FP32 pass: events whose rounding-error estimate exceeds tau

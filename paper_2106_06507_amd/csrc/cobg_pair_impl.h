@@ -79,7 +79,8 @@ struct Ctx {
   static constexpr bool kLC = LC;
   static constexpr bool kEst = EST;  // carry the rounding-error bounds (see State::Sb)
   static constexpr bool kDirectP2 = false;  // 1/P^2 from the per-event table
-  static constexpr bool kNoDt = false;      // V4 dot products from the Dt table
+  static constexpr bool kNoDt = N >= 8;     // V4 dot products from the Dt table (n <= 7) or
+                                            // recomputed (n = 8: the table would not fit)
   double lcsum;
   T est_s2, est_a2;   // EST: sum over orderings of Sb(top)^2 and of |A|^2
   const double* mom;
@@ -337,7 +338,6 @@ __device__ __forceinline__ double cobg_pair_body(unsigned char* lds, int64_t E,
                                                int64_t e, bool live, double* __restrict__ amp,
                                                int64_t astride, int64_t acol,
                                                T* amp_raw = nullptr, T* est = nullptr) {
-  constexpr int M = N - 1;
   const int lane = threadIdx.x & 63;  // lane within this wave (the wave owns lds)
   const int pair = lane >> 1;
   const int h = lane & 1;
@@ -433,14 +433,18 @@ __device__ __forceinline__ double cobg_pair_body(unsigned char* lds, int64_t E,
   return c.lcsum;
 }
 
+// Amplitudes of events e0 .. e0 + count - 1 of an [n][4][E] input into
+// amp [2][K][count] (real plane, imaginary plane).
 template <int N, typename T>
-__global__ void __launch_bounds__(64) cobg_pair_kernel(int64_t E, const double* __restrict__ mom,
+__global__ void __launch_bounds__(64) cobg_pair_kernel(int64_t E, int64_t e0, int64_t count,
+                                                      const double* __restrict__ mom,
                                                       const int8_t* __restrict__ hel, int hconf,
                                                       double* __restrict__ amp) {
   extern __shared__ __align__(16) unsigned char bg_pair_lds[];
-  const int64_t e = (int64_t)blockIdx.x * Lds<N>::kPairs + (threadIdx.x >> 1);
-  const bool live = e < E;
-  cobg_pair_body<N, T>(bg_pair_lds, E, mom, hel, hconf, live ? e : E - 1, live, amp, E, e);
+  const int64_t j = (int64_t)blockIdx.x * Lds<N>::kPairs + (threadIdx.x >> 1);
+  const bool live = j < count;
+  cobg_pair_body<N, T>(bg_pair_lds, E, mom, hel, hconf, e0 + (live ? j : count - 1), live, amp,
+                       count, j);
 }
 
 }  // namespace pairk

@@ -133,6 +133,22 @@ int64_t perm_rank(const std::vector<int>& p) {
 
 }  // namespace
 
+// Fills row 0 of C(n) (K entries): the entries C_{id, t} for every ordering t
+// in lexicographic order.  Returns K.
+int64_t colour_matrix_row0(int n, double* row) {
+  const int k = n - 2;
+  std::vector<std::vector<int>> perms;
+  all_perms(k, perms);
+  const int64_t K = (int64_t)perms.size();
+  std::vector<Word> w0, wj;
+  nested_commutator_words(n, perms[0].data(), w0);
+  for (int64_t j = 0; j < K; ++j) {
+    nested_commutator_words(n, perms[j].data(), wj);
+    row[j] = (double)entry(n, w0, wj);
+  }
+  return K;
+}
+
 // Fills C (K x K row-major) for n in [4, 8].  Returns K.
 int64_t colour_matrix(int n, double* C) {
   const int k = n - 2;

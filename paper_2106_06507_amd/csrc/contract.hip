@@ -2,17 +2,25 @@
 // (Section 2.2, eq. color_summed_analytic) in FP64.
 //
 // C is real and symmetric, so with x = Re A and y = Im A the contraction is
-// x^T C x + y^T C y.  For a tile of 64 events the 2x64 vectors form the
-// columns of X (K x 128); Z = C X is a dense FP64 product done on the matrix
-// cores with v_mfma_f64_16x16x4f64, and me2_e = sum_s X_se Z_se + X_s,e+64 Z_s,e+64.
-// K is padded to KP (a multiple of 16) with zero rows/columns of C.
-//
-// Operand layout of v_mfma_f64_16x16x4f64 (wave64, one block): lane l supplies
-// A[l%16][l/16] and B[l/16][l%16].  The accumulator layout is not assumed:
-// the same instruction multiplies X by an identity tile, which places X in
-// exactly the accumulator layout of Z, so the elementwise products X*Z line up
-// whatever the row order.  Only the column of an accumulator element is used
-// (lanes with equal l%16 share a column), and bg_mfma_selftest checks it.
+// x^T C x + y^T C y.  Matrix-core path (K = 24, 120): a wave takes 16
+// consecutive events, the columns of X (one plane at a time), and forms
+// Z = C' X on v_mfma_f64_16x16x4f64.  C' is C in block-triangular form over
+// blocks of 16 rows and columns: the diagonal blocks as they are, the blocks
+// right of the diagonal doubled, those left of it dropped, so that
+// x^T C x = sum over row blocks b of x_b . (C' x)_b by the symmetry of C;
+// row block b runs over the k range from 16 b to K only (K = 24: 6 + 2 k
+// steps of 4 instead of 2 x 6; K = 120: 128 instead of 240).  Operand layout
+// (wave64): lane l supplies A[l%16][l/16] and B[l/16][l%16]; accumulator
+// element r of lane l is D[l/16 + 4 r][l%16] (bg_mfma_layout_probe; the
+// tests assert rows and columns).  The X operands of all K/4 k steps are
+// loaded once from global memory into registers (16 events of one row are
+// 128 contiguous bytes); the k dimension needs no padding.  Lane l holds
+// X rows 4 ks + l/16, which are also the rows of its accumulator elements in
+// row block b (ks = 4 b + r), so x . Z needs no second read.  C' sits in LDS
+// as FP32 (entries are integers below 2^24 in modulus, also when doubled:
+// exact), rows padded with zeros to a multiple of 16 and the row stride odd
+// (K + 1) against bank conflicts.  The four lane groups of a column are
+// added with two cross-lane exchanges.
 #include "bg_kernels.h"
 
 namespace bg {
@@ -42,74 +50,62 @@ __global__ void __launch_bounds__(256) contract_valu_kernel(int K, int64_t E,
   me2[e] = accumulate ? me2[e] + acc : acc;
 }
 
-template <int KP>
-__global__ void __launch_bounds__(64) contract_mfma_kernel(int K, int64_t E,
-                                                          const double* __restrict__ amp,
-                                                          const double* __restrict__ Cp,
-                                                          double* __restrict__ me2,
-                                                          int accumulate) {
-  // X tile in LDS: [KP][128] (columns 0..63 real parts, 64..127 imaginary parts)
-  __shared__ double X[KP][128];
-  const int l = threadIdx.x;
-  const int64_t e0 = (int64_t)blockIdx.x * 64;
-  const int64_t e = e0 + l;
-  const bool live = e < E;
-  for (int s = 0; s < KP; ++s) {
-    double xr = 0.0, xi = 0.0;
-    if (s < K && live) {
-      xr = amp[(int64_t)s * E + e];
-      xi = amp[((int64_t)K + s) * E + e];
-    }
-    X[s][l] = xr;
-    X[s][64 + l] = xi;
+template <int K>
+struct MfmaShape {
+  static constexpr int KS = K / 4;          // k steps of 4
+  static constexpr int RB = (K + 15) / 16;  // row blocks of 16
+  static constexpr int RP = RB * 16;
+  static constexpr int KL = K + 1;          // LDS row stride (odd)
+  static constexpr size_t lds = sizeof(float) * (size_t)RP * KL;
+  static constexpr int kBlock = K <= 32 ? 256 : 768;  // threads per block (K = 120: 3 waves/SIMD)
+};
+
+template <int K>
+__global__ void __launch_bounds__(MfmaShape<K>::kBlock) contract_mfma_kernel(
+    int64_t E, const double* __restrict__ amp, const double* __restrict__ C,
+    double* __restrict__ me2, int accumulate) {
+  using S = MfmaShape<K>;
+  static_assert(K % 4 == 0, "k steps of four");
+  extern __shared__ float bg_contract_c[];  // C' [RP][KL], rows >= K zero
+  for (int i = threadIdx.x; i < S::RP * K; i += S::kBlock) {
+    const int r = i / K, t = i % K;
+    const int br = r >> 4, bt = t >> 4;
+    const float c = r < K ? (float)C[r * K + t] : 0.0f;
+    bg_contract_c[r * S::KL + t] = bt == br ? c : (bt > br ? 2.0f * c : 0.0f);
   }
   __syncthreads();
-
-  const int li = l & 15;  // row of A / column of B and D
-  const int lk = l >> 4;  // k of A and B
-  double part[4] = {0.0, 0.0, 0.0, 0.0};  // per column group (events li + 16 g)
-#pragma unroll 1
-  for (int rt = 0; rt < KP / 16; ++rt) {
-    d4_t acc[8], xd[8];
+  const int l = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int c16 = l & 15, g = l >> 4;
+  const int64_t e = ((int64_t)blockIdx.x * (S::kBlock / 64) + w) * 16 + c16;
+  const bool live = e < E;
+  const int64_t ee = live ? e : E - 1;  // lanes past the end read a valid event, store nothing
+  double bx[S::KS], by[S::KS];
 #pragma unroll
-    for (int ct = 0; ct < 8; ++ct) {
-      acc[ct] = d4_t{0.0, 0.0, 0.0, 0.0};
-      xd[ct] = d4_t{0.0, 0.0, 0.0, 0.0};
+  for (int ks = 0; ks < S::KS; ++ks) {
+    bx[ks] = amp[(int64_t)(4 * ks + g) * E + ee];
+    by[ks] = amp[(int64_t)(K + 4 * ks + g) * E + ee];
+  }
+  double q = 0.0;
+#pragma unroll
+  for (int rb = 0; rb < S::RB; ++rb) {
+    d4_t ax = d4_t{0.0, 0.0, 0.0, 0.0}, ay = d4_t{0.0, 0.0, 0.0, 0.0};
+    const float* crow = bg_contract_c + (16 * rb + c16) * S::KL + g;
+#pragma unroll
+    for (int ks = 4 * rb; ks < S::KS; ++ks) {
+      const double a = (double)crow[4 * ks];
+      ax = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bx[ks], ax, 0, 0, 0);
+      ay = __builtin_amdgcn_mfma_f64_16x16x4f64(a, by[ks], ay, 0, 0, 0);
     }
-#pragma unroll 4
-    for (int ks = 0; ks < KP / 4; ++ks) {
-      const double a = Cp[(rt * 16 + li) * KP + ks * 4 + lk];
+    // element r: row 16 rb + g + 4 r = 4 (4 rb + r) + g, held in bx/by[4 rb + r]
 #pragma unroll
-      for (int ct = 0; ct < 8; ++ct) {
-        const double b = X[ks * 4 + lk][ct * 16 + li];
-        acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[ct], 0, 0, 0);
-      }
-    }
-    // X rows rt*16..rt*16+15 in accumulator layout: I(16x16) x X_tile
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      const double a = (li == ks * 4 + lk) ? 1.0 : 0.0;
-#pragma unroll
-      for (int ct = 0; ct < 8; ++ct) {
-        const double b = X[rt * 16 + ks * 4 + lk][ct * 16 + li];
-        xd[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, xd[ct], 0, 0, 0);
-      }
-    }
-#pragma unroll
-    for (int ct = 0; ct < 8; ++ct) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) part[ct & 3] += xd[ct][r] * acc[ct][r];
+    for (int r = 0; r < 4; ++r) {
+      if (4 * rb + r < S::KS) q += bx[4 * rb + r] * ax[r] + by[4 * rb + r] * ay[r];
     }
   }
-  // reduce over the four row groups (lanes li, li+16, li+32, li+48)
-#pragma unroll
-  for (int g = 0; g < 4; ++g) {
-    part[g] += __shfl_xor(part[g], 16);
-    part[g] += __shfl_xor(part[g], 32);
-  }
-  // lane l writes event l: its column group is l/16 (== lk), column li
-  const double v = part[lk];
-  if (live) me2[e] = accumulate ? me2[e] + v : v;
+  q += __shfl_xor(q, 16);
+  q += __shfl_xor(q, 32);
+  if (g == 0 && live) me2[e] = accumulate ? me2[e] + q : q;
 }
 
 // Layout self-test: D = A x B with A[i][k] = i + 1 + 100 k and B[k][j] =
@@ -170,15 +166,22 @@ int contract_valu(int K, int64_t E, const double* amp, const double* C, double* 
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int contract_mfma(int K, int64_t E, const double* amp, const double* C_pad, int KP, double* me2,
+int contract_mfma(int K, int64_t E, const double* amp, const double* C, double* me2,
                   int accumulate, hipStream_t stream) {
   if (E <= 0) return 0;
-  const unsigned grid = (unsigned)((E + 63) / 64);
-  switch (KP) {
-    case 32:
-      hipLaunchKernelGGL(contract_mfma_kernel<32>, dim3(grid), dim3(64), 0, stream, K, E, amp,
-                         C_pad, me2, accumulate);
-      break;
+  switch (K) {
+#define BG_CASE(KK)                                                                           \
+  case KK: {                                                                                  \
+    using S = MfmaShape<KK>;                                                                  \
+    const int64_t per_block = (S::kBlock / 64) * 16;                                          \
+    const unsigned grid = (unsigned)((E + per_block - 1) / per_block);                        \
+    hipLaunchKernelGGL(contract_mfma_kernel<KK>, dim3(grid), dim3(S::kBlock), S::lds, stream, \
+                       E, amp, C, me2, accumulate);                                           \
+    break;                                                                                    \
+  }
+    BG_CASE(24)
+    BG_CASE(120)
+#undef BG_CASE
     default:
       return -2;
   }

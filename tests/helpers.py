@@ -73,19 +73,31 @@ def fp64_allowance(n, ref, mag):
     return np.maximum(1e-12 * np.abs(ref), 12 * (np.asarray(n) - 2) * U64 * mag)
 
 
-def reference_cobg(mom, hel, with_oracle_fp64=False):
+def reference_cobg(mom, hel, with_oracle_fp64=False, C=None):
     """Colour-summed |M|^2 from the oracle in long double (float64 result)
     and its FP64 magnitude m (see fp64_allowance); optionally also the FP64
     oracle's own result (an independent FP64 evaluation, see
-    fp64_comparable)."""
+    fp64_comparable).  C: the colour matrix, if the caller has it (n = 8:
+    colour_matrix_n8)."""
     from oracle import me2 as ome2
     from oracle.conditioning import me2_cobg_magnitude
     from oracle.numeric import extended
-    ref = ome2.me2_cobg(extended(mom), hel).astype(np.float64)
-    _, mag = me2_cobg_magnitude(mom, hel)
+    ref = ome2.me2_cobg(extended(mom), hel, C=C).astype(np.float64)
+    _, mag = me2_cobg_magnitude(mom, hel, C=C)
     if with_oracle_fp64:
-        return ref, mag, ome2.me2_cobg(mom, hel)
+        return ref, mag, ome2.me2_cobg(mom, hel, C=C)
     return ref, mag
+
+
+def colour_matrix_n8():
+    """C(8) from its stored first row (tests/golden, written by make_golden.py
+    from the oracle, pinned in test_oracle_precision) by the oracle's
+    relabelling; recomputing the row takes about 30 s."""
+    import os
+    from oracle.color import color_matrix_from_row0
+    row0 = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "colour_matrix_n8_row0.txt"),
+                      dtype=np.int64)
+    return color_matrix_from_row0(8, row0)
 
 
 def fp64_comparable(err_gpu, err_oracle, factor=10.0, floor=1e-15):

@@ -22,8 +22,8 @@ import pytest
 from bg_inputs import make_events, workload
 from oracle import cobg as ocobg
 from oracle import me2 as ome2
-from tests.helpers import (fp64_allowance, fp64_comparable, mhv_helicities, nonvanishing,
-                           reference_cobg)
+from tests.helpers import (colour_matrix_n8, fp64_allowance, fp64_comparable, mhv_helicities,
+                           nonvanishing, reference_cobg)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -70,10 +70,10 @@ def test_amplitudes_fp64_match_oracle(api, n):
     assert np.max(np.abs(got[:, ~nz]), initial=0.0) < 1e-10 * typical
 
 
-def _check_sampled(got, mom, hel, precision):
+def _check_sampled(got, mom, hel, precision, C=None):
     """Per-event bars against the long-double reference (module docstring)."""
     n = mom.shape[0]
-    ref, mag, o64 = reference_cobg(mom, hel, with_oracle_fp64=True)
+    ref, mag, o64 = reference_cobg(mom, hel, with_oracle_fp64=True, C=C)
     nz = nonvanishing(hel)
     d = np.abs(got - ref)
     rel = (d / np.abs(ref))[nz]
@@ -155,9 +155,10 @@ def test_fused_equals_two_stage(api, n, precision):
         assert np.median(rel) < 1e-6 and rel.max() < 1e-4
 
 
-@pytest.mark.parametrize("n", [5, 6])
+@pytest.mark.parametrize("n", [5, 6, 7])
 def test_contraction_matches_oracle(api, n):
-    """bg_color_contract on oracle amplitudes (matrix cores at n = 6)."""
+    """bg_color_contract on oracle amplitudes (VALU at n = 5, matrix cores at
+    n = 6 and 7); 300 events: several event tiles and a ragged tail."""
     E = 300
     mom, hel = _events(n, E, 3200 + n)
     hel = np.where(nonvanishing(hel)[None, :], hel, np.array([[-1], [-1]] + [[1]] * (n - 2)))
@@ -233,3 +234,91 @@ def test_single_event(api, n):
         for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
             got = api.me2(dm, None if h is None else _dev(h), precision=prec).cpu().numpy()
             assert abs(got[0] - ref[0]) <= tol * abs(ref[0]), (prec, h is None, got[0], ref[0])
+
+
+# ---------------------------------------------------------------------------
+# full colour at n = 8 (K = 720, colour matrix held as its first row)
+
+@pytest.fixture(scope="module")
+def c8():
+    return colour_matrix_n8()
+
+
+def test_full_colour_n8_match_oracle(api, c8):
+    """n = 8, one helicity per event, 40 events (two blocks of the recursion
+    with a ragged tail; one full and one partial event block of the
+    contraction): bg_currents against the oracle's 720 amplitudes, bg_me2
+    (recursion, then the colour sum through the relabelled first row of C)
+    against the long-double reference with the per-event bars of the module
+    docstring, and bg_color_contract on the oracle's own amplitudes against
+    the oracle's contraction with the full C(8)."""
+    n, E = 8, 40
+    mom, hel = _events(n, E, 3800)
+    dm, dh = _dev(mom), _dev(hel)
+    nz = nonvanishing(hel)
+    _say(f"bg_currents fp64 n=8 E={E}")
+    amp = api.currents(dm, dh, "fp64").cpu().numpy()
+    A = ocobg.partial_amplitudes(mom, hel)
+    scale = np.max(np.abs(A), axis=0)
+    err = np.max(np.abs(amp[0] + 1j * amp[1] - A), axis=0) / scale
+    _say(f"  amplitudes: max err / max |A| {np.max(err[nz]):.2e}")
+    assert np.max(err[nz]) < 1e-11
+    _say(f"bg_me2 cobg fp64 n=8 E={E}")
+    got = api.me2(dm, dh, mode="cobg").cpu().numpy()
+    ref = _check_sampled(got, mom, hel, "fp64", C=c8)
+    assert np.max(np.abs(got[~nz]), initial=0.0) < 1e-20 * np.median(np.abs(ref[nz]))
+    _say(f"bg_color_contract n=8 E={E} on oracle amplitudes")
+    con = api.color_contract(_dev(np.stack([A.real, A.imag])), n).cpu().numpy()
+    refc = ome2.contract(A, c8)
+    rel = np.abs(con - refc)[nz] / np.abs(refc[nz])
+    _say(f"  contraction rel err max {rel.max():.2e}")
+    assert rel.max() < 1e-12
+    out = _dev(np.full(E, 2.0))
+    api.color_contract(_dev(np.stack([A.real, A.imag])), n, out=out, accumulate=True)
+    assert np.array_equal(out.cpu().numpy(), 2.0 + con)
+
+
+def test_full_colour_n8_chunks_sampled(api, c8):
+    """2^17 + 2^16 + 37 events: two chunks of the n = 8 two-stage path (the
+    second one ragged), 8 sampled non-vanishing events against the oracle
+    with the per-event bars; the two-stage calls give the same values."""
+    n, E = 8, (1 << 17) + (1 << 16) + 37
+    mom, hel = _events(n, E, 3810)
+    dm, dh = _dev(mom), _dev(hel)
+    _say(f"bg_me2 cobg fp64 n=8 E={E}")
+    got = api.me2(dm, dh, mode="cobg").cpu().numpy()
+    assert np.all(np.isfinite(got))
+    ok = np.nonzero(nonvanishing(hel))[0]
+    idx = np.sort(np.concatenate([np.random.default_rng(12).choice(ok[ok < (1 << 17)], 4, replace=False),
+                                  np.random.default_rng(13).choice(ok[ok >= (1 << 17)], 4, replace=False)]))
+    _check_sampled(got[idx], np.ascontiguousarray(mom[:, :, idx]), np.ascontiguousarray(hel[:, idx]),
+                   "fp64", C=c8)
+    head = slice(E - 3000, E)
+    m2, h2 = _dev(np.ascontiguousarray(mom[:, :, head])), _dev(np.ascontiguousarray(hel[:, head]))
+    two = api.color_contract(api.currents(m2, h2), n).cpu().numpy()
+    assert np.array_equal(two, got[head])
+
+
+def test_full_colour_n8_helicity_sum(api):
+    """hel = NULL at n = 8 sums the 256 configurations (accumulated through
+    the contraction); equal to the sum of the per-configuration results
+    within rounding of the different summation order; configurations are
+    checked against the oracle above."""
+    n, E = 8, 5
+    mom, _ = _events(n, E, 3820)
+    dm = _dev(mom)
+    _say(f"bg_me2 cobg n=8 helicity sum E={E}")
+    tot = api.me2(dm, None, mode="cobg").cpu().numpy()
+    acc = np.zeros(E)
+    for h in range(256):
+        hel = np.array([[1 if (h >> (n - 1 - i)) & 1 == 0 else -1] * E for i in range(n)], dtype=np.int8)
+        acc += api.me2(dm, _dev(hel), mode="cobg").cpu().numpy()
+    assert np.max(np.abs(tot - acc) / acc) < 1e-12
+
+
+def test_full_colour_n8_fp32_unsupported(api):
+    """Colour-ordered n = 8 runs in FP64 only (the FP32 recursion has no
+    accuracy check there): refused, not silently degraded."""
+    mom, hel = _events(8, 4, 3830)
+    with pytest.raises(RuntimeError):
+        api.me2(_dev(mom), _dev(hel), mode="cobg", precision="fp32")

@@ -10,8 +10,9 @@ pytestmark = pytest.mark.gpu
 
 def test_mfma_f64_accumulator_columns():
     """Every accumulator element of v_mfma_f64_16x16x4f64 decodes to a unique
-    (row, column) of A x B under the assumed A/B lane layout, and its column is
-    lane % 16 (the only accumulator property the contraction uses)."""
+    (row, column) of A x B under the assumed A/B lane layout: element r of lane
+    l is D[l / 16 + 4 r][l % 16], the layout the contraction kernels read
+    their accumulators in."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2106_06507_amd import api
@@ -25,11 +26,13 @@ def test_mfma_f64_accumulator_columns():
     lookup = {float(D[i, j]): (i, j) for i in range(16) for j in range(16)}
     seen = set()
     rows = np.zeros((64, 4), dtype=int)
+    cols = np.zeros((64, 4), dtype=int)
     for l in range(64):
         for r in range(4):
-            i, j = lookup[float(out[4 * l + r])]
-            assert j == l % 16
-            rows[l, r] = i
-            seen.add((i, j))
-    assert len(seen) == 256
+            rows[l, r], cols[l, r] = lookup[float(out[4 * l + r])]
+            seen.add((rows[l, r], cols[l, r]))
     print("accumulator rows by (lane group, register):", rows[::16].tolist(), flush=True)
+    assert len(seen) == 256
+    lanes = np.arange(64)[:, None]
+    assert np.array_equal(cols, np.broadcast_to(lanes % 16, (64, 4)))
+    assert np.array_equal(rows, lanes // 16 + 4 * np.arange(4)[None, :])

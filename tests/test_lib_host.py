@@ -50,6 +50,10 @@ def test_colour_matrix_n8_sampled_entries():
     assert lib().bg_color_matrix(n, out.ctypes.data_as(ctypes.c_void_p), K * K) == 0
     C = out.reshape(K, K)
     assert np.array_equal(C, C.T)
+    import os
+    row0 = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "colour_matrix_n8_row0.txt"),
+                      dtype=np.int64)
+    assert np.array_equal(C, color.color_matrix_from_row0(n, row0).astype(np.float64))
     perms = color.middle_permutations(n)
     rng = np.random.default_rng(8)
     for _ in range(6):

@@ -204,3 +204,19 @@ def test_golden_colour_matrix_n7_row0():
     stored = np.loadtxt(f"{GOLDEN}/colour_matrix_n7_row0.txt", dtype=np.int64, ndmin=2)
     assert np.array_equal(stored[0], color.color_matrix(7)[0])
     assert stored[0, 0] == 6 ** 5 * 8
+
+
+def test_golden_colour_matrix_n8_row0():
+    """The stored first row of C(8) (720 entries, about 30 s to recompute)
+    on 40 sampled entries against the oracle's trace words; the diagonal
+    value; and the matrix filled from it by relabelling is symmetric, as
+    C(8) must be (a wrong relabelling map or a wrong stored entry breaks
+    the symmetry)."""
+    stored = np.loadtxt(f"{GOLDEN}/colour_matrix_n8_row0.txt", dtype=np.int64, ndmin=2)[0]
+    perms = color.middle_permutations(8)
+    assert stored.shape == (720,) and stored[0] == 6 ** 6 * 8
+    for j in np.random.default_rng(88).choice(720, 40, replace=False):
+        assert stored[j] == color.color_entry(8, perms[0], perms[j])
+    C = color.color_matrix_from_row0(8, stored)
+    assert np.array_equal(C, C.T)
+    assert np.all(np.diag(C) == stored[0])

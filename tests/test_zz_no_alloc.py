@@ -80,6 +80,10 @@ def test_noalloc_refuses(api):
     stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     r = api._request(mom, hel, col, "comc", "fp64", out)
     assert lib().bg_me2_noalloc(ctx.handle, ctypes.byref(r), stream) == BG_EUNSUPPORTED
+    # colour-ordered n = 8 runs through a chunk workspace that grows
+    ev8 = make_events(8, 16, seed=9402, cuts=True, sample_hel=True)
+    r8 = api._request(_dev(ev8["mom"]), _dev(ev8["hel"]), None, "cobg", "fp64", out)
+    assert lib().bg_me2_noalloc(ctx.handle, ctypes.byref(r8), stream) == BG_EUNSUPPORTED
     # beyond the maximum: refused before anything is read or launched
     big = bg_request()
     big.n, big.mode, big.precision, big.flags = 6, 0, 0, 0
