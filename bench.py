@@ -497,10 +497,16 @@ def section_per_n(args, api, wm, torch):
             buf = torch.empty(E, dtype=torch.float64, device="cuda")
             lms = time_events(lambda: api.me2(mom, hel, mode="lc", precision="fp64", out=buf),
                               steps, 1)
+            lc64 = buf.cpu().numpy()
             row["leading_colour_fp64"] = {
                 "events_per_s": E / (lms * 1e-3), "ms": lms,
-                "rel_dev_from_full_colour": rel_err_stats(buf.cpu().numpy()[keep],
-                                                          res["fp64"][keep])}
+                "rel_dev_from_full_colour": rel_err_stats(lc64[keep], res["fp64"][keep])}
+            buf32 = torch.empty(E, dtype=torch.float64, device="cuda")
+            lms32 = time_events(lambda: api.me2(mom, hel, mode="lc", precision="fp32", out=buf32),
+                                steps, 1)
+            row["leading_colour_fp32_checked"] = {
+                "events_per_s": E / (lms32 * 1e-3), "ms": lms32,
+                "rel_err_vs_fp64": rel_err_stats(buf32.cpu().numpy()[keep], lc64[keep])}
         if args.continuous:
             Ec = min(E, 1 << (22 - n))
             phi_c, eta_c = api.generate_continuous(n, Ec, 2106065070 + 60 + n)

@@ -198,20 +198,24 @@ int bg_me2_noalloc(bg_context* ctx, const bg_request* req, void* stream);
  * |p^0| over the gluons, the remaining terms being the four-gluon vertex
  * (colour-ordered, Section 2.3 eq. cobg) or the tensor couplings
  * (colour-dressed, eq. color_dressed_currents) term by term.  An event whose
- *   est = sum_sigma S_sigma^2 / sum_sigma |A_sigma|^2   (colour-ordered), or
- *   est = S^2 / |A|^2                                    (colour-dressed)
+ *   est = sum_sigma S_sigma^2 / sum_sigma |A_sigma|^2   (colour-ordered, and
+ *         leading colour over its (n-1)! orderings),
+ *   est = S^2 / |A|^2                                    (colour-dressed), or
+ *   est = (sum_sigma S_sigma)^2 / |A|^2                  (colour-sampled
+ *         colour-ordered: A the sum of the closing orderings' amplitudes)
  * exceeds tau(mode, n) -- its amplitudes cancel strongly, so FP32 rounding of
  * the inputs and of the recursion is amplified -- is listed on the device and
  * evaluated again in FP64 by a second kernel on the same stream (no host
- * synchronisation), which overwrites its me2.  Helicity configurations whose
+ * synchronisation), which overwrites its me2 (BG_MODE_COMC: the listed
+ * event's orderings are evaluated again and summed again).  Helicity configurations whose
  * tree amplitude vanishes identically (fewer than two gluons of either
  * helicity) are never listed.  The default tau are chosen so that the
  * per-event relative error of me2 against FP64 stays below 1e-5 for 99% of
  * the sampled-helicity (and sampled-flow) events of the RAMBO workloads.
- * mode: BG_MODE_COBG (n in [4, 7]) or BG_MODE_CDBG (n in [4, 9]), the bg_me2
- * modes the check applies to.  tau = 0 lists every non-vanishing event (then
- * me2 equals the FP64 path bit for bit); tau = +inf lists none (as
- * BG_FLAG_FP32_UNCHECKED).  Host only; BG_EINVAL for another mode or n, or
+ * mode: BG_MODE_COBG or BG_MODE_LC (n in [4, 7]), BG_MODE_CDBG or
+ * BG_MODE_COMC (n in [4, 9]), the bg_me2 modes the check applies to.  tau = 0 lists every
+ * non-vanishing event (then me2 equals the FP64 path bit for bit); tau =
+ * +inf lists none (as BG_FLAG_FP32_UNCHECKED).  Host only; BG_EINVAL for another mode or n, or
  * tau < 0 or NaN. */
 int bg_fp32_check_set(bg_context* ctx, int mode, int n, float tau);
 int bg_fp32_check_get(bg_context* ctx, int mode, int n, float* tau);

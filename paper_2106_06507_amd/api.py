@@ -161,7 +161,7 @@ def me2(mom, hel=None, col=None, mode="cobg", precision="fp64", out=None, ctx=No
 
 
 def fp32_check(n, tau=None, mode="cobg", ctx=None):
-    """Threshold of the FP32 accuracy check of `mode` ("cobg" or "cdbg") at n
+    """Threshold of the FP32 accuracy check of `mode` ("cobg", "cdbg", "comc" or "lc") at n
     (bg_fp32_check_get/set): returns the current value; sets it first if tau
     is given."""
     ctx = ctx or default_context()

@@ -69,23 +69,64 @@ __global__ void __launch_bounds__(64) cobg_fix_kernel(int64_t E, const double* _
   }
 }
 
-// Leading colour, one 32-event tile per block.
-template <int N, typename T>
+// Leading colour, one 32-event tile per block (CHK: FP32 pass that lists
+// ill-conditioned events, see lc_tile).
+template <int N, typename T, bool CHK = false>
 __global__ void __launch_bounds__(64) lc_kernel(int64_t E, const double* __restrict__ mom,
                                                const int8_t* __restrict__ hel,
-                                               double* __restrict__ me2) {
+                                               double* __restrict__ me2, TileCheck chk) {
   extern __shared__ __align__(16) unsigned char bg_lc_lds[];
   const int64_t first = (int64_t)blockIdx.x * kTileEvents;
   const int64_t left = E - first;
-  lc_tile<N, T>(bg_lc_lds, E, mom, hel, me2, first, (int)(left < kTileEvents ? left : kTileEvents));
+  lc_tile<N, T, CHK>(bg_lc_lds, E, mom, hel, me2, first,
+                     (int)(left < kTileEvents ? left : kTileEvents), chk);
+}
+
+// FP64 leading colour of the listed events: persistent blocks stride over
+// 32-event tiles of the list, whose length is read on the device.
+template <int N>
+__global__ void __launch_bounds__(64) lc_fix_kernel(int64_t E, const double* __restrict__ mom,
+                                                   const int8_t* __restrict__ hel,
+                                                   const unsigned* __restrict__ count,
+                                                   const unsigned* __restrict__ list,
+                                                   double* __restrict__ me2) {
+  extern __shared__ __align__(16) unsigned char bg_lc_lds[];
+  const unsigned cnt = *count;
+  for (unsigned first = blockIdx.x * kTileEvents; first < cnt; first += gridDim.x * kTileEvents) {
+    const unsigned left = cnt - first;
+    lc_tile<N, double, false, true>(bg_lc_lds, E, mom, hel, me2, first,
+                                    (int)(left < (unsigned)kTileEvents ? left : (unsigned)kTileEvents),
+                                    TileCheck{}, list);
+  }
 }
 
 template <int N, typename T>
-int lc_launch(int64_t E, const double* mom, const int8_t* hel, double* me2, hipStream_t stream) {
+int lc_launch(int64_t E, const double* mom, const int8_t* hel, double* me2, const CheckArgs* chk,
+              int fix_grid, hipStream_t stream) {
   const unsigned tiles = (unsigned)((E + kTileEvents - 1) / kTileEvents);
-  hipLaunchKernelGGL((lc_kernel<N, T>), dim3(tiles), dim3(64),
-                     (pairk::Lds<N, true>::template bytes<T>()), stream, E, mom, hel, me2);
+  if (!chk) {
+    hipLaunchKernelGGL((lc_kernel<N, T>), dim3(tiles), dim3(64),
+                       (pairk::Lds<N, true>::template bytes<T>()), stream, E, mom, hel, me2,
+                       TileCheck{});
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+  }
+  hipLaunchKernelGGL((lc_kernel<N, float, true>), dim3(tiles), dim3(64),
+                     (pairk::Lds<N, true>::template bytes<float>()), stream, E, mom, hel, me2,
+                     TileCheck{chk->tau, chk->count, chk->list});
+  hipLaunchKernelGGL((lc_fix_kernel<N>), dim3((unsigned)fix_grid), dim3(64),
+                     (pairk::Lds<N, true>::template bytes<double>()), stream, E, mom, hel,
+                     chk->count, chk->list, me2);
   return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int N>
+int lc_fix_occupancy() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lc_fix_kernel<N>, 64,
+                                                   pairk::Lds<N, true>::template bytes<double>()) !=
+      hipSuccess)
+    return -1;
+  return nb;
 }
 
 __global__ void zero_counter_kernel(unsigned* c) {
@@ -310,13 +351,29 @@ int fused_occupancy(bool hsum) {
 }  // namespace fusedk
 
 int lc_me2(int n, bool fp32, int64_t E, const double* mom, const int8_t* hel, double* me2,
-           hipStream_t stream) {
+           const CheckArgs* chk, int fix_grid, hipStream_t stream) {
   if (E <= 0) return 0;
+  if (chk && !fp32) return -2;
   switch (n) {
-    case 4: return fp32 ? fusedk::lc_launch<4, float>(E, mom, hel, me2, stream) : fusedk::lc_launch<4, double>(E, mom, hel, me2, stream);
-    case 5: return fp32 ? fusedk::lc_launch<5, float>(E, mom, hel, me2, stream) : fusedk::lc_launch<5, double>(E, mom, hel, me2, stream);
-    case 6: return fp32 ? fusedk::lc_launch<6, float>(E, mom, hel, me2, stream) : fusedk::lc_launch<6, double>(E, mom, hel, me2, stream);
-    case 7: return fp32 ? fusedk::lc_launch<7, float>(E, mom, hel, me2, stream) : fusedk::lc_launch<7, double>(E, mom, hel, me2, stream);
+#define BG_CASE(NN)                                                                           \
+  case NN:                                                                                    \
+    return fp32 ? fusedk::lc_launch<NN, float>(E, mom, hel, me2, chk, fix_grid, stream)       \
+                : fusedk::lc_launch<NN, double>(E, mom, hel, me2, nullptr, 0, stream);
+    BG_CASE(4)
+    BG_CASE(5)
+    BG_CASE(6)
+    BG_CASE(7)
+#undef BG_CASE
+    default: return -2;
+  }
+}
+
+int lc_fix_blocks_per_cu(int n) {
+  switch (n) {
+    case 4: return fusedk::lc_fix_occupancy<4>();
+    case 5: return fusedk::lc_fix_occupancy<5>();
+    case 6: return fusedk::lc_fix_occupancy<6>();
+    case 7: return fusedk::lc_fix_occupancy<7>();
     default: return -2;
   }
 }

@@ -76,6 +76,8 @@ struct bg_context {
   size_t comc_ws_words = 0;
   uint64_t* comc_items = nullptr;            // (event, ordering) items
   double* comc_amp = nullptr;                // their amplitudes
+  float* comc_bnd = nullptr;                 // their FP32 error bounds (checked FP32)
+  unsigned* comc_sel = nullptr;              // items listed for FP64 re-evaluation
   size_t comc_cap = 0;
   void* cdmc_state = nullptr;                // per-block state slabs (FP64, n = 9)
   size_t cdmc_state_bytes = 0;
@@ -90,7 +92,8 @@ struct bg_context {
   int occ_cdbg[BG_N_MAX + 1][2] = {};        // of the colour-dressed event kernel
   size_t occ_batch_lds[4][2] = {};
   uint32_t flags = 0;                        // BG_FLAG_* applied to every request
-  float fp32_tau[2][BG_N_MAX + 1] = {};      // FP32 check thresholds [COBG, CDBG][n]
+  float fp32_tau[4][BG_N_MAX + 1] = {};      // FP32 check thresholds [COBG, CDBG, COMC, LC][n]
+  int occ_lc_fix[BG_N_MAX + 1] = {};         // of the FP64 leading-colour re-evaluation
   unsigned* flag_ws = nullptr;               // FP32 check: [0] count, list from word 64
   size_t flag_ws_words = 0;
   int occ_fix[BG_N_MAX + 1][2] = {};         // blocks per CU of the FP64 re-evaluation [n][hsum]
@@ -287,9 +290,20 @@ bool valid_n(int n) { return n >= BG_N_MIN && n <= BG_N_MAX; }
 //   n = 9: 5e9, ~48% (~6e-6).
 // The dressed bound is looser than the colour-ordered one (many more terms
 // per current), so larger fractions are listed.
-constexpr float kDefaultFp32Tau[2][BG_N_MAX + 1] = {
+// Colour-sampled colour-ordered, same flows (the flow amplitude sums a few
+// orderings that cancel: p99 without the check 3e-4 .. 7e-4 for n >= 5):
+//   n = 4: 1e6 (p99 2.1e-6, max 2.7e-5; without: max 5.4e-4);
+//   n = 5: 1e5, ~20% re-evaluated (5.9e-6);  n = 6: 1e6, ~28% (6.8e-6);
+//   n = 7: 1e7, ~35% (7.3e-6);  n = 8: 1e8, ~42% (7.0e-6);
+//   n = 9: 1e9, ~51% (6.1e-6).
+// Leading colour (2^18 events, n = 7: 2^15):
+//   n = 4 is not checked (largest error 7.5e-7);  n = 5: 1e6, ~9% (6.0e-6);
+//   n = 6: 3e7, ~10% (6.2e-6);  n = 7: 1e9, ~9% (6.1e-6).
+constexpr float kDefaultFp32Tau[4][BG_N_MAX + 1] = {
     {0.f, 0.f, 0.f, 0.f, INFINITY, 3e5f, 3e6f, 1e8f, 0.f, 0.f},
-    {0.f, 0.f, 0.f, 0.f, 1e8f, 3e5f, 2e6f, 3e7f, 3e8f, 5e9f}};
+    {0.f, 0.f, 0.f, 0.f, 1e8f, 3e5f, 2e6f, 3e7f, 3e8f, 5e9f},
+    {0.f, 0.f, 0.f, 0.f, 1e6f, 1e5f, 1e6f, 1e7f, 1e8f, 1e9f},
+    {0.f, 0.f, 0.f, 0.f, INFINITY, 1e6f, 3e7f, 1e9f, 0.f, 0.f}};
 
 // Grows the per-block scratch.  An outgrown buffer is kept until the context
 // is destroyed, since a recorded graph may still refer to it.
@@ -526,7 +540,7 @@ int bg_context_create(bg_context** out, int device, uint32_t flags) {
   ctx->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor;
   ctx->lds_per_block = prop.sharedMemPerBlock;
   ctx->flags = flags;
-  for (int m = 0; m < 2; ++m)
+  for (int m = 0; m < 4; ++m)
     for (int n = 0; n <= BG_N_MAX; ++n) ctx->fp32_tau[m][n] = kDefaultFp32Tau[m][n];
   {
     DeviceGuard g(device);
@@ -568,6 +582,8 @@ void bg_context_destroy(bg_context* ctx) {
   if (ctx->comc_ws) (void)hipFree(ctx->comc_ws);
   if (ctx->comc_items) (void)hipFree(ctx->comc_items);
   if (ctx->comc_amp) (void)hipFree(ctx->comc_amp);
+  if (ctx->comc_bnd) (void)hipFree(ctx->comc_bnd);
+  if (ctx->comc_sel) (void)hipFree(ctx->comc_sel);
   if (ctx->cdmc_state) (void)hipFree(ctx->cdmc_state);
   if (ctx->counter) (void)hipFree(ctx->counter);
   if (ctx->flag_ws) (void)hipFree(ctx->flag_ws);
@@ -746,18 +762,21 @@ static int me2_cdbg(bg_context* ctx, const bg_request* r, uint32_t flags, hipStr
                                     check ? &ca : nullptr, (int)fix_grid, stream));
 }
 
-static int me2_comc(bg_context* ctx, const bg_request* r, hipStream_t stream) {
+static int me2_comc(bg_context* ctx, const bg_request* r, uint32_t flags, hipStream_t stream) {
   const int n = r->n;
   const int64_t E = r->n_events;
   if (E > 0x7fffffffLL) return BG_ERANGE;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive)
     return BG_EINVAL;  // needs a synchronisation
+  const bool fp32 = r->precision == BG_PREC_FP32_MIXED;
+  const float tau = ctx->fp32_tau[2][n];
+  const bool check = fp32 && !(flags & BG_FLAG_FP32_UNCHECKED) && tau != INFINITY;
   // workspace in 8-byte words: block item and valid-event offsets [nb + 1]
-  // each, then counts, offsets and the valid-event list [E] each as 32-bit
-  // words
+  // each, then as 32-bit words counts, offsets and the valid-event list [E]
+  // each, the listed-event count and work counter, the listed events [E]
   const int64_t nb = (E + 255) / 256;
-  const size_t words = (size_t)(2 * (nb + 1) + (3 * E + 1) / 2);
+  const size_t words = (size_t)(2 * (nb + 1) + (4 * E + 2 + 1) / 2);
   int st;
   if (ctx->comc_ws_words < words) {
     st = hip_status(hipDeviceSynchronize(), "hipDeviceSynchronize");
@@ -774,6 +793,8 @@ static int me2_comc(bg_context* ctx, const bg_request* r, hipStream_t stream) {
   unsigned* counts = reinterpret_cast<unsigned*>(block_valid + nb + 1);
   unsigned* offsets = counts + E;
   unsigned* valid = offsets + E;
+  unsigned* fcount = valid + E;  // [0] listed events, [1] listed items
+  unsigned* flist = fcount + 2;
   st = launch_status(bg::comc_count(n, E, r->col, r->me2, counts, offsets, valid, block_items,
                                     block_valid, stream));
   if (st) return st;
@@ -794,25 +815,47 @@ static int me2_comc(bg_context* ctx, const bg_request* r, hipStream_t stream) {
     const size_t cap = std::max<size_t>((size_t)n_items, 2 * ctx->comc_cap);
     if (ctx->comc_items) (void)hipFree(ctx->comc_items);
     if (ctx->comc_amp) (void)hipFree(ctx->comc_amp);
+    if (ctx->comc_bnd) (void)hipFree(ctx->comc_bnd);
+    if (ctx->comc_sel) (void)hipFree(ctx->comc_sel);
     ctx->comc_items = nullptr;
     ctx->comc_amp = nullptr;
+    ctx->comc_bnd = nullptr;
+    ctx->comc_sel = nullptr;
     ctx->comc_cap = 0;
     st = hip_status(hipMalloc(&ctx->comc_items, sizeof(uint64_t) * cap), "hipMalloc(comc items)");
     if (!st) st = hip_status(hipMalloc(&ctx->comc_amp, 2 * sizeof(double) * cap), "hipMalloc(comc amp)");
+    if (!st) st = hip_status(hipMalloc(&ctx->comc_bnd, sizeof(float) * cap), "hipMalloc(comc bounds)");
+    if (!st) st = hip_status(hipMalloc(&ctx->comc_sel, sizeof(unsigned) * cap), "hipMalloc(comc list)");
     if (st) return st;
     ctx->comc_cap = cap;
   }
   st = launch_status(bg::comc_items(n, E, r->col, valid, (unsigned)n_valid, counts, offsets,
                                     ctx->comc_items, stream));
   if (st) return st;
-  const bool fp32 = r->precision == BG_PREC_FP32_MIXED;
   const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((n_items + 31) / 32,
                                                                  (uint64_t)ctx->num_cus * 8));
   st = launch_status(bg::comc_amplitudes(n, fp32, E, r->mom, r->hel, ctx->comc_items,
-                                         block_items + nb, ctx->comc_amp, grid, stream));
+                                         block_items + nb, ctx->comc_amp,
+                                         check ? ctx->comc_bnd : nullptr, grid, stream));
   if (st) return st;
-  return launch_status(bg::comc_reduce(valid, (unsigned)n_valid, counts, offsets, ctx->comc_amp,
-                                       r->me2, stream));
+  if (!check)
+    return launch_status(bg::comc_reduce(valid, (unsigned)n_valid, counts, offsets, ctx->comc_amp,
+                                         r->me2, stream));
+  // FP32 check: the listed events' items again in FP64, then those events
+  // reduced again (counts stay on the device)
+  st = launch_status(bg::fill_u32(fcount, 2, 0u, stream));
+  if (!st)
+    st = launch_status(bg::comc_reduce_check(n, E, r->hel, valid, (unsigned)n_valid, counts,
+                                             offsets, ctx->comc_amp, ctx->comc_bnd, r->me2, tau,
+                                             fcount, flist, ctx->comc_sel, stream));
+  if (!st)
+    st = launch_status(bg::comc_amplitudes_listed(n, E, r->mom, r->hel, ctx->comc_items,
+                                                  ctx->comc_sel, fcount + 1, ctx->comc_amp, grid,
+                                                  stream));
+  if (!st)
+    st = launch_status(bg::comc_reduce_listed(flist, fcount, (unsigned)n_valid, counts, offsets,
+                                              ctx->comc_amp, r->me2, stream));
+  return st;
 }
 
 static int validate_request(const bg_request* r) {
@@ -830,17 +873,41 @@ static int validate_request(const bg_request* r) {
   return BG_OK;
 }
 
+// Leading colour (fused, n <= 7), with the FP32 check of the colour-ordered
+// path (running error bounds summed over the (n-1)! orderings).
+static int me2_lc(bg_context* ctx, const bg_request* r, uint32_t flags, hipStream_t stream,
+                  const FixedWs* fixed) {
+  const int n = r->n;
+  const int64_t E = r->n_events;
+  if (n > 7) return BG_EUNSUPPORTED;
+  if (!r->hel) return BG_EINVAL;
+  const bool fp32 = r->precision == BG_PREC_FP32_MIXED;
+  const float tau = ctx->fp32_tau[3][n];
+  const bool check = fp32 && !(flags & BG_FLAG_FP32_UNCHECKED) && !(tau == INFINITY) &&
+                     E <= (int64_t)0xffffffffLL;
+  if (!check)
+    return launch_status(bg::lc_me2(n, fp32, E, r->mom, r->hel, r->me2, nullptr, 0, stream));
+  int& occ = ctx->occ_lc_fix[n];
+  if (occ <= 0) occ = bg::lc_fix_blocks_per_cu(n);
+  if (occ <= 0) return BG_EDEVICE;
+  const int64_t fix_grid = std::min<int64_t>((E + 31) / 32, (int64_t)ctx->num_cus * occ);
+  if (!fixed) {
+    int st = ensure_flags(ctx, E);
+    if (st) return st;
+  }
+  unsigned* ws = fixed ? fixed->flag_ws : ctx->flag_ws;
+  bg::CheckArgs ca{tau, ws, ws + kFlagListOffset};
+  int st = launch_status(bg::fill_u32(ca.count, 1, 0u, stream));
+  if (st) return st;
+  return launch_status(bg::lc_me2(n, true, E, r->mom, r->hel, r->me2, &ca, (int)fix_grid, stream));
+}
+
 static int me2_dispatch(bg_context* ctx, const bg_request* r, uint32_t flags, hipStream_t stream,
                         const FixedWs* fixed = nullptr) {
   const int mode = r->mode == BG_MODE_AUTO ? (r->n <= 7 ? BG_MODE_COBG : BG_MODE_CDBG) : r->mode;
   if (mode == BG_MODE_COBG) return me2_cobg(ctx, r, flags, stream, fixed);
-  if (mode == BG_MODE_COMC) return fixed ? BG_EUNSUPPORTED : me2_comc(ctx, r, stream);
-  if (mode == BG_MODE_LC) {
-    if (r->n > 7) return BG_EUNSUPPORTED;
-    if (!r->hel) return BG_EINVAL;
-    return launch_status(bg::lc_me2(r->n, r->precision == BG_PREC_FP32_MIXED, r->n_events, r->mom,
-                                    r->hel, r->me2, stream));
-  }
+  if (mode == BG_MODE_COMC) return fixed ? BG_EUNSUPPORTED : me2_comc(ctx, r, flags, stream);
+  if (mode == BG_MODE_LC) return me2_lc(ctx, r, flags, stream, fixed);
   return me2_cdbg(ctx, r, flags, stream, fixed);
 }
 
@@ -884,6 +951,8 @@ int bg_me2_noalloc(bg_context* ctx, const bg_request* r, void* stream) {
 static int check_slot(int mode, int n) {
   if (mode == BG_MODE_COBG && n >= 4 && n <= 7) return 0;
   if (mode == BG_MODE_CDBG && valid_n(n)) return 1;
+  if (mode == BG_MODE_COMC && valid_n(n)) return 2;
+  if (mode == BG_MODE_LC && n >= 4 && n <= 7) return 3;
   return -1;
 }
 

@@ -119,8 +119,12 @@ int cobg_fix_me2(int n, int64_t E, const double* mom, const int8_t* hel, const d
 int cobg_fix_blocks_per_cu(int n, bool hsum);
 int cobg_fused_scratch_doubles(int n);
 // Leading-colour |M|^2 over all (n-1)! orderings, one helicity per event.
+// Leading colour; chk (FP32 only): list ill-conditioned events into
+// chk->count / chk->list (count zeroed beforehand), then evaluate them again
+// in FP64 on fix_grid persistent blocks.
 int lc_me2(int n, bool fp32, int64_t E, const double* mom, const int8_t* hel, double* me2,
-           hipStream_t stream);
+           const CheckArgs* chk, int fix_grid, hipStream_t stream);
+int lc_fix_blocks_per_cu(int n);
 int cobg_fused_persistent_blocks_per_cu(bool fp32, bool hsum, bool chk);
 // LDS of a colour-ordered tile (recursion state plus staged amplitudes).
 size_t cobg_lds_bytes(int n, bool fp32);
@@ -192,10 +196,25 @@ int comc_items(int n, int64_t E, const int8_t* col, const unsigned* valid, unsig
                const unsigned* counts, const unsigned* offsets, uint64_t* items,
                hipStream_t stream);
 int comc_amplitudes(int n, bool fp32, int64_t E, const double* mom, const int8_t* hel,
-                    const uint64_t* items, const uint64_t* total, double* amp, int grid,
-                    hipStream_t stream);
+                    const uint64_t* items, const uint64_t* total, double* amp, float* bnd,
+                    int grid, hipStream_t stream);
 int comc_reduce(const unsigned* valid, unsigned n_valid, const unsigned* counts,
                 const unsigned* offsets, const double* amp, double* me2, hipStream_t stream);
+// FP32 check (bnd from comc_amplitudes with fp32 and bnd non-null): events
+// with B^2 > tau |A|^2 are appended to flist (count fcount[0]) and their
+// items to sel (count fcount[1]; both zeroed beforehand); then the listed
+// items again in FP64 and the listed events reduced again (max_listed: an
+// upper bound on fcount[0] that sizes the grid).
+int comc_reduce_check(int n, int64_t E, const int8_t* hel, const unsigned* valid, unsigned n_valid,
+                      const unsigned* counts, const unsigned* offsets, const double* amp,
+                      const float* bnd, double* me2, float tau, unsigned* fcount, unsigned* flist,
+                      unsigned* sel, hipStream_t stream);
+int comc_amplitudes_listed(int n, int64_t E, const double* mom, const int8_t* hel,
+                           const uint64_t* items, const unsigned* sel, const unsigned* sel_count,
+                           double* amp, int grid, hipStream_t stream);
+int comc_reduce_listed(const unsigned* flist, const unsigned* fcount, unsigned max_listed,
+                       const unsigned* counts, const unsigned* offsets, const double* amp,
+                       double* me2, hipStream_t stream);
 
 // Continuous colour / real-polarization sampling with the dressed recursion
 // (cdmc.hip).  gstate: blocks x cdmc_state_bytes when cdmc_global_state.

@@ -26,6 +26,15 @@
 // from the FP64 prefix momenta).  (6) one wave per valid event adds its
 // items' amplitudes and writes |A|^2.  The totals are read back once (a
 // synchronisation) to size the item arrays and the enumeration grid.
+//
+// FP32 check: with the FP32 recursion each item also carries the running
+// error bound of its top current (State::Sb of cobg_pair_impl.h, scaled like
+// the amplitude); the flow amplitude's FP32 error is bounded by the sum of
+// its items' bounds B, so pass 6 lists the event when B^2 > tau |A|^2
+// (helicity configurations whose tree amplitude vanishes identically are
+// never listed), together with its items.  The listed items are evaluated
+// again in FP64 (pass 5 over the item list, its length read on the device)
+// and the listed events reduced again (pass 6 over the event list).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -322,9 +331,9 @@ __global__ void __launch_bounds__(kThreads) enumerate_kernel(int64_t E, const in
 // Per-lane context for one ordering (see pairk::Ctx; 1/P^2 computed from the
 // prefix momenta, V4 dot products recomputed when the Dt table would not fit
 // in registers).
-template <int N, typename T, bool NODT>
+template <int N, typename T, bool NODT, bool EST = false>
 struct Ctx {
-  static constexpr bool kRaw = false, kP64G = false, kLC = false, kEst = false;
+  static constexpr bool kRaw = false, kP64G = false, kLC = false, kEst = EST;
   static constexpr bool kDirectP2 = true;
   static constexpr bool kNoDt = NODT;
   T* gl_slots;   // [6 (g-1) + x][lane]
@@ -336,7 +345,8 @@ struct Ctx {
 };
 
 template <int N, typename T, int D, class C>
-__device__ __forceinline__ void path(pairk::State<N, T>& s, C& c, uint32_t code, Cx<T>& top) {
+__device__ __forceinline__ void path(pairk::State<N, T>& s, C& c, uint32_t code, Cx<T>& top,
+                                     T& topb) {
   constexpr int M = N - 1;
   int g = (int)((code >> (4 * (D - 1))) & 15u);
   g = g < 1 ? 1 : (g > N - 1 ? N - 1 : g);  // codes hold 1..N-1; keeps LDS reads in bounds
@@ -348,6 +358,14 @@ __device__ __forceinline__ void path(pairk::State<N, T>& s, C& c, uint32_t code,
     s.J[D][D].im[m] = c.gl_slots[(base + 2 + m) * 64 + c.lane];
     s.Pg[D].v[m] = c.gl_slots[(base + 4 + m) * 64 + c.lane];
     s.P0[D].v[m] = s.P0[D - 1].v[m] + c.p64[(2 * (g - 1) + m) * 64 + c.lane];
+  }
+  if constexpr (C::kEst) {
+    // |p^0| of the gluon: the h = 0 lane holds it, the h = 1 lane takes it
+    // from its partner (both lanes run this exchange)
+    const double pg = c.p64[(2 * (g - 1)) * 64 + c.lane];
+    const double px = pairk::xswap(pg);
+    s.Ep[D] = s.Ep[D - 1] + (T)fabs(c.h == 0 ? pg : px);
+    s.Sb[D][D] = T(1);
   }
   pairk::set_gd<N, T, D, D>(s, c);
   if constexpr (D == M - 1) {
@@ -361,9 +379,8 @@ __device__ __forceinline__ void path(pairk::State<N, T>& s, C& c, uint32_t code,
       c.epsN.im[m] = c.gl_slots[(lb + 2 + m) * 64 + c.lane];
     }
   }
-  T topb;
   pairk::build_column<N, T, D, D - 1>(s, c, 0, top, topb);
-  if constexpr (D < M - 1) path<N, T, D + 1>(s, c, code, top);
+  if constexpr (D < M - 1) path<N, T, D + 1>(s, c, code, top, topb);
 }
 
 template <int N>
@@ -375,19 +392,24 @@ struct AmpLds {
 };
 
 // Pass 4: persistent blocks over 32-item tiles; amp[2 item + h] = plane h
-// of A(1, sigma) including the couplings.
-template <int N, typename T, bool NODT>
+// of A(1, sigma) including the couplings; EST: bnd[item] = the running error
+// bound of the top current times the same couplings.  sel (re-evaluation of
+// listed items): the items are sel[0 .. *sel_count) instead of all.
+template <int N, typename T, bool NODT, bool EST>
 __global__ void __launch_bounds__(64) amp_kernel(int64_t E, const double* __restrict__ mom,
                                                 const int8_t* __restrict__ hel,
                                                 const uint64_t* __restrict__ items,
                                                 const uint64_t* __restrict__ total_p,
-                                                double* __restrict__ amp) {
+                                                double* __restrict__ amp,
+                                                float* __restrict__ bnd,
+                                                const unsigned* __restrict__ sel,
+                                                const unsigned* __restrict__ sel_count) {
   extern __shared__ __align__(16) unsigned char bg_comc_lds[];
-  const unsigned total = (unsigned)*total_p;  // below 2^31 (host check)
+  const unsigned total = sel ? *sel_count : (unsigned)*total_p;  // below 2^31 (host check)
   const int lane = threadIdx.x;
   const int pair = lane >> 1, h = lane & 1;
   const bool hi = h != 0;
-  Ctx<N, T, NODT> c;
+  Ctx<N, T, NODT, EST> c;
   c.gl_slots = reinterpret_cast<T*>(bg_comc_lds);
   c.p64 = reinterpret_cast<double*>(c.gl_slots + (size_t)6 * (N - 1) * 64);
   c.tab = nullptr;
@@ -399,7 +421,8 @@ __global__ void __launch_bounds__(64) amp_kernel(int64_t E, const double* __rest
 #pragma unroll
   for (int i = 0; i < N - 2; ++i) scale *= kGsOverSqrt2;
   for (unsigned base = blockIdx.x * 32u; base < total; base += gridDim.x * 32u) {
-    const unsigned it = base + pair < total ? base + pair : total - 1;
+    const unsigned slot = base + pair < total ? base + pair : total - 1;
+    const unsigned it = sel ? sel[slot] : slot;
     const uint64_t item = items[it];
     int64_t e = (int64_t)(item >> 32);
     e = e < E ? e : E - 1;  // items always hold e < E; the clamp keeps reads in bounds regardless
@@ -431,6 +454,10 @@ __global__ void __launch_bounds__(64) amp_kernel(int64_t E, const double* __rest
         s.Pg[0].v[1] = v[5];
         s.P0[0].v[0] = ph[0];
         s.P0[0].v[1] = ph[1];
+        if constexpr (EST) {
+          s.Ep[0] = (T)fabs(p[0]);
+          s.Sb[0][0] = T(1);
+        }
       } else {
 #pragma unroll
         for (int x = 0; x < 6; ++x) c.gl_slots[(6 * (i - 1) + x) * 64 + lane] = v[x];
@@ -440,8 +467,12 @@ __global__ void __launch_bounds__(64) amp_kernel(int64_t E, const double* __rest
     }
     s.gl[0] = 0;
     Cx<T> top;
-    path<N, T, 1>(s, c, code, top);
-    if (base + pair < total) amp[2 * (size_t)it + h] = (double)(h == 0 ? top.re : top.im) * scale;
+    T topb = T(0);
+    path<N, T, 1>(s, c, code, top, topb);
+    if (base + pair < total) {
+      amp[2 * (size_t)it + h] = (double)(h == 0 ? top.re : top.im) * scale;
+      if (EST && h == 0) bnd[it] = (float)((double)topb * scale);
+    }
   }
 }
 
@@ -474,12 +505,82 @@ __global__ void __launch_bounds__(kThreads) reduce_kernel(const unsigned* __rest
   if (lane == 0) me2[e] = re * re + im * im;
 }
 
-template <int N, typename T>
+// Pass 6 with the FP32 check: as reduce_kernel, and the sum B of the items'
+// error bounds; the event is listed when B^2 > tau |A|^2 (or the test is not
+// a number) unless its helicity configuration vanishes identically: appended
+// to flist (count fcount[0]) and its items to sel (count fcount[1]).
+__global__ void __launch_bounds__(kThreads) reduce_check_kernel(
+    int n, int64_t E, const int8_t* __restrict__ hel, const unsigned* __restrict__ valid,
+    unsigned n_valid, const unsigned* __restrict__ counts, const unsigned* __restrict__ offsets,
+    const double* __restrict__ amp, const float* __restrict__ bnd, double* __restrict__ me2,
+    float tau, unsigned* __restrict__ fcount, unsigned* __restrict__ flist,
+    unsigned* __restrict__ sel) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const unsigned v = blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
+  if (v >= n_valid) return;  // whole waves leave together
+  const unsigned e = valid[v];
+  const unsigned c = counts[e];
+  const unsigned o = offsets[e];
+  double re = 0.0, im = 0.0, b = 0.0;
+  for (unsigned k = lane; k < c; k += kWave) {
+    re += amp[2 * (size_t)(o + k)];
+    im += amp[2 * (size_t)(o + k) + 1];
+    b += (double)bnd[o + k];
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    re += __shfl_xor(re, off, kWave);
+    im += __shfl_xor(im, off, kWave);
+    b += __shfl_xor(b, off, kWave);
+  }
+  const double a2 = re * re + im * im;
+  int neg = 0;
+  for (int k = 0; k < n; ++k) neg += hel[(int64_t)k * E + e] < 0 ? 1 : 0;
+  const bool listed = neg >= 2 && neg <= n - 2 && !(b * b <= (double)tau * a2);
+  if (lane == 0) me2[e] = a2;
+  if (!listed) return;  // uniform over the wave
+  unsigned ib = 0u;
+  if (lane == 0) {
+    flist[atomicAdd(fcount, 1u)] = e;
+    ib = atomicAdd(fcount + 1, c);
+  }
+  ib = (unsigned)__shfl((int)ib, 0, kWave);
+  for (unsigned k = lane; k < c; k += kWave) sel[ib + k] = o + k;
+}
+
+// Pass 6 again for the listed events flist[0 .. *fcount) after their items'
+// FP64 re-evaluation (waves past the count leave at once).
+__global__ void __launch_bounds__(kThreads) reduce_listed_kernel(
+    const unsigned* __restrict__ flist, const unsigned* __restrict__ fcount,
+    const unsigned* __restrict__ counts, const unsigned* __restrict__ offsets,
+    const double* __restrict__ amp, double* __restrict__ me2) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const unsigned v = blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
+  if (v >= *fcount) return;  // whole waves leave together
+  const unsigned e = flist[v];
+  const unsigned c = counts[e];
+  const unsigned o = offsets[e];
+  double re = 0.0, im = 0.0;
+  for (unsigned k = lane; k < c; k += kWave) {
+    re += amp[2 * (size_t)(o + k)];
+    im += amp[2 * (size_t)(o + k) + 1];
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    re += __shfl_xor(re, off, kWave);
+    im += __shfl_xor(im, off, kWave);
+  }
+  if (lane == 0) me2[e] = re * re + im * im;
+}
+
+template <int N, typename T, bool EST = false>
 int amp_launch(int64_t E, const double* mom, const int8_t* hel, const uint64_t* items,
-               const uint64_t* total, double* amp, int grid, hipStream_t stream) {
+               const uint64_t* total, double* amp, float* bnd, const unsigned* sel,
+               const unsigned* sel_count, int grid, hipStream_t stream) {
   constexpr bool NODT = N >= 8;
-  hipLaunchKernelGGL((amp_kernel<N, T, NODT>), dim3(grid), dim3(64), (AmpLds<N>::template bytes<T>()),
-                     stream, E, mom, hel, items, total, amp);
+  hipLaunchKernelGGL((amp_kernel<N, T, NODT, EST>), dim3(grid), dim3(64),
+                     (AmpLds<N>::template bytes<T>()), stream, E, mom, hel, items, total, amp, bnd,
+                     sel, sel_count);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -540,11 +641,25 @@ int comc_items(int n, int64_t E, const int8_t* col, const unsigned* valid, unsig
 }
 
 int comc_amplitudes(int n, bool fp32, int64_t E, const double* mom, const int8_t* hel,
-                    const uint64_t* items, const uint64_t* total, double* amp, int grid,
-                    hipStream_t stream) {
-#define C_(NN)                                                                             \
-  (fp32 ? comck::amp_launch<NN, float>(E, mom, hel, items, total, amp, grid, stream)       \
-        : comck::amp_launch<NN, double>(E, mom, hel, items, total, amp, grid, stream))
+                    const uint64_t* items, const uint64_t* total, double* amp, float* bnd,
+                    int grid, hipStream_t stream) {
+#define C_(NN)                                                                              \
+  (!fp32 ? comck::amp_launch<NN, double>(E, mom, hel, items, total, amp, nullptr, nullptr,   \
+                                         nullptr, grid, stream)                              \
+   : bnd ? comck::amp_launch<NN, float, true>(E, mom, hel, items, total, amp, bnd, nullptr,  \
+                                              nullptr, grid, stream)                         \
+         : comck::amp_launch<NN, float>(E, mom, hel, items, total, amp, nullptr, nullptr,    \
+                                        nullptr, grid, stream))
+  BG_COMC_SWITCH(C_)
+#undef C_
+}
+
+int comc_amplitudes_listed(int n, int64_t E, const double* mom, const int8_t* hel,
+                           const uint64_t* items, const unsigned* sel, const unsigned* sel_count,
+                           double* amp, int grid, hipStream_t stream) {
+#define C_(NN)                                                                              \
+  comck::amp_launch<NN, double>(E, mom, hel, items, nullptr, amp, nullptr, sel, sel_count, \
+                                grid, stream)
   BG_COMC_SWITCH(C_)
 #undef C_
 }
@@ -555,6 +670,28 @@ int comc_reduce(const unsigned* valid, unsigned n_valid, const unsigned* counts,
   const unsigned nb = (n_valid + per_block - 1) / per_block;
   hipLaunchKernelGGL(comck::reduce_kernel, dim3(nb), dim3(comck::kThreads), 0, stream, valid,
                      n_valid, counts, offsets, amp, me2);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int comc_reduce_check(int n, int64_t E, const int8_t* hel, const unsigned* valid, unsigned n_valid,
+                      const unsigned* counts, const unsigned* offsets, const double* amp,
+                      const float* bnd, double* me2, float tau, unsigned* fcount, unsigned* flist,
+                      unsigned* sel, hipStream_t stream) {
+  constexpr unsigned per_block = comck::kThreads / comck::kWave;  // one wave per valid event
+  const unsigned nb = (n_valid + per_block - 1) / per_block;
+  hipLaunchKernelGGL(comck::reduce_check_kernel, dim3(nb), dim3(comck::kThreads), 0, stream, n, E,
+                     hel, valid, n_valid, counts, offsets, amp, bnd, me2, tau, fcount, flist, sel);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int comc_reduce_listed(const unsigned* flist, const unsigned* fcount, unsigned max_listed,
+                       const unsigned* counts, const unsigned* offsets, const double* amp,
+                       double* me2, hipStream_t stream) {
+  constexpr unsigned per_block = comck::kThreads / comck::kWave;  // one wave per listed event
+  const unsigned nb = (max_listed + per_block - 1) / per_block;
+  if (nb == 0) return 0;
+  hipLaunchKernelGGL(comck::reduce_listed_kernel, dim3(nb), dim3(comck::kThreads), 0, stream, flist,
+                     fcount, counts, offsets, amp, me2);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

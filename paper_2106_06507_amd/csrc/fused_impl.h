@@ -188,19 +188,25 @@ __device__ __forceinline__ void cobg_tile(unsigned char* lds, int64_t E,
 // Leading-colour |M|^2 (Section 3.1): N^(n-2) (N^2 - 1) sum over all (n-1)!
 // orderings (1, rho) of |A(1, rho)|^2, N = 3, for events [first, first +
 // count) (count <= 32), one helicity configuration per event.  lds holds
-// pairk::Lds<N, true>::bytes<T>().
-template <int N, typename T>
+// pairk::Lds<N, true>::bytes<T>().  CHK: list the events whose
+// sum_rho S_rho^2 > tau sum_rho |A_rho|^2 (running error bounds of the
+// orderings' top currents; helicity configurations that vanish identically
+// are never listed).  IDX: the events are idx[first .. first + count - 1].
+template <int N, typename T, bool CHK = false, bool IDX = false>
 __device__ __forceinline__ void lc_tile(unsigned char* lds, int64_t E,
                                         const double* __restrict__ mom,
                                         const int8_t* __restrict__ hel, double* __restrict__ me2,
-                                        int64_t first, int count) {
+                                        int64_t first, int count, TileCheck chk = TileCheck{},
+                                        const unsigned* __restrict__ idx = nullptr) {
   const int lane = threadIdx.x & 63;
   const int pair = lane >> 1;
   const int h = lane & 1;
   const bool live = pair < count;
-  const int64_t e = first + (live ? pair : (count > 0 ? count - 1 : 0));
-  const double q = pairk::cobg_pair_body<N, T, false, false, true>(lds, E, mom, hel, 0, e, false,
-                                                                    nullptr, 0, 0);
+  const int64_t slot = first + (live ? pair : (count > 0 ? count - 1 : 0));
+  const int64_t e = IDX ? (int64_t)idx[slot] : slot;
+  T est[2] = {T(0), T(0)};
+  const double q = pairk::cobg_pair_body<N, T, false, false, true, CHK>(
+      lds, E, mom, hel, 0, e, false, nullptr, 0, 0, nullptr, est);
   __syncthreads();
   double scale = 1.0;  // (g_s / sqrt2)^(n-2) per amplitude, squared
 #pragma unroll
@@ -210,6 +216,17 @@ __device__ __forceinline__ void lc_tile(unsigned char* lds, int64_t E,
   for (int i = 0; i < N - 2; ++i) colour *= 3.0;
   const double tot = pairk::pair_sum(q) * scale * scale * colour;
   if (live && h == 0) me2[e] = tot;
+  if constexpr (CHK) {
+    bool f = false;
+    if (live && h == 0) {
+      int neg = 0;
+#pragma unroll
+      for (int i = 0; i < N; ++i) neg += hel[(int64_t)i * E + e] < 0 ? 1 : 0;
+      // the negated test also lists events whose estimate is not a number
+      f = neg >= 2 && neg <= N - 2 && !(est[0] <= chk.tau * est[1]);
+    }
+    flag_events(f, (unsigned)e, chk);
+  }
 }
 
 // Colour-dressed |A|^2 of events [first, first + count), count <= NL, on

@@ -100,7 +100,57 @@ def test_colour_dressed_fp32_p99(api, n):
     assert mx <= FP32_MAX
 
 
-@pytest.mark.parametrize("mode,n", [("cobg", 5), ("cobg", 6), ("cobg", 7), ("cdbg", 6), ("cdbg", 8)])
+@pytest.mark.parametrize("n", [4, 5, 6, 7, 8, 9])
+def test_colour_sampled_ordered_fp32_p99(api, n):
+    """BG_MODE_COMC: sum of the closing orderings' FP32 amplitudes; the
+    orderings of events whose summed error bound is large against |A| are
+    evaluated again in FP64; against the FP64 path on the same flows."""
+    E = 1 << 18
+    ev = make_events(n, E, seed=8400 + n, cuts=True, sample_hel=True, sample_col=True)
+    dm, dh, dc = _dev(ev["mom"]), _dev(ev["hel"]), _dev(ev["col"])
+    _say(f"checked fp32 colour-sampled colour-ordered n={n} E={E}")
+    f64 = api.me2(dm, dh, dc, mode="comc", precision="fp64").cpu().numpy()
+    f32 = api.me2(dm, dh, dc, mode="comc", precision="fp32").cpu().numpy()
+    raw = api.me2(dm, dh, dc, mode="comc", precision="fp32_unchecked").cpu().numpy()
+    keep = _dressed_keep(ev["hel"], f64)
+    # flows without a closed chain are exactly 0 on both paths (helicity
+    # configurations that vanish identically give rounding noise instead)
+    nz = nonvanishing(ev["hel"])
+    typical = np.median(np.abs(f64[f64 != 0.0]))
+    noise = (np.abs(f64) < 1e-8 * typical) & (np.abs(f32) < 1e-8 * typical)
+    assert np.array_equal(((f32 == 0.0) | noise)[nz], ((f64 == 0.0) | noise)[nz])
+    med, p99, mx = _stats(f32, f64, keep)
+    _, p99r, mxr = _stats(raw, f64, keep)
+    listed = np.mean((f32 != raw)[keep])
+    _say(f"  {keep.sum()} valid: checked median {med:.2e} p99 {p99:.2e} max {mx:.2e}; "
+         f"unchecked p99 {p99r:.2e} max {mxr:.2e}; re-evaluated ~{listed:.1%}")
+    assert p99 <= FP32_P99
+    assert mx <= FP32_MAX
+
+
+@pytest.mark.parametrize("n", [4, 5, 6, 7])
+def test_leading_colour_fp32_p99(api, n):
+    """BG_MODE_LC: FP32 sum of |A|^2 over the (n-1)! orderings, events whose
+    summed squared error bounds are large against it evaluated again in
+    FP64; against the FP64 leading-colour path."""
+    E = (1 << 18) if n < 7 else (1 << 15)
+    ev = make_events(n, E, seed=8500 + n, cuts=True, sample_hel=True)
+    dm, dh = _dev(ev["mom"]), _dev(ev["hel"])
+    _say(f"checked fp32 leading colour n={n} E={E}")
+    f64 = api.me2(dm, dh, mode="lc", precision="fp64").cpu().numpy()
+    f32 = api.me2(dm, dh, mode="lc", precision="fp32").cpu().numpy()
+    raw = api.me2(dm, dh, mode="lc", precision="fp32_unchecked").cpu().numpy()
+    keep = nonvanishing(ev["hel"])
+    med, p99, mx = _stats(f32, f64, keep)
+    _, p99r, mxr = _stats(raw, f64, keep)
+    _say(f"  checked median {med:.2e} p99 {p99:.2e} max {mx:.2e}; unchecked p99 {p99r:.2e} "
+         f"max {mxr:.2e}")
+    assert p99 <= FP32_P99
+    assert mx <= FP32_MAX
+
+
+@pytest.mark.parametrize("mode,n", [("cobg", 5), ("cobg", 6), ("cobg", 7), ("cdbg", 6), ("cdbg", 8),
+                                    ("comc", 6), ("comc", 8), ("lc", 6)])
 def test_threshold_extremes(api, mode, n):
     """tau = 0: every non-vanishing event is re-evaluated in FP64, so the
     result equals the FP64 path bit for bit; tau = inf: none is, so it equals
@@ -109,7 +159,7 @@ def test_threshold_extremes(api, mode, n):
     E = 3001 if mode == "cobg" else 20011
     ev = make_events(n, E, seed=8300 + n, cuts=True, sample_hel=True, sample_col=True)
     dm, dh = _dev(ev["mom"]), _dev(ev["hel"])
-    dc = _dev(ev["col"]) if mode == "cdbg" else None
+    dc = _dev(ev["col"]) if mode in ("cdbg", "comc") else None
     keep = nonvanishing(ev["hel"])
     f64 = api.me2(dm, dh, dc, mode=mode, precision="fp64").cpu().numpy()
     raw = api.me2(dm, dh, dc, mode=mode, precision="fp32_unchecked").cpu().numpy()
@@ -132,6 +182,7 @@ def test_threshold_api(api):
         assert 0.0 < api.fp32_check(n) < float("inf")
     for n in range(4, 10):
         assert 0.0 < api.fp32_check(n, mode="cdbg") < float("inf")
+        assert 0.0 < api.fp32_check(n, mode="comc") < float("inf")
     for bad in ((8, "cobg"), (3, "cdbg"), (10, "cdbg")):
         with pytest.raises(BGError):
             api.fp32_check(bad[0], mode=bad[1])
@@ -139,8 +190,10 @@ def test_threshold_api(api):
         api.fp32_check(6, -1.0)
     with pytest.raises(BGError):
         api.fp32_check(6, float("nan"))
+    for n in (5, 6, 7):
+        assert 0.0 < api.fp32_check(n, mode="lc") < float("inf")
     with pytest.raises(BGError):
-        api.fp32_check(6, mode="comc")
+        api.fp32_check(8, mode="lc")
 
 
 def test_mixed_batch_fp32_p99(api):

@@ -4,8 +4,10 @@ The oracle evaluates N^(n-2)(N^2-1) sum over the (n-1)! orderings (1, rho)
 of |A(1, rho)|^2 with its own recursion; its formula is pinned to the full
 colour sum at n = 4, 5, where it is exact.  Error statistic as for the
 colour-ordered path: per-event relative error on events with a
-non-vanishing helicity configuration, FP64 median 1e-13 / max 1e-10, FP32
-median 1e-5 / max 1e-2.
+non-vanishing helicity configuration, FP64 median 1e-13 / max 1e-10; FP32
+(checked: ill-conditioned events evaluated again in FP64) median 1e-6 / max
+3e-4, the bars of the checked colour-ordered path (p99 <= 1e-5 is asserted
+on 2^18-event samples in test_gpu_fp32_check).
 """
 import numpy as np
 import pytest
@@ -17,7 +19,7 @@ from tests.helpers import nonvanishing
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-BARS = {"fp64": (1e-13, 1e-10), "fp32": (1e-5, 1e-2)}
+BARS = {"fp64": (1e-13, 1e-10), "fp32": (1e-6, 3e-4)}
 
 
 @pytest.fixture(scope="module")
