@@ -426,6 +426,21 @@ def two_stage_row(api, wm, torch, n, mom, hel, steps):
     return row
 
 
+def section_two_stage(args, api, wm, torch):
+    """Only the two-stage colour-ordered path (amplitudes to memory, then the
+    colour sum) at n = 6, 7, 8: K = 24 and 120 on matrix cores, K = 720 from
+    the first row of C.  Device-generated inputs; used for kernel profiles."""
+    rows = {}
+    steps = max(2, args.steps // 4)
+    for n, E in ((6, args.events), (7, 1 << 18), (8, 1 << 16)):
+        out = api.generate(n, E, 2106065070 + 40 + n, n_attempts=3 * E)
+        torch.cuda.synchronize()
+        if int(out["n_generated"]) < E:
+            raise RuntimeError(f"device generator produced too few events at n={n}")
+        rows[str(n)] = two_stage_row(api, wm, torch, n, out["mom"], out["hel"], steps)
+    return rows
+
+
 def section_per_n(args, api, wm, torch):
     """Events/s and roofline fraction per gluon multiplicity, FP64 and FP32
     (checked), with the FP32 error relative to the FP64 evaluation of the same
@@ -595,7 +610,7 @@ def main():
     ap.add_argument("--events", type=int, default=1 << 20)
     ap.add_argument("--sections", default="cfg1,cdbg,adjoint,batch,pipeline,per_n",
                     help="extra rows beside the headline: any of cfg1, cdbg, adjoint, batch, "
-                         "pipeline, per_n, or none")
+                         "pipeline, per_n, two_stage (profiling only), or none")
     ap.add_argument("--continuous", action="store_true",
                     help="also time the continuous colour/polarization variant per n")
     ap.add_argument("--cpu-sample", type=int, default=1 << 18,
@@ -635,6 +650,8 @@ def main():
         extra["device_phase_space_pipeline"] = section_pipeline(args, api, torch)
     if "per_n" in sections:
         extra["per_multiplicity"] = section_per_n(args, api, wm, torch)
+    if "two_stage" in sections:
+        extra["two_stage_colour_ordered"] = section_two_stage(args, api, wm, torch)
     cpu = None if args.no_cpu else cpu_baseline(args, ev)
 
     rec = {

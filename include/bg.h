@@ -156,14 +156,16 @@ typedef struct bg_request {
 } bg_request;
 
 /* |M|^2 per event.  COBG: colour-summed (eq. color_summed_analytic), for one
- * helicity per event or summed over helicities (hel NULL); for n <= 7 the
- * recursion and the colour sum run in one kernel and the partial amplitudes
- * never reach device memory outside a small per-block scratch (FP64 colour
- * sum in VALU; bg_currents + bg_color_contract give the same quantity
- * through the matrix-core contraction with the amplitudes exposed).  For
- * n = 8 (BG_PREC_FP64 only, BG_EUNSUPPORTED otherwise) it runs as those two
- * calls over chunks of 2^17 events, once per helicity configuration
- * (accumulated) when hel is NULL, with 1.5 GB of context workspace.  CDBG: |A|^2 of the
+ * helicity per event or summed over helicities (hel NULL).  For n <= 6, and
+ * for n = 7 in FP32, the recursion and the colour sum run in one kernel and
+ * the partial amplitudes never reach device memory outside a small
+ * per-block scratch (FP64 colour sum in VALU).  For n = 7 in FP64 and for
+ * n = 8 (BG_PREC_FP64 only, BG_EUNSUPPORTED otherwise) it runs as
+ * bg_currents followed by bg_color_contract (one straight path per ordering,
+ * then the matrix-core colour sum) over chunks of 2^18 (n = 7, 0.5 GB of
+ * context workspace) or 2^17 events (n = 8, 1.5 GB), once per helicity
+ * configuration (accumulated) when hel is NULL; the FP32 check at n = 7
+ * re-evaluates its listed events through the same two stages.  CDBG: |A|^2 of the
  * colour-flow amplitude of the given assignment (eq. color_decomposition_colorflow
  * via eq. color_dressed_currents); assignments without a closed colour chain
  * give exactly 0.  May allocate context workspace on first use of a size. */
@@ -173,8 +175,9 @@ int bg_me2(bg_context* ctx, const bg_request* req, void* stream);
  * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
  * request, kernels and results (bit for bit) as bg_me2, but every piece of
  * device memory beyond the caller's inputs and outputs (check lists,
- * counters, colour-dressed event lists, per-block scratch of the n = 7
- * kernels) comes from a file-scope device array of BG_NOALLOC_SCRATCH_BYTES
+ * counters, colour-dressed event lists, per-block scratch and two-stage
+ * amplitude chunks of the n = 7 paths, in chunks of at most 16,930 events)
+ * comes from a file-scope device array of BG_NOALLOC_SCRATCH_BYTES
  * that each GPU holds until the process ends; its address is looked up once
  * per device when the first context on it is created, and the colour
  * matrices it needs are uploaded then.  The call itself calls no hipMalloc
@@ -235,10 +238,11 @@ int bg_me2_grad(bg_context* ctx, const bg_request* req, const double* grad_me2,
  * for n >= 8 per segment; explicit modes are honoured (COBG needs n <= 7).
  * Every segment must have the same precision, hel non-NULL, me2 non-NULL when
  * its n_events > 0, and col for CDBG; at most BG_BATCH_MAX_SEGS segments.
- * Colour-ordered FP64 segments give bg_me2's results on each segment alone
- * bit for bit (the same device routines evaluate every event; only the
- * scheduling differs).  Other segments agree within the two paths' error
- * bars: the FP32 kernels may contract products into multiply-adds
+ * Colour-ordered FP64 segments with n <= 6 give bg_me2's results on each
+ * segment alone bit for bit (the same device routines evaluate every event;
+ * only the scheduling differs).  Other segments agree within the two paths'
+ * error bars: bg_me2 runs FP64 n = 7 in two stages (1/P^2 from prefix sums,
+ * another colour-sum order), the FP32 kernels may contract products into multiply-adds
  * differently, a colour-dressed event is split over 256 lanes here and over
  * 128 or 256 in bg_me2, and an FP32 event close to the check threshold of
  * bg_fp32_check_set may be re-evaluated in FP64 by one path only.

@@ -490,9 +490,27 @@ int contract_dispatch(bg_context* ctx, int n, int64_t E, const double* amp, doub
   return launch_status(bg::contract_valu(K, E, amp, ctx->C_dev[n], me2, accumulate, stream));
 }
 
+// Colour-ordered amplitudes [2][K][count] of events e0 .. e0 + count - 1:
+// the depth-first walk with shared prefixes, except FP64 at n >= 7, where
+// one straight path per ordering avoids the walk's register spills.
+int amplitudes_dispatch(bg_context* ctx, int n, bool fp32, int64_t E, int64_t e0, int64_t count,
+                        const double* mom, const int8_t* hel, int hconf, double* amp,
+                        hipStream_t stream) {
+  if (!fp32 && n >= 7) {
+    int st = ensure_perms(ctx, n);
+    if (st) return st;
+    return launch_status(bg::cobg_path_amplitudes(n, E, e0, count, mom, hel, hconf,
+                                                  ctx->perms_dev[n], amp, nullptr, nullptr,
+                                                  stream));
+  }
+  return launch_status(bg::cobg_amplitudes_range(n, fp32, E, e0, count, mom, hel, hconf, amp,
+                                                 stream));
+}
+
 // Events per chunk of the two-stage colour-ordered path at n = 8 (amplitudes
 // 11.5 KB per event in FP64 through the context workspace).
 constexpr int64_t kN8Chunk = (int64_t)1 << 17;  // events per two-stage n = 8 chunk (1.5 GB of amplitudes)
+constexpr int64_t kN7Chunk = (int64_t)1 << 18;  // n = 7: 0.5 GB
 
 }  // namespace
 
@@ -552,6 +570,7 @@ int bg_context_create(bg_context** out, int device, uint32_t flags) {
     // the colour matrices of the colour-ordered path, so that bg_me2_noalloc
     // never has to upload one
     for (int n = 4; n <= 7 && !st; ++n) st = ensure_colour(ctx, n);
+    if (!st) st = ensure_perms(ctx, 7);
     if (st) {
       bg_context_destroy(ctx);
       return st;
@@ -603,8 +622,8 @@ int bg_currents(bg_context* ctx, int n, int64_t E, const double* mom, const int8
   if (!mom || !hel || !amp) return BG_EINVAL;
   DeviceGuard g(ctx->device);
   if (!g.ok) return BG_EDEVICE;
-  return launch_status(bg::cobg_amplitudes(n, precision == BG_PREC_FP32_MIXED, E, mom, hel, 0,
-                                           amp, (hipStream_t)stream));
+  return amplitudes_dispatch(ctx, n, precision == BG_PREC_FP32_MIXED, E, 0, E, mom, hel, 0, amp,
+                             (hipStream_t)stream);
 }
 
 int bg_color_contract(bg_context* ctx, int n, int64_t E, const double* amp, double* me2,
@@ -631,26 +650,81 @@ static int ensure_counters(bg_context* ctx) {
 
 // fixed (may be null): use the static workspace, allocate nothing (the
 // colour matrix must then be uploaded already, see bg_context_create).
-// Colour-ordered n = 8 (K = 720, FP64): amplitudes of a chunk of events into
-// the workspace, then the colour sum through the relabelled storage; over
-// all 2^8 helicity configurations (accumulated) when hel is null.
-static int me2_cobg8(bg_context* ctx, const bg_request* r, hipStream_t stream) {
-  const int n = 8;
+// Colour-ordered FP64 at n = 7 (K = 120) and n = 8 (K = 720): the
+// amplitudes of a chunk of events into the workspace (one straight path per
+// ordering), then the colour sum (matrix cores with C in LDS at K = 120;
+// through the relabelled first row of C at K = 720); over all 2^n helicity
+// configurations (accumulated) when hel is null.  Each event's arithmetic
+// does not depend on the chunk, so any chunk size gives the same bits.
+// fixed: n = 7 only, chunks that fit the static workspace.
+static int me2_cobg_two_stage(bg_context* ctx, const bg_request* r, hipStream_t stream,
+                              const FixedWs* fixed) {
+  const int n = r->n;
   const int64_t E = r->n_events;
   const int64_t K = bg::factorial(n - 2);
-  const int64_t chunk = std::min<int64_t>(E, kN8Chunk);
-  int st = ensure_relabel(ctx, n);
-  if (!st) st = ensure_ws(ctx, sizeof(double) * 2 * (size_t)K * (size_t)chunk);
-  if (!st) st = ensure_part(ctx, chunk);
-  if (st) return st;
+  const size_t per_event = sizeof(double) * 2 * (size_t)K;
+  int64_t chunk;
+  double* ws;
+  int st = BG_OK;
+  if (fixed) {
+    if (n != 7 || !ctx->C_dev[n] || !ctx->perms_dev[n]) return BG_EUNSUPPORTED;
+    chunk = std::min<int64_t>(E, (int64_t)(fixed->scratch_bytes / per_event));
+    ws = fixed->scratch;
+  } else {
+    chunk = std::min<int64_t>(E, n == 7 ? kN7Chunk : kN8Chunk);
+    st = n == 8 ? ensure_relabel(ctx, n) : ensure_colour(ctx, n);
+    if (!st) st = ensure_ws(ctx, per_event * (size_t)chunk);
+    if (!st && n == 8) st = ensure_part(ctx, chunk);
+    if (st) return st;
+    ws = ctx->ws;
+  }
   const int nh = r->hel ? 1 : 1 << n;
   for (int64_t e0 = 0; e0 < E && !st; e0 += chunk) {
     const int64_t c = std::min<int64_t>(chunk, E - e0);
     for (int hc = 0; hc < nh && !st; ++hc) {
-      st = launch_status(bg::cobg_amplitudes_range(n, false, E, e0, c, r->mom, r->hel, hc,
-                                                   ctx->ws, stream));
+      st = amplitudes_dispatch(ctx, n, false, E, e0, c, r->mom, r->hel, hc, ws, stream);
       if (!st)
-        st = contract_dispatch(ctx, n, c, ctx->ws, r->me2 + e0, hc > 0 ? 1 : 0, stream, ctx->part);
+        st = contract_dispatch(ctx, n, c, ws, r->me2 + e0, hc > 0 ? 1 : 0, stream, ctx->part);
+    }
+  }
+  return st;
+}
+
+// FP64 re-evaluation of the n = 7 events listed by the FP32 check (count and
+// list on the device) through the same two stages as the FP64 path, so that
+// each listed event gets the FP64 path's result bit for bit: the listed
+// events' amplitudes into a compact workspace, then the matrix-core colour
+// sum written to their me2 (accumulated over the helicity configurations
+// when hel is null).  The list is covered in slices of the workspace's
+// capacity; slices past the list length return at once.
+static int fix_listed_two_stage(bg_context* ctx, const bg_request* r, const unsigned* count,
+                                const unsigned* list, hipStream_t stream, const FixedWs* fixed) {
+  const int n = 7;
+  const int64_t E = r->n_events;
+  const int64_t K = bg::factorial(n - 2);
+  const size_t per_event = sizeof(double) * 2 * (size_t)K;
+  int64_t slice;
+  double* ws;
+  int st = ensure_perms(ctx, n);
+  if (st) return st;
+  if (fixed) {
+    slice = std::min<int64_t>(E, (int64_t)(fixed->scratch_bytes / per_event));
+    ws = fixed->scratch;
+  } else {
+    slice = std::min<int64_t>(E, kN7Chunk);
+    st = ensure_ws(ctx, per_event * (size_t)slice);
+    if (st) return st;
+    ws = ctx->ws;
+  }
+  const int nh = r->hel ? 1 : 1 << n;
+  for (int64_t f0 = 0; f0 < E && !st; f0 += slice) {
+    const int64_t c = std::min<int64_t>(slice, E - f0);
+    for (int hc = 0; hc < nh && !st; ++hc) {
+      st = launch_status(bg::cobg_path_amplitudes(n, E, f0, c, r->mom, r->hel, hc,
+                                                  ctx->perms_dev[n], ws, list, count, stream));
+      if (!st)
+        st = launch_status(bg::contract_mfma((int)K, c, ws, ctx->C_dev[n], r->me2, hc > 0 ? 1 : 0,
+                                             stream, list, count, f0));
     }
   }
   return st;
@@ -661,9 +735,10 @@ static int me2_cobg(bg_context* ctx, const bg_request* r, uint32_t flags, hipStr
   const int n = r->n;
   if (n == 8) {
     if (fixed || r->precision != BG_PREC_FP64) return BG_EUNSUPPORTED;
-    return me2_cobg8(ctx, r, stream);
+    return me2_cobg_two_stage(ctx, r, stream, nullptr);
   }
   if (n > 8) return BG_EUNSUPPORTED;
+  if (n == 7 && r->precision == BG_PREC_FP64) return me2_cobg_two_stage(ctx, r, stream, fixed);
   const int64_t E = r->n_events;
   if (fixed && !ctx->Cb_dev[n]) return BG_EINVAL;
   int st = ensure_colour(ctx, n);
@@ -717,6 +792,7 @@ static int me2_cobg(bg_context* ctx, const bg_request* r, uint32_t flags, hipStr
                                         counter ? counter + 1 : nullptr, (int)grid, r->me2,
                                         check ? &ca : nullptr, stream));
   if (st || !check) return st;
+  if (n == 7) return fix_listed_two_stage(ctx, r, ca.count, ca.list, stream, fixed);
   return launch_status(bg::cobg_fix_me2(n, E, r->mom, r->hel, ctx->Cb_dev[n], scratch, ca.count,
                                         ca.list, (int)fix_grid, r->me2, stream));
 }
@@ -1007,7 +1083,7 @@ int grad_run(bg_context* ctx, const bg_request* r, const double* grad_me2, doubl
   if (st) return st;
   double* amp = ctx->ws;
   double* Y = ctx->ws + 2 * K * E;
-  st = launch_status(bg::cobg_amplitudes(n, fp32, E, r->mom, r->hel, 0, amp, s));
+  st = amplitudes_dispatch(ctx, n, fp32, E, 0, E, r->mom, r->hel, 0, amp, s);
   if (!st) st = launch_status(bg::contract_y((int)K, E, amp, ctx->C_dev[n], Y, r->me2, s));
   if (!st)
     st = launch_status(

@@ -20,7 +20,9 @@
 // as FP32 (entries are integers below 2^24 in modulus, also when doubled:
 // exact), rows padded with zeros to a multiple of 16 and the row stride odd
 // (K + 1) against bank conflicts.  The four lane groups of a column are
-// added with two cross-lane exchanges.
+// added with two cross-lane exchanges.  Listed form (idx non-null): column e
+// of the amplitude array belongs to event idx[first + e], written only for
+// first + e < *cnt.
 #include "bg_kernels.h"
 
 namespace bg {
@@ -63,7 +65,8 @@ struct MfmaShape {
 template <int K>
 __global__ void __launch_bounds__(MfmaShape<K>::kBlock) contract_mfma_kernel(
     int64_t E, const double* __restrict__ amp, const double* __restrict__ C,
-    double* __restrict__ me2, int accumulate) {
+    double* __restrict__ me2, int accumulate, const unsigned* __restrict__ idx,
+    const unsigned* __restrict__ cnt, int64_t first) {
   using S = MfmaShape<K>;
   static_assert(K % 4 == 0, "k steps of four");
   extern __shared__ float bg_contract_c[];  // C' [RP][KL], rows >= K zero
@@ -105,7 +108,16 @@ __global__ void __launch_bounds__(MfmaShape<K>::kBlock) contract_mfma_kernel(
   }
   q += __shfl_xor(q, 16);
   q += __shfl_xor(q, 32);
-  if (g == 0 && live) me2[e] = accumulate ? me2[e] + q : q;
+  if (g == 0 && live) {
+    if (idx) {
+      if (first + e < (int64_t)*cnt) {
+        const int64_t o = idx[first + e];
+        me2[o] = accumulate ? me2[o] + q : q;
+      }
+    } else {
+      me2[e] = accumulate ? me2[e] + q : q;
+    }
+  }
 }
 
 // Layout self-test: D = A x B with A[i][k] = i + 1 + 100 k and B[k][j] =
@@ -167,7 +179,8 @@ int contract_valu(int K, int64_t E, const double* amp, const double* C, double* 
 }
 
 int contract_mfma(int K, int64_t E, const double* amp, const double* C, double* me2,
-                  int accumulate, hipStream_t stream) {
+                  int accumulate, hipStream_t stream, const unsigned* idx, const unsigned* cnt,
+                  int64_t first) {
   if (E <= 0) return 0;
   switch (K) {
 #define BG_CASE(KK)                                                                           \
@@ -176,7 +189,7 @@ int contract_mfma(int K, int64_t E, const double* amp, const double* C, double* 
     const int64_t per_block = (S::kBlock / 64) * 16;                                          \
     const unsigned grid = (unsigned)((E + per_block - 1) / per_block);                        \
     hipLaunchKernelGGL(contract_mfma_kernel<KK>, dim3(grid), dim3(S::kBlock), S::lds, stream, \
-                       E, amp, C, me2, accumulate);                                           \
+                       E, amp, C, me2, accumulate, idx, cnt, first);                          \
     break;                                                                                    \
   }
     BG_CASE(24)

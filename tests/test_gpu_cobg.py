@@ -5,7 +5,8 @@ agreement with a 40-digit evaluation is pinned on the CPU.  Per event:
   * FP64 path: |got - ref| <= max(1e-12 |ref|, 12 (n - 2) u m) for every
     event (helpers.fp64_allowance: m is the event's magnitude, so the second
     term is the running error bound of any FP64 evaluation order; rigorous
-    but loose), the median relative error below 1e-14, and the p99 and max
+    but loose), the median relative error below 1e-14 (or ten times the FP64
+    oracle's own median where that is larger), and the p99 and max
     of the relative errors within 10x those of the FP64 oracle on the same
     events (helpers.fp64_comparable: two FP64 evaluations of the same
     conditioned function);
@@ -22,7 +23,7 @@ import pytest
 from bg_inputs import make_events, workload
 from oracle import cobg as ocobg
 from oracle import me2 as ome2
-from tests.helpers import (colour_matrix_n8, fp64_allowance, fp64_comparable, mhv_helicities,
+from tests.helpers import (U64, colour_matrix_n8, fp64_allowance, fp64_comparable, mhv_helicities,
                            nonvanishing, reference_cobg)
 
 torch = pytest.importorskip("torch")
@@ -87,7 +88,9 @@ def _check_sampled(got, mom, hel, precision, C=None):
              f"{np.mean((d > 1e-12 * np.abs(ref))[nz]):.1%}")
         _say(f"  FP64 oracle's own error: p99 {np.percentile(orel, 99):.2e} max {orel.max():.2e}")
         assert worst <= 1.0
-        assert np.median(rel) < 1e-14
+        # median: 1e-14, or ten times the FP64 oracle's own median where that
+        # is larger (n = 8: 720 orderings, more roundings per event)
+        assert np.median(rel) < max(1e-14, 10 * np.median(orel))
         assert fp64_comparable(rel, orel)
     else:
         assert rel.max() <= FP32_MAX
@@ -134,10 +137,12 @@ def test_helicity_sum_fused(api, n):
 def test_fused_equals_two_stage(api, n, precision):
     """bg_me2 (recursion and colour sum in one kernel) against bg_currents
     followed by bg_color_contract (amplitudes through memory, matrix cores at
-    n = 6): the same recursion, colour sums in a different order.  In FP64
-    the two agree to rounding of the sums; in FP32 the compiler may fuse a
-    product into a different multiply-add in the two kernels, so they agree
-    to FP32 rounding amplified by the event's cancellations."""
+    n = 6, 7; at n = 7 in FP64 one straight path per ordering with 1/P^2 from
+    prefix sums instead of the walk's subset table): colour sums in a
+    different order.  In FP64 the two agree within twice the running error
+    bound; in FP32 the compiler may fuse a product into a different
+    multiply-add in the two kernels, so they agree to FP32 rounding amplified
+    by the event's cancellations."""
     E = 1000 if n < 7 else 200
     mom, hel = _events(n, E, 3180 + n)
     dm, dh = _dev(mom), _dev(hel)
@@ -150,7 +155,18 @@ def test_fused_equals_two_stage(api, n, precision):
     rel = np.abs(fused - two)[nz] / np.abs(two[nz])
     _say(f"  max rel {rel.max():.2e} median {np.median(rel):.2e}")
     if precision == "fp64":
-        assert rel.max() < 1e-12
+        # both sides are FP64 evaluations within the running error bound
+        # 12 (n - 2) u m of the exact value (helpers.fp64_allowance), so they
+        # differ by at most twice it; checked on the events above 1e-12
+        assert np.median(rel) < 1e-14
+        d = np.abs(fused - two)
+        over = np.nonzero(nz & (d > 1e-12 * np.abs(two)))[0]
+        if over.size:
+            from oracle.conditioning import me2_cobg_magnitude
+            _, mag = me2_cobg_magnitude(mom[:, :, over], hel[:, over])
+            _say(f"  {over.size} events above 1e-12: max |d| / (2 x bound) "
+                 f"{np.max(d[over] / (2 * 12 * (n - 2) * U64 * mag)):.2e}")
+            assert np.all(d[over] <= 2 * 12 * (n - 2) * U64 * mag)
     else:
         assert np.median(rel) < 1e-6 and rel.max() < 1e-4
 
