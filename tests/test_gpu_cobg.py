@@ -338,3 +338,32 @@ def test_full_colour_n8_fp32_unsupported(api):
     mom, hel = _events(8, 4, 3830)
     with pytest.raises(RuntimeError):
         api.me2(_dev(mom), _dev(hel), mode="cobg", precision="fp32")
+
+
+def test_helicity_sum_n7_two_stage(api):
+    """hel = NULL at n = 7: FP64 runs the two-stage path once per helicity
+    configuration (accumulated), equal to the sum of the 128 per-
+    configuration results within rounding of the summation order; the
+    checked FP32 helicity sum (fused, listed events again in two FP64 stages)
+    within the FP32 bars of the module docstring."""
+    n, E = 7, 6
+    mom, _ = _events(n, E, 3840)
+    dm = _dev(mom)
+    _say(f"bg_me2 cobg n=7 helicity sum E={E}")
+    tot = api.me2(dm, None).cpu().numpy()
+    acc = np.zeros(E)
+    for h in range(1 << n):
+        hel = np.array([[1 if (h >> (n - 1 - i)) & 1 == 0 else -1] * E for i in range(n)], dtype=np.int8)
+        acc += api.me2(dm, _dev(hel)).cpu().numpy()
+    assert np.max(np.abs(tot - acc) / acc) < 1e-12
+    t32 = api.me2(dm, None, precision="fp32").cpu().numpy()
+    rel = np.abs(t32 - tot) / tot
+    _say(f"  fp32 helicity sum rel err max {rel.max():.2e}")
+    assert rel.max() <= FP32_MAX
+    default = api.fp32_check(n)
+    try:
+        api.fp32_check(n, 0.0)
+        all64 = api.me2(dm, None, precision="fp32").cpu().numpy()
+    finally:
+        api.fp32_check(n, default)
+    assert np.array_equal(all64, tot)
