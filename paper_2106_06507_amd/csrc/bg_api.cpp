@@ -496,13 +496,9 @@ int contract_dispatch(bg_context* ctx, int n, int64_t E, const double* amp, doub
 int amplitudes_dispatch(bg_context* ctx, int n, bool fp32, int64_t E, int64_t e0, int64_t count,
                         const double* mom, const int8_t* hel, int hconf, double* amp,
                         hipStream_t stream) {
-  if (!fp32 && n >= 7) {
-    int st = ensure_perms(ctx, n);
-    if (st) return st;
-    return launch_status(bg::cobg_path_amplitudes(n, E, e0, count, mom, hel, hconf,
-                                                  ctx->perms_dev[n], amp, nullptr, nullptr,
-                                                  stream));
-  }
+  if (!fp32 && n >= 7)
+    return launch_status(bg::cobg_path_amplitudes(n, E, e0, count, mom, hel, hconf, amp, nullptr,
+                                                  nullptr, stream));
   return launch_status(bg::cobg_amplitudes_range(n, fp32, E, e0, count, mom, hel, hconf, amp,
                                                  stream));
 }
@@ -570,7 +566,6 @@ int bg_context_create(bg_context** out, int device, uint32_t flags) {
     // the colour matrices of the colour-ordered path, so that bg_me2_noalloc
     // never has to upload one
     for (int n = 4; n <= 7 && !st; ++n) st = ensure_colour(ctx, n);
-    if (!st) st = ensure_perms(ctx, 7);
     if (st) {
       bg_context_destroy(ctx);
       return st;
@@ -667,7 +662,7 @@ static int me2_cobg_two_stage(bg_context* ctx, const bg_request* r, hipStream_t 
   double* ws;
   int st = BG_OK;
   if (fixed) {
-    if (n != 7 || !ctx->C_dev[n] || !ctx->perms_dev[n]) return BG_EUNSUPPORTED;
+    if (n != 7 || !ctx->C_dev[n]) return BG_EUNSUPPORTED;
     chunk = std::min<int64_t>(E, (int64_t)(fixed->scratch_bytes / per_event));
     ws = fixed->scratch;
   } else {
@@ -705,8 +700,7 @@ static int fix_listed_two_stage(bg_context* ctx, const bg_request* r, const unsi
   const size_t per_event = sizeof(double) * 2 * (size_t)K;
   int64_t slice;
   double* ws;
-  int st = ensure_perms(ctx, n);
-  if (st) return st;
+  int st = BG_OK;
   if (fixed) {
     slice = std::min<int64_t>(E, (int64_t)(fixed->scratch_bytes / per_event));
     ws = fixed->scratch;
@@ -720,8 +714,8 @@ static int fix_listed_two_stage(bg_context* ctx, const bg_request* r, const unsi
   for (int64_t f0 = 0; f0 < E && !st; f0 += slice) {
     const int64_t c = std::min<int64_t>(slice, E - f0);
     for (int hc = 0; hc < nh && !st; ++hc) {
-      st = launch_status(bg::cobg_path_amplitudes(n, E, f0, c, r->mom, r->hel, hc,
-                                                  ctx->perms_dev[n], ws, list, count, stream));
+      st = launch_status(bg::cobg_path_amplitudes(n, E, f0, c, r->mom, r->hel, hc, ws, list,
+                                                  count, stream));
       if (!st)
         st = launch_status(bg::contract_mfma((int)K, c, ws, ctx->C_dev[n], r->me2, hc > 0 ? 1 : 0,
                                              stream, list, count, f0));

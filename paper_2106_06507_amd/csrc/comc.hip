@@ -39,7 +39,7 @@
 #include <stdint.h>
 
 #include "cdbg_impl.h"
-#include "cobg_pair_impl.h"
+#include "cobg_path_impl.h"
 
 namespace bg {
 namespace comck {
@@ -328,68 +328,11 @@ __global__ void __launch_bounds__(kThreads) enumerate_kernel(int64_t E, const in
   orderings<N, 3>(f, 1u | (1u << a) | (1u << b), b, (uint32_t)a | ((uint32_t)b << 4), visit);
 }
 
-// Per-lane context for one ordering (see pairk::Ctx; 1/P^2 computed from the
-// prefix momenta, V4 dot products recomputed when the Dt table would not fit
-// in registers).
 template <int N, typename T, bool NODT, bool EST = false>
-struct Ctx {
-  static constexpr bool kRaw = false, kP64G = false, kLC = false, kEst = EST;
-  static constexpr bool kDirectP2 = true;
-  static constexpr bool kNoDt = NODT;
-  T* gl_slots;   // [6 (g-1) + x][lane]
-  double* p64;   // [2 (g-1) + c][lane]
-  T* tab;        // unused
-  int lane, pair, h;
-  T g0;
-  H<T> epsN;
-};
-
-template <int N, typename T, int D, class C>
-__device__ __forceinline__ void path(pairk::State<N, T>& s, C& c, uint32_t code, Cx<T>& top,
-                                     T& topb) {
-  constexpr int M = N - 1;
-  int g = (int)((code >> (4 * (D - 1))) & 15u);
-  g = g < 1 ? 1 : (g > N - 1 ? N - 1 : g);  // codes hold 1..N-1; keeps LDS reads in bounds
-  s.gl[D] = g;
-  const int base = 6 * (g - 1);
-#pragma unroll
-  for (int m = 0; m < 2; ++m) {
-    s.J[D][D].re[m] = c.gl_slots[(base + m) * 64 + c.lane];
-    s.J[D][D].im[m] = c.gl_slots[(base + 2 + m) * 64 + c.lane];
-    s.Pg[D].v[m] = c.gl_slots[(base + 4 + m) * 64 + c.lane];
-    s.P0[D].v[m] = s.P0[D - 1].v[m] + c.p64[(2 * (g - 1) + m) * 64 + c.lane];
-  }
-  if constexpr (C::kEst) {
-    // |p^0| of the gluon: the h = 0 lane holds it, the h = 1 lane takes it
-    // from its partner (both lanes run this exchange)
-    const double pg = c.p64[(2 * (g - 1)) * 64 + c.lane];
-    const double px = pairk::xswap(pg);
-    s.Ep[D] = s.Ep[D - 1] + (T)fabs(c.h == 0 ? pg : px);
-    s.Sb[D][D] = T(1);
-  }
-  pairk::set_gd<N, T, D, D>(s, c);
-  if constexpr (D == M - 1) {
-    // the ordering's last gluon closes it
-    int gl = (int)((code >> (4 * (N - 2))) & 15u);
-    gl = gl < 1 ? 1 : (gl > N - 1 ? N - 1 : gl);
-    const int lb = 6 * (gl - 1);
-#pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      c.epsN.re[m] = c.gl_slots[(lb + m) * 64 + c.lane];
-      c.epsN.im[m] = c.gl_slots[(lb + 2 + m) * 64 + c.lane];
-    }
-  }
-  pairk::build_column<N, T, D, D - 1>(s, c, 0, top, topb);
-  if constexpr (D < M - 1) path<N, T, D + 1>(s, c, code, top, topb);
-}
-
+using Ctx = pathk::Ctx<N, T, NODT, EST>;
 template <int N>
-struct AmpLds {
-  template <typename T>
-  static constexpr size_t bytes() {
-    return sizeof(T) * (size_t)6 * (N - 1) * 64 + sizeof(double) * (size_t)2 * (N - 1) * 64;
-  }
-};
+using AmpLds = pathk::Lds<N>;
+using pathk::path;
 
 // Pass 4: persistent blocks over 32-item tiles; amp[2 item + h] = plane h
 // of A(1, sigma) including the couplings; EST: bnd[item] = the running error
@@ -575,29 +518,19 @@ __global__ void __launch_bounds__(kThreads) reduce_listed_kernel(
 
 // Colour-ordered amplitudes A(1, sigma, n) of every ordering sigma for
 // events e0 .. e0 + count - 1 of an [n][4][E] input, into amp [2][K][count]
-// (the layout of cobg_pair_kernel), one straight path per ordering (path
-// above, 1/P^2 from the FP64 prefix momenta): the ranges of an ordering are
-// built again rather than shared with the orderings of the same prefix (13%
-// more vertex work at n = 7, 21% at n = 8), so only one path's state is live.
-// With FP64 at n >= 7 the depth-first walk's state overflows the register
-// file (0.45 KB/lane of spills at n = 7, 1.5 KB at n = 8, which at n = 8 go
-// to HBM); one path fits at n = 7 and spills a third as much at n = 8.
-// perms: the orderings' middle gluons [K][n-2] in lexicographic order.
-// idx (re-evaluation of listed events): column j holds event idx[e0 + j] for
-// e0 + j < *cnt (blocks past the list length return at once).
-template <int N, typename T, bool NODT>
+// (the layout of cobg_pair_kernel), one straight path per ordering
+// (cobg_path_impl.h).  idx (re-evaluation of listed events): column j holds
+// event idx[e0 + j] for e0 + j < *cnt (blocks past the list length return at
+// once).
+template <int N, typename T>
 __global__ void __launch_bounds__(64) cobg_path_kernel(int64_t E, int64_t e0, int64_t count,
                                                       const double* __restrict__ mom,
                                                       const int8_t* __restrict__ hel, int hconf,
-                                                      const uint8_t* __restrict__ perms,
                                                       double* __restrict__ amp,
                                                       const unsigned* __restrict__ idx,
                                                       const unsigned* __restrict__ cnt) {
   extern __shared__ __align__(16) unsigned char bg_path_lds[];
-  constexpr int K = (int)Factorial<N - 2>::value;
-  const int lane = threadIdx.x;
-  const int pair = lane >> 1, h = lane & 1;
-  const bool hi = h != 0;
+  const int pair = (int)threadIdx.x >> 1;
   const int64_t j = (int64_t)blockIdx.x * 32 + pair;
   bool live = j < count;
   int64_t e;
@@ -610,74 +543,16 @@ __global__ void __launch_bounds__(64) cobg_path_kernel(int64_t E, int64_t e0, in
   } else {
     e = e0 + (live ? j : count - 1);
   }
-  Ctx<N, T, NODT> c;
-  c.gl_slots = reinterpret_cast<T*>(bg_path_lds);
-  c.p64 = reinterpret_cast<double*>(c.gl_slots + (size_t)6 * (N - 1) * 64);
-  c.tab = nullptr;
-  c.lane = lane;
-  c.pair = pair;
-  c.h = h;
-  c.g0 = h == 0 ? T(1) : T(-1);
-  double scale = 1.0;
-#pragma unroll
-  for (int i = 0; i < N - 2; ++i) scale *= kGsOverSqrt2;
-  pairk::State<N, T> s;
-  // each lane reads back only its own LDS slots: no barrier needed
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    double p[4], er[4], ei[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) p[m] = mom[((int64_t)i * 4 + m) * E + e];
-    const int hh = hel ? (int)hel[(int64_t)i * E + e] : (((hconf >> (N - 1 - i)) & 1) ? -1 : 1);
-    polarization(p, hh, er, ei);
-    T v[6];
-    double ph[2];
-    if (hi) {
-      v[0] = (T)er[2]; v[1] = (T)er[3]; v[2] = (T)ei[2]; v[3] = (T)ei[3];
-      ph[0] = p[2]; ph[1] = p[3];
-    } else {
-      v[0] = (T)er[0]; v[1] = (T)er[1]; v[2] = (T)ei[0]; v[3] = (T)ei[1];
-      ph[0] = p[0]; ph[1] = p[1];
-    }
-    v[4] = (T)ph[0];
-    v[5] = (T)ph[1];
-    if (i == 0) {
-      s.J[0][0].re[0] = v[0];
-      s.J[0][0].re[1] = v[1];
-      s.J[0][0].im[0] = v[2];
-      s.J[0][0].im[1] = v[3];
-      s.Pg[0].v[0] = v[4];
-      s.Pg[0].v[1] = v[5];
-      s.P0[0].v[0] = ph[0];
-      s.P0[0].v[1] = ph[1];
-    } else {
-#pragma unroll
-      for (int x = 0; x < 6; ++x) c.gl_slots[(6 * (i - 1) + x) * 64 + lane] = v[x];
-      c.p64[(2 * (i - 1) + 0) * 64 + lane] = ph[0];
-      c.p64[(2 * (i - 1) + 1) * 64 + lane] = ph[1];
-    }
-  }
-  s.gl[0] = 0;
-#pragma unroll 1
-  for (int sig = 0; sig < K; ++sig) {  // wave-uniform
-    uint32_t code = (uint32_t)(N - 1) << (4 * (N - 2));  // the last gluon closes the ordering
-#pragma unroll
-    for (int k = 0; k < N - 2; ++k) code |= (uint32_t)perms[sig * (N - 2) + k] << (4 * k);
-    Cx<T> top;
-    T topb = T(0);
-    path<N, T, 1>(s, c, code, top, topb);
-    if (live) amp[((int64_t)h * K + sig) * count + j] = (double)(h == 0 ? top.re : top.im) * scale;
-  }
+  pathk::cobg_path_body<N, T>(bg_path_lds, E, mom, hel, hconf, e, live, amp, count, j);
 }
 
 template <int N, typename T>
 int path_launch(int64_t E, int64_t e0, int64_t count, const double* mom, const int8_t* hel,
-                int hconf, const uint8_t* perms, double* amp, const unsigned* idx,
-                const unsigned* cnt, hipStream_t stream) {
-  constexpr bool NODT = N >= 8;
+                int hconf, double* amp, const unsigned* idx, const unsigned* cnt,
+                hipStream_t stream) {
   const unsigned grid = (unsigned)((count + 31) / 32);
-  hipLaunchKernelGGL((cobg_path_kernel<N, T, NODT>), dim3(grid), dim3(64),
-                     (AmpLds<N>::template bytes<T>()), stream, E, e0, count, mom, hel, hconf, perms,
+  hipLaunchKernelGGL((cobg_path_kernel<N, T>), dim3(grid), dim3(64),
+                     (pathk::Lds<N>::template bytes<T>()), stream, E, e0, count, mom, hel, hconf,
                      amp, idx, cnt);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -774,16 +649,12 @@ int comc_amplitudes_listed(int n, int64_t E, const double* mom, const int8_t* he
 }
 
 int cobg_path_amplitudes(int n, int64_t E, int64_t e0, int64_t count, const double* mom,
-                         const int8_t* hel, int hconf, const uint8_t* perms, double* amp,
-                         const unsigned* idx, const unsigned* cnt, hipStream_t stream) {
+                         const int8_t* hel, int hconf, double* amp, const unsigned* idx,
+                         const unsigned* cnt, hipStream_t stream) {
   if (count <= 0) return 0;
   switch (n) {
-    case 7:
-      return comck::path_launch<7, double>(E, e0, count, mom, hel, hconf, perms, amp, idx, cnt,
-                                           stream);
-    case 8:
-      return comck::path_launch<8, double>(E, e0, count, mom, hel, hconf, perms, amp, idx, cnt,
-                                           stream);
+    case 7: return comck::path_launch<7, double>(E, e0, count, mom, hel, hconf, amp, idx, cnt, stream);
+    case 8: return comck::path_launch<8, double>(E, e0, count, mom, hel, hconf, amp, idx, cnt, stream);
     default: return -2;
   }
 }

@@ -24,6 +24,7 @@
 
 #include "cdbg_impl.h"
 #include "cobg_pair_impl.h"
+#include "cobg_path_impl.h"
 
 namespace bg {
 namespace fusedk {
@@ -33,7 +34,8 @@ constexpr int kTileEvents = 32;  // events per colour-ordered sub-tile (one per 
 // Where a tile keeps its amplitudes: up to n = 6 in LDS, unscaled, in the
 // recursion's type (at most 12 KB); at n = 7 (K = 120) in a block-private
 // FP64 scratch slice of device memory, which stays in L2 because the block
-// reuses it for every tile it takes.
+// reuses it for every tile it takes.  The amplitudes come from the
+// depth-first walk, except FP64 at n = 7: one straight path per ordering.
 template <int N>
 struct Cobg {
   static constexpr int K = (int)Factorial<N - 2>::value;
@@ -142,8 +144,19 @@ __device__ __forceinline__ void cobg_tile(unsigned char* lds, int64_t E,
                                                           0, 0, amp_lds, est);
       return lower_quadform<K>(Cb, amp_lds + (size_t)h * K * kTileEvents + pair, kTileEvents);
     } else {
-      pairk::cobg_pair_body<N, T, false, P64G, false, CHK>(lds, E, mom, hp, hc, e, true, blk,
-                                                           kTileEvents, pair, nullptr, est);
+      if constexpr (sizeof(T) == 8) {
+        // FP64 n = 7: one straight path per ordering (cobg_path_impl.h); the
+        // walk's FP64 state does not fit the registers there (FP32: the
+        // walk, 13% fewer vertices, is faster)
+        static_assert(pathk::Lds<N>::template bytes<T>() <=
+                          pairk::Lds<N>::template bytes<T, P64G>(),
+                      "the path's LDS fits the wave's region");
+        pathk::cobg_path_body<N, T, CHK>(lds, E, mom, hp, hc, e, true, blk, kTileEvents, pair,
+                                         est);
+      } else {
+        pairk::cobg_pair_body<N, T, false, P64G, false, CHK>(lds, E, mom, hp, hc, e, true, blk,
+                                                             kTileEvents, pair, nullptr, est);
+      }
       return lower_quadform<K>(Cb, blk + (size_t)h * K * kTileEvents + pair, kTileEvents);
     }
   };
