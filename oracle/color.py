@@ -181,6 +181,24 @@ def color_row_gellmann(n, row=0):
     return out
 
 
+def color_entry_gellmann(n, i, j):
+    """C(n)[i, j] from the definition with explicit F matrices (float), two
+    colour chains of 8^n entries: an entry check where a whole row would be
+    too slow (n = 8: 16.8 M complex entries per chain)."""
+    F = adjoint_F()
+    perms = middle_permutations(n)
+    k = n - 2
+
+    def chain(sigma):
+        M = None
+        for gl in sigma:
+            Fb = np.moveaxis(F.reshape((8,) + (1,) * (k - 1) + (8, 8)), 0, gl - 1)
+            M = Fb if M is None else np.einsum("...ij,...jk->...ik", M, Fb)
+        return M
+
+    return float(np.real(np.sum(chain(perms[i]) * np.conj(chain(perms[j])))))
+
+
 def color_matrix_gellmann(n):
     """C(n) from its definition with explicit F matrices (float, n <= 6)."""
     F = adjoint_F()

@@ -206,6 +206,21 @@ def test_golden_colour_matrix_n7_row0():
     assert stored[0, 0] == 6 ** 5 * 8
 
 
+@pytest.mark.slow
+def test_colour_matrix_n8_entries_equal_gellmann():
+    """Entries of the stored first row of C(8) from the definition with
+    explicit 8x8 F matrices (eq. color_coefficient_adjoint, chains of 8^8
+    entries): the diagonal, a non-zero and a zero off-diagonal entry, the
+    entry of the last ordering and six random ones.  This pins C(8) independently of the
+    trace-word method that the oracle and the library share."""
+    stored = np.loadtxt(f"{GOLDEN}/colour_matrix_n8_row0.txt", dtype=np.int64, ndmin=2)[0]
+    zero = int(np.nonzero(stored == 0)[0][0])
+    extra = np.random.default_rng(808).choice(np.arange(2, 719), 6, replace=False)
+    for j in [0, 1, zero, 719] + [int(x) for x in extra]:
+        g = color.color_entry_gellmann(8, 0, j)
+        assert abs(g - stored[j]) < 1e-9 * stored[0], (j, g, stored[j])
+
+
 def test_golden_colour_matrix_n8_row0():
     """The stored first row of C(8) (720 entries, about 30 s to recompute)
     on 40 sampled entries against the oracle's trace words; the diagonal
