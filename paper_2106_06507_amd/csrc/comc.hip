@@ -40,6 +40,7 @@
 
 #include "cdbg_impl.h"
 #include "cobg_path_impl.h"
+#include "cobg_quad_impl.h"
 
 namespace bg {
 namespace comck {
@@ -557,6 +558,97 @@ int path_launch(int64_t E, int64_t e0, int64_t count, const double* mom, const i
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// Pass 4 for FP64 at n >= 8 on quads (cobg_quad_impl.h): 16 items per
+// 64-lane block and round, one Lorentz component per lane.
+template <int N>
+__global__ void __launch_bounds__(64) amp_kernel_q(int64_t E, const double* __restrict__ mom,
+                                                  const int8_t* __restrict__ hel,
+                                                  const uint64_t* __restrict__ items,
+                                                  const uint64_t* __restrict__ total_p,
+                                                  double* __restrict__ amp,
+                                                  const unsigned* __restrict__ sel,
+                                                  const unsigned* __restrict__ sel_count) {
+  extern __shared__ __align__(16) unsigned char bg_quad_lds[];
+  const unsigned total = sel ? *sel_count : (unsigned)*total_p;  // below 2^31 (host check)
+  const int lane = threadIdx.x;
+  const int quad = lane >> 2, cc = lane & 3;
+  double scale = 1.0;
+#pragma unroll
+  for (int i = 0; i < N - 2; ++i) scale *= kGsOverSqrt2;
+  for (unsigned base = blockIdx.x * 16u; base < total; base += gridDim.x * 16u) {
+    const unsigned slot = base + quad < total ? base + quad : total - 1;
+    const unsigned it = sel ? sel[slot] : slot;
+    const uint64_t item = items[it];
+    int64_t e = (int64_t)(item >> 32);
+    e = e < E ? e : E - 1;  // items always hold e < E; the clamp keeps reads in bounds regardless
+    quadk::State<N> s;
+    quadk::Ctx c;
+    quadk::setup<N>(s, c, reinterpret_cast<double*>(bg_quad_lds), E, mom, hel, 0, e);
+    quadk::Q top;
+    quadk::path<N, 1>(s, c, (uint32_t)item, top);
+    if (base + quad < total && cc < 2) amp[2 * (size_t)it + cc] = (cc == 0 ? top.re : top.im) * scale;
+  }
+}
+
+template <int N>
+int amp_launch_q(int64_t E, const double* mom, const int8_t* hel, const uint64_t* items,
+                 const uint64_t* total, double* amp, const unsigned* sel, const unsigned* sel_count,
+                 int grid, hipStream_t stream) {
+  hipLaunchKernelGGL((amp_kernel_q<N>), dim3(2 * grid), dim3(64), quadk::Lds<N>::bytes(), stream,
+                     E, mom, hel, items, total, amp, sel, sel_count);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// Colour-ordered amplitudes of every ordering on quads (FP64, n = 8): as
+// cobg_path_kernel, 16 events per block.
+template <int N>
+__global__ void __launch_bounds__(64) cobg_path_kernel_q(int64_t E, int64_t e0, int64_t count,
+                                                        const double* __restrict__ mom,
+                                                        const int8_t* __restrict__ hel, int hconf,
+                                                        double* __restrict__ amp,
+                                                        const unsigned* __restrict__ idx,
+                                                        const unsigned* __restrict__ cnt) {
+  extern __shared__ __align__(16) unsigned char bg_quad_lds[];
+  constexpr int K = (int)Factorial<N - 2>::value;
+  const int lane = threadIdx.x;
+  const int quad = lane >> 2, cc = lane & 3;
+  const int64_t j = (int64_t)blockIdx.x * 16 + quad;
+  bool live = j < count;
+  int64_t e;
+  if (idx) {
+    const int64_t tot = (int64_t)*cnt;
+    const int64_t b0 = e0 + (int64_t)blockIdx.x * 16;
+    if (b0 >= tot) return;  // the whole block (uniform)
+    live = live && e0 + j < tot;
+    e = (int64_t)idx[live ? e0 + j : b0];
+  } else {
+    e = e0 + (live ? j : count - 1);
+  }
+  double scale = 1.0;
+#pragma unroll
+  for (int i = 0; i < N - 2; ++i) scale *= kGsOverSqrt2;
+  quadk::State<N> s;
+  quadk::Ctx c;
+  quadk::setup<N>(s, c, reinterpret_cast<double*>(bg_quad_lds), E, mom, hel, hconf, e);
+#pragma unroll 1
+  for (int sig = 0; sig < K; ++sig) {  // wave-uniform
+    quadk::Q top;
+    quadk::path<N, 1>(s, c, pathk::lex_code<N>(sig), top);
+    if (live && cc < 2)
+      amp[((int64_t)cc * K + sig) * count + j] = (cc == 0 ? top.re : top.im) * scale;
+  }
+}
+
+template <int N>
+int path_launch_q(int64_t E, int64_t e0, int64_t count, const double* mom, const int8_t* hel,
+                  int hconf, double* amp, const unsigned* idx, const unsigned* cnt,
+                  hipStream_t stream) {
+  const unsigned grid = (unsigned)((count + 15) / 16);
+  hipLaunchKernelGGL((cobg_path_kernel_q<N>), dim3(grid), dim3(64), quadk::Lds<N>::bytes(), stream,
+                     E, e0, count, mom, hel, hconf, amp, idx, cnt);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 template <int N, typename T, bool EST = false>
 int amp_launch(int64_t E, const double* mom, const int8_t* hel, const uint64_t* items,
                const uint64_t* total, double* amp, float* bnd, const unsigned* sel,
@@ -628,8 +720,10 @@ int comc_amplitudes(int n, bool fp32, int64_t E, const double* mom, const int8_t
                     const uint64_t* items, const uint64_t* total, double* amp, float* bnd,
                     int grid, hipStream_t stream) {
 #define C_(NN)                                                                              \
-  (!fp32 ? comck::amp_launch<NN, double>(E, mom, hel, items, total, amp, nullptr, nullptr,   \
-                                         nullptr, grid, stream)                              \
+  (!fp32 ? (NN >= 8 ? comck::amp_launch_q<NN>(E, mom, hel, items, total, amp, nullptr,       \
+                                              nullptr, grid, stream)                         \
+                    : comck::amp_launch<NN, double>(E, mom, hel, items, total, amp, nullptr, \
+                                                    nullptr, nullptr, grid, stream))         \
    : bnd ? comck::amp_launch<NN, float, true>(E, mom, hel, items, total, amp, bnd, nullptr,  \
                                               nullptr, grid, stream)                         \
          : comck::amp_launch<NN, float>(E, mom, hel, items, total, amp, nullptr, nullptr,    \
@@ -641,9 +735,11 @@ int comc_amplitudes(int n, bool fp32, int64_t E, const double* mom, const int8_t
 int comc_amplitudes_listed(int n, int64_t E, const double* mom, const int8_t* hel,
                            const uint64_t* items, const unsigned* sel, const unsigned* sel_count,
                            double* amp, int grid, hipStream_t stream) {
-#define C_(NN)                                                                              \
-  comck::amp_launch<NN, double>(E, mom, hel, items, nullptr, amp, nullptr, sel, sel_count, \
-                                grid, stream)
+#define C_(NN)                                                                               \
+  (NN >= 8 ? comck::amp_launch_q<NN>(E, mom, hel, items, nullptr, amp, sel, sel_count, grid,  \
+                                     stream)                                                  \
+           : comck::amp_launch<NN, double>(E, mom, hel, items, nullptr, amp, nullptr, sel,    \
+                                           sel_count, grid, stream))
   BG_COMC_SWITCH(C_)
 #undef C_
 }
@@ -654,7 +750,7 @@ int cobg_path_amplitudes(int n, int64_t E, int64_t e0, int64_t count, const doub
   if (count <= 0) return 0;
   switch (n) {
     case 7: return comck::path_launch<7, double>(E, e0, count, mom, hel, hconf, amp, idx, cnt, stream);
-    case 8: return comck::path_launch<8, double>(E, e0, count, mom, hel, hconf, amp, idx, cnt, stream);
+    case 8: return comck::path_launch_q<8>(E, e0, count, mom, hel, hconf, amp, idx, cnt, stream);
     default: return -2;
   }
 }

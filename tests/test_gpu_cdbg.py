@@ -87,7 +87,7 @@ def _check(got, ref, mom, hel, col, precision, label):
 @pytest.mark.parametrize("n", [4, 5, 6, 7, 8, 9])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_valid_flows_match_oracle(api, n, precision):
-    E = {4: 130, 5: 130, 6: 100, 7: 40, 8: 12, 9: 8}[n]
+    E = {4: 130, 5: 130, 6: 100, 7: 64, 8: 48, 9: 40}[n]
     ev = make_events(n, E, seed=5000 + n, cuts=True)
     col = valid_colours(n, E, np.random.default_rng(50 + n))
     _say(f"bg_me2 cdbg {precision} n={n} E={E}")
