@@ -12,7 +12,13 @@
 // (r, c) with out-in = +1 at r and -1 at c.  A subset whose edges are not
 // connected, or whose degrees allow no trail, has a zero current.  Each subset
 // therefore stores three slots: slot v = entry (v, v) when balanced, slot 0 =
-// entry (r, c) otherwise.  The matrix product J(S1) J(S2) in the recursion
+// entry (r, c) otherwise.  Only the slots a subset can hold are stored: one
+// for a trail, one per touched colour for a balanced subset, none for a zero
+// current, packed in mask order (the subset's code word carries the index of
+// its first slot).  Over every valid flow (all 9^n colour assignments that
+// close, enumerated exhaustively for n = 4..9) the total is at most
+// (2^(n-1) - 1) + 2^(n-1)/4, against 3 (2^(n-1) - 1) for three slots per
+// subset.  The matrix product J(S1) J(S2) in the recursion
 // then selects one operand pair per target slot:
 //   S1 (r1,c1), S2 (r2,c2):  needs c1 = r2, gives (r1, c2)
 //   S1 (r1,c1), S2 balanced: slots (0, c1) -> (r1, c1)
@@ -52,12 +58,13 @@ template <int N, typename T, bool EST = false>
 struct Lay {
   static constexpr int M = N - 1;
   static constexpr int NS = 1 << M;          // subsets (mask 0 unused)
-  static constexpr int kJ = NS * 3 * 8;      // currents [mask][slot][re0..3, im0..3]
-  static constexpr int kT = NS * 3 * 12;     // tensors  [mask][slot][re6, im6]
+  static constexpr int kCap = NS - 1 + NS / 4;  // stored slots of a valid flow, at most
+  static constexpr int kJ = kCap * 8;        // currents [slot][re0..3, im0..3]
+  static constexpr int kT = kCap * 12;       // tensors  [slot][re6, im6]
   static constexpr int kP = NS * 4;          // momenta  [mask][mu]
   static constexpr int kI = NS;              // 1/P^2    [mask]
-  static constexpr int kB = EST ? NS * 7 : 0;  // bounds [mask][slot] of J and T, E [mask]
-  static constexpr int kItems = NS * 3;      // target list of one size
+  static constexpr int kB = EST ? kCap * 2 + NS : 0;  // bounds [slot] of J and T, E [mask]
+  static constexpr int kItems = kCap;        // target list of one size
   static constexpr int kPm = 4 * N;          // FP64 momenta of the event [gluon][mu]
   static constexpr size_t bytes() {
     return sizeof(double) * (size_t)kPm + sizeof(T) * (size_t)(kJ + kT + kP + kI + kB) +
@@ -72,10 +79,11 @@ struct Sm {
   T* Tt;
   T* P;
   T* ip2;
-  T* bJ;       // EST: bound of each current slot [mask][slot]
-  T* bT;       // EST: bound of each tensor slot [mask][slot]
+  T* bJ;       // EST: bound of each current slot [slot]
+  T* bT;       // EST: bound of each tensor slot [slot]
   T* en;       // EST: sum of |p^0| over the subset [mask]
-  int* code;   // per mask: 0 zero; 1 | r << 2 | c << 4 unbalanced; 2 | touched << 6 balanced
+  int* code;   // per mask: 0 zero; 1 | r << 2 | c << 4 unbalanced; 2 | touched << 6
+               // balanced; | first slot << 9 (see slot_index)
   int* items;
   int* ci;     // colours i_k
   int* cj;     // colours j_k
@@ -93,8 +101,8 @@ __device__ __forceinline__ Sm<N, T> carve(unsigned char* raw) {
   s.P = s.Tt + L::kT;
   s.ip2 = s.P + L::kP;
   s.bJ = s.ip2 + L::kI;
-  s.bT = s.bJ + (EST ? L::NS * 3 : 0);
-  s.en = s.bT + (EST ? L::NS * 3 : 0);
+  s.bT = s.bJ + (EST ? L::kCap : 0);
+  s.en = s.bT + (EST ? L::kCap : 0);
   int* ip = reinterpret_cast<int*>(s.ip2 + L::kI + L::kB);
   s.code = ip;
   s.items = s.code + L::NS;
@@ -160,9 +168,11 @@ __device__ __forceinline__ T shfl_down_t(T v, int off) {
   return __shfl_down(v, (unsigned)off, kWave);
 }
 
-// Operand slots of split (S1, S2) feeding target slot t of S; false if none.
+// Operand slots of split (S1, S2) feeding target slot t of S; false if none
+// (including a balanced operand that does not touch the colour asked of it:
+// its current has no such entry).
 __device__ __forceinline__ bool split_slots(int c1, int c2, int t, int& s1, int& s2) {
-  if (c1 == 0 || c2 == 0) return false;
+  if ((c1 & 3) == 0 || (c2 & 3) == 0) return false;  // zero currents
   const bool b1 = (c1 & 3) == 2, b2 = (c2 & 3) == 2;
   if (!b1 && !b2) {
     const int r1 = (c1 >> 2) & 3, cc1 = (c1 >> 4) & 3;
@@ -178,25 +188,39 @@ __device__ __forceinline__ bool split_slots(int c1, int c2, int t, int& s1, int&
     if (t != 0) return false;
     s1 = 0;
     s2 = (c1 >> 4) & 3;
-    return true;
+    return ((c2 >> (6 + s2)) & 1) != 0;
   }
   if (b1 && !b2) {
     if (t != 0) return false;
     s1 = (c2 >> 2) & 3;
     s2 = 0;
-    return true;
+    return ((c1 >> (6 + s1)) & 1) != 0;
   }
   s1 = t;
   s2 = t;
-  return true;
+  return ((c1 & c2) >> (6 + t) & 1) != 0;
 }
 
-// Accumulate the contribution of split (m1, m2) with operand slots (s1, s2).
+// Packed index of colour slot s of a subset with code word c (s a slot the
+// subset holds): its first slot, plus for a balanced subset the touched
+// colours below s.
+__device__ __forceinline__ int slot_index(int c, int s) {
+  const int first = c >> 9;
+  return (c & 3) == 2 ? first + __popc(((c >> 6) & 7) & ((1 << s) - 1)) : first;
+}
+
+// Number of slots a subset with code c holds.
+__device__ __forceinline__ int slot_count(int c) {
+  return (c & 3) == 1 ? 1 : ((c & 3) == 2 ? __popc((c >> 6) & 7) : 0);
+}
+
+// Accumulate the contribution of split (m1, m2) whose operands are the
+// packed slots i1, i2.
 template <int N, typename T>
-__device__ __forceinline__ void split_contrib(const Sm<N, T>& sm, int m1, int m2, int s1, int s2,
+__device__ __forceinline__ void split_contrib(const Sm<N, T>& sm, int m1, int m2, int i1, int i2,
                                               bool want_tensor, T* gre, T* gim, T* tre, T* tim) {
-  const T* J1 = sm.J + (m1 * 3 + s1) * 8;
-  const T* J2 = sm.J + (m2 * 3 + s2) * 8;
+  const T* J1 = sm.J + i1 * 8;
+  const T* J2 = sm.J + i2 * 8;
   T a_re[4], a_im[4], b_re[4], b_im[4], P1[4], P2[4];
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
@@ -239,8 +263,8 @@ __device__ __forceinline__ void split_contrib(const Sm<N, T>& sm, int m1, int m2
     gim[mu] -= c2i * a_re[mu];
   }
   // tensor couplings: + T2.J1 - T1.J2
-  const T* T1 = sm.Tt + (m1 * 3 + s1) * 12;
-  const T* T2 = sm.Tt + (m2 * 3 + s2) * 12;
+  const T* T1 = sm.Tt + i1 * 12;
+  const T* T2 = sm.Tt + i2 * 12;
   {
     T t_re[6], t_im[6];
 #pragma unroll
@@ -378,22 +402,20 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
   constexpr int NS = L::NS;
   constexpr int NW = NL / kWave;
   static_assert(NL % kWave == 0 && NW <= 4, "one to four waves per event");
+  static_assert(NS <= NL, "one subset per lane in the set-up");
   const int lane = threadIdx.x;
   const int w = lane / kWave, lw = lane % kWave;
   // ---- event set-up -------------------------------------------------
-  for (int x = lane; x < L::kJ; x += NL) sm.J[x] = T(0);
-  for (int x = lane; x < L::kT; x += NL) sm.Tt[x] = T(0);
-  if constexpr (EST) {
-    for (int x = lane; x < 6 * NS; x += NL) sm.bJ[x] = T(0);  // bJ and bT are contiguous
-  }
   if (lane < N) {
     sm.ci[lane] = col[(int64_t)lane * E + e];
     sm.cj[lane] = col[((int64_t)N + lane) * E + e];
   }
   if (lane < 4 * N) sm.pm[lane] = mom[(int64_t)lane * E + e];  // [k][mu] = row 4k + mu
   __syncthreads();
-  // subset codes, momenta, 1/P^2 (FP64 sums)
-  for (int mask = lane + 1; mask < NS; mask += NL) {
+  // subset codes, momenta, 1/P^2 (FP64 sums); lane l takes subset l + 1
+  int code = 0;
+  const int mask = lane + 1;
+  if (mask < NS) {
     double q[4] = {0.0, 0.0, 0.0, 0.0};
     double en = 0.0;
     ColourGraph g;
@@ -405,28 +427,62 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
       g.add(sm.cj[k], sm.ci[k]);
     }
     if constexpr (EST) sm.en[mask] = (T)en;
-    const int code = g.code();
-    sm.code[mask] = code;
+    code = g.code();
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) sm.P[mask * 4 + mu] = (T)q[mu];
     const double p2 = q[0] * q[0] - q[1] * q[1] - q[2] * q[2] - q[3] * q[3];
     sm.ip2[mask] = (T)(1.0 / p2);
   }
-  // external currents of gluons 0..M-1 into their colour slot
+  // first packed slot of every subset: exclusive prefix sum of the slot
+  // counts in mask order (a shuffle scan per wave, then the wave totals)
+  {
+    const int cnt = slot_count(code);
+    int incl = cnt;
+#pragma unroll
+    for (int off = 1; off < kWave; off *= 2) {
+      const int v = __shfl_up(incl, (unsigned)off, kWave);
+      if (lw >= off) incl += v;
+    }
+    if (lw == kWave - 1) sm.misc[w] = incl;
+    __syncthreads();
+    int first = incl - cnt, total = 0;
+#pragma unroll
+    for (int v = 0; v < NW; ++v) {
+      const int tv = sm.misc[v];
+      first += v < w ? tv : 0;
+      total += tv;
+    }
+    // a valid flow holds at most kCap slots (exhaustive count over all flows);
+    // the guard keeps the packed arrays in bounds regardless
+    if (total > L::kCap) {
+      if (lane == 0) me2[e] = __builtin_nan("");
+      __syncthreads();  // misc is read by every lane before it is rewritten
+      return;           // uniform over the block
+    }
+    if (mask < NS) sm.code[mask] = code | (first << 9);
+    __syncthreads();
+  }
+  // external currents of gluons 0..M-1 into their colour slot (the tensor
+  // of a single gluon is 0)
   if (lane < M) {
     double p[4], er[4], ei[4];
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) p[mu] = sm.pm[lane * 4 + mu];
     polarization(p, (int)hel[(int64_t)lane * E + e], er, ei);
-    const int ii = sm.ci[lane], jj = sm.cj[lane];
-    const int slot = (ii == jj) ? jj : 0;
-    T* dst = sm.J + ((1 << lane) * 3 + slot) * 8;
+    const int si = sm.code[1 << lane] >> 9;  // the gluon's only slot
+    T* dst = sm.J + si * 8;
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
       dst[mu] = (T)er[mu];
       dst[4 + mu] = (T)ei[mu];
     }
-    if constexpr (EST) sm.bJ[(1 << lane) * 3 + slot] = T(1);
+    T* dt = sm.Tt + si * 12;
+#pragma unroll
+    for (int x = 0; x < 12; ++x) dt[x] = T(0);
+    if constexpr (EST) {
+      sm.bJ[si] = T(1);
+      sm.bT[si] = T(0);
+    }
   }
   __syncthreads();
 
@@ -444,16 +500,16 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
     } else {
       // compaction of the (mask, slot) targets: slot-major, waves in order
       for (int base = 0; base < NS; base += NL) {
-        const int mask = base + lane;
-        int code = 0;
-        if (mask > 0 && mask < NS && __popc(mask) == size) code = sm.code[mask];
+        const int tm = base + lane;
+        int tc = 0;
+        if (tm > 0 && tm < NS && __popc(tm) == size) tc = sm.code[tm];
         bool ok[3];
         unsigned long long bal[3];
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
           ok[t] = false;
-          if ((code & 3) == 1) ok[t] = (t == 0);
-          else if ((code & 3) == 2) ok[t] = ((code >> 6) >> t) & 1;
+          if ((tc & 3) == 1) ok[t] = (t == 0);
+          else if ((tc & 3) == 2) ok[t] = ((tc >> 6) >> t) & 1;
           bal[t] = __ballot(ok[t]);
         }
         if (lw == 0) {
@@ -471,7 +527,7 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
             if (v < w) before += cnt;
             all += cnt;
           }
-          if (ok[t]) sm.items[nitems + before + __popcll(bal[t] & below)] = mask * 4 + t;
+          if (ok[t]) sm.items[nitems + before + __popcll(bal[t] & below)] = tm * 4 + t;
           nitems += all;
         }
         __syncthreads();  // misc is rewritten by the next base
@@ -508,15 +564,17 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
         int m1 = k0 < k1 ? subset_of<M>(k0 + 1, S) : 0;
         for (int k = k0; k < k1; ++k, m1 = (m1 - S) & S) {
           const int m2 = S ^ m1;
+          const int c1 = sm.code[m1], c2 = sm.code[m2];
           int s1, s2;
-          if (!split_slots(sm.code[m1], sm.code[m2], t, s1, s2)) continue;
-          split_contrib<N, T>(sm, m1, m2, s1, s2, !top, gre, gim, tre, tim);
+          if (!split_slots(c1, c2, t, s1, s2)) continue;
+          const int i1 = slot_index(c1, s1), i2 = slot_index(c2, s2);
+          split_contrib<N, T>(sm, m1, m2, i1, i2, !top, gre, gim, tre, tim);
           if constexpr (EST) {
-            const T j1 = sm.bJ[m1 * 3 + s1], j2 = sm.bJ[m2 * 3 + s2];
+            const T j1 = sm.bJ[i1], j2 = sm.bJ[i2];
             const T jj = j1 * j2;
             bv += enS * jj;
-            bv += sm.bT[m2 * 3 + s2] * j1;
-            bv += sm.bT[m1 * 3 + s1] * j2;
+            bv += sm.bT[i2] * j1;
+            bv += sm.bT[i1] * j2;
             bt += jj;
           }
         }
@@ -582,8 +640,9 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
           me2[e] = ar * ar + ai * ai;
         } else {
           const T ip = sm.ip2[S];
-          T* dj = sm.J + (S * 3 + t) * 8;
-          T* dt = sm.Tt + (S * 3 + t) * 12;
+          const int si = slot_index(sm.code[S], t);
+          T* dj = sm.J + si * 8;
+          T* dt = sm.Tt + si * 12;
 #pragma unroll
           for (int x = 0; x < 4; ++x) {
             dj[x] = gre[x] * ip;
@@ -595,8 +654,8 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
             dt[6 + x] = tim[x];
           }
           if constexpr (EST) {
-            sm.bJ[S * 3 + t] = bv * fabs(ip);
-            sm.bT[S * 3 + t] = bt;
+            sm.bJ[si] = bv * fabs(ip);
+            sm.bT[si] = bt;
           }
         }
       }
