@@ -233,8 +233,11 @@ int bg_fp32_check_get(bg_context* ctx, int mode, int n, float* tau);
 int bg_me2_grad(bg_context* ctx, const bg_request* req, const double* grad_me2,
                 double* grad_mom, void* stream);
 
-/* Several requests (mixed multiplicities, uneven event counts) in ONE
- * persistent kernel launch.  Mode BG_MODE_AUTO picks COBG for n <= 7 and CDBG
+/* Several requests (mixed multiplicities, uneven event counts) in one
+ * persistent kernel launch per pass, or (config split_kinds, the default) one
+ * per segment kind: colour-ordered segments, then colour-dressed ones, each
+ * with the LDS and register budget of its own kind; either way a fixed
+ * sequence of launches that a graph can record.  Mode BG_MODE_AUTO picks COBG for n <= 7 and CDBG
  * for n >= 8 per segment; explicit modes are honoured (COBG needs n <= 7).
  * Every segment must have the same precision, hel non-NULL, me2 non-NULL when
  * its n_events > 0, and col for CDBG; at most BG_BATCH_MAX_SEGS segments.
@@ -250,8 +253,8 @@ int bg_me2_grad(bg_context* ctx, const bg_request* req, const double* grad_me2,
  * segment's mode and n; BG_FLAG_FP32_UNCHECKED in a segment's flags turns it
  * off for that segment): an FP32 pass lists the events, a one-block kernel
  * turns the per-segment counts into a tile table on the device, and an FP64
- * pass of the same persistent kernel re-evaluates them; all three launches
- * can be recorded into a graph.
+ * pass of the same persistent kernel re-evaluates them (per kind when split);
+ * every launch can be recorded into a graph.
  * The events are cut into tiles (config below), the tiles are ordered by
  * decreasing estimated cost and the blocks of the persistent grid take them
  * from an atomic queue.
@@ -278,16 +281,22 @@ typedef struct bg_batch_config {
     int waves_per_simd;     /* register budget of the kernel: 1 = all registers the
                                largest branch wants (one block per CU), 2 = at most 256
                                per lane (two blocks per CU, some spilling at n = 7) */
+    int split_kinds;        /* 0 = one persistent launch over every tile; 1 = one over
+                               the colour-ordered tiles (with waves_per_simd), then one
+                               over the colour-dressed tiles, each sized by the LDS and
+                               registers of its own kind (the dressed kernel always at
+                               budget 2), so that a dressed segment does not run at the
+                               occupancy the colour-ordered branches need */
 } bg_batch_config;
 
-/* Current batch config of `precision` (defaults: 0, 128, 256, 2) into *out (host). */
+/* Current batch config of `precision` (defaults: 0, 128, 256, 2, 1) into *out (host). */
 int bg_batch_config_get(bg_context* ctx, int precision, bg_batch_config* out);
 /* Set it; BG_EINVAL for values outside the ranges above. */
 int bg_batch_config_set(bg_context* ctx, int precision, const bg_batch_config* cfg);
 
 /* Autotuner: times bg_me2_batch on the given segments (their outputs are
- * written) for candidate configs -- register budget {2, 1} x blocks per CU
- * {max, 1}, then
+ * written) for candidate configs -- split {1, 0} x register budget {2, 1} x
+ * blocks per CU {max, 1}, then
  * colour-ordered tile {128, 256, 512, 1024}, then colour-dressed tile
  * {256, 512, 1024}, each stage keeping the best -- with HIP events on
  * `stream`, and installs the fastest config for the segments' precision.

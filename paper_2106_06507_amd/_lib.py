@@ -44,6 +44,7 @@ class bg_batch_config(ctypes.Structure):
         ("cobg_tile_events", ctypes.c_int),
         ("cdbg_tile_events", ctypes.c_int),
         ("waves_per_simd", ctypes.c_int),
+        ("split_kinds", ctypes.c_int),
     ]
 
 

@@ -251,7 +251,8 @@ def batch_config(precision="fp32", ctx=None):
     c = bg_batch_config()
     check(lib().bg_batch_config_get(ctx.handle, _PREC[precision], ctypes.byref(c)), "bg_batch_config_get")
     return {"blocks_per_cu": c.blocks_per_cu, "cobg_tile_events": c.cobg_tile_events,
-            "cdbg_tile_events": c.cdbg_tile_events, "waves_per_simd": c.waves_per_simd}
+            "cdbg_tile_events": c.cdbg_tile_events, "waves_per_simd": c.waves_per_simd,
+            "split_kinds": c.split_kinds}
 
 
 def set_batch_config(precision="fp32", ctx=None, **cfg):
@@ -259,7 +260,7 @@ def set_batch_config(precision="fp32", ctx=None, **cfg):
     cur = batch_config(precision, ctx)
     cur.update(cfg)
     c = bg_batch_config(cur["blocks_per_cu"], cur["cobg_tile_events"], cur["cdbg_tile_events"],
-                        cur["waves_per_simd"])
+                        cur["waves_per_simd"], cur["split_kinds"])
     check(lib().bg_batch_config_set(ctx.handle, _PREC[precision], ctypes.byref(c)), "bg_batch_config_set")
 
 
@@ -273,7 +274,8 @@ def batch_tune(segments, precision="fp32", ctx=None):
     check(lib().bg_me2_batch_tune(ctx.handle, arr, len(outs), ctypes.byref(c), ctypes.byref(ms),
                                   _stream(dev)), "bg_me2_batch_tune")
     return {"blocks_per_cu": c.blocks_per_cu, "cobg_tile_events": c.cobg_tile_events,
-            "cdbg_tile_events": c.cdbg_tile_events, "waves_per_simd": c.waves_per_simd}, ms.value
+            "cdbg_tile_events": c.cdbg_tile_events, "waves_per_simd": c.waves_per_simd,
+            "split_kinds": c.split_kinds}, ms.value
 
 
 class BatchGraph:

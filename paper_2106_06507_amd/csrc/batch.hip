@@ -1,6 +1,22 @@
-// Fused colour-ordered kernel (recursion and colour sum in one pass) and the
-// persistent mixed-multiplicity batch kernel.  Tile routines: fused_impl.h.
-#include "fused_impl.h"
+// Fused colour-ordered kernel (recursion and colour sum in one pass), the
+// leading-colour kernels, and the host side of the persistent
+// mixed-multiplicity batch (kernel template: batch_impl.h).  Tile routines:
+// fused_impl.h.
+#include "batch_impl.h"
+
+namespace bg {
+// the batch kernel instances live in batch_kinds_*.hip
+#define BG_EXTERN_KINDS(KK)                                                                   \
+  extern template int batch_occupancy_kinds<KK>(bool, int, int, size_t);                      \
+  extern template void batch_launch_kinds<KK>(bool, int, int, const BatchSegTable&,            \
+                                              const BatchTile*, unsigned, unsigned,            \
+                                              const unsigned*, unsigned*, double*, int64_t,    \
+                                              int, size_t, hipStream_t);
+BG_EXTERN_KINDS(kBatchKindsAll)
+BG_EXTERN_KINDS(kBatchKindsCobg)
+BG_EXTERN_KINDS(kBatchKindsCdbg)
+#undef BG_EXTERN_KINDS
+}  // namespace bg
 
 namespace bg {
 namespace fusedk {
@@ -133,120 +149,21 @@ __global__ void zero_counter_kernel(unsigned* c) {
   if (threadIdx.x == 0) c[0] = 0u;
 }
 
-// Batch blocks: four waves.  A colour-ordered tile is split into 32-event
-// sub-tiles, wave w taking sub-tiles w, w + 4, ... with its own LDS region and
-// scratch slice; every wave runs the same number of rounds (a wave without a
-// sub-tile evaluates a stand-in event and stores nothing), because the tile
-// routine synchronises the block.  A colour-dressed tile is evaluated by all
-// 256 lanes, one valid event at a time.  LDS: a 64-byte header (validity
-// masks, tile broadcast) followed by the tile region.
-constexpr int kBatchWaves = 4;
-constexpr int kBatchLanes = 64 * kBatchWaves;
-constexpr size_t kBatchHeader = 64;
-
-// n >= 6 re-read FP64 momenta from global memory so that four waves of
-// colour-ordered tiles fit beside a colour-dressed n = 9 event's LDS.
-template <int N>
-struct BatchP64G {
-  static constexpr bool value = N >= 6;
-};
-
-template <int N, typename T, int PASS>
-__device__ __forceinline__ void run_cobg(unsigned char* lds, const BatchSeg& s, double* blk,
-                                         int64_t first, int count) {
-  constexpr bool G = BatchP64G<N>::value;
-  const int w = threadIdx.x >> 6;
-  unsigned char* mine = lds + (size_t)w * Cobg<N>::template lds_bytes<T, G>();
-  double* myblk = blk + (size_t)w * Cobg<N>::kScratch;
-  const int nsub = (count + kTileEvents - 1) / kTileEvents;
-  for (int i = 0; i < nsub; i += kBatchWaves) {
-    const int j = i + w;
-    const int off = j * kTileEvents;
-    const int c = j < nsub ? (count - off < kTileEvents ? count - off : kTileEvents) : 0;
-    const int64_t f = first + (j < nsub ? off : 0);
-    if constexpr (PASS == kBatchFix)
-      cobg_tile<N, T, false, G, false, true>(mine, s.E, s.mom, s.hel, s.Cl, myblk, s.me2, f, c,
-                                             TileCheck{}, s.idx);
-    else if constexpr (PASS == kBatchCheck)
-      cobg_tile<N, T, false, G, true>(mine, s.E, s.mom, s.hel, s.Cl, myblk, s.me2, f, c,
-                                      TileCheck{s.tau, s.fcount, s.flist});
-    else
-      cobg_tile<N, T, false, G>(mine, s.E, s.mom, s.hel, s.Cl, myblk, s.me2, f, c);
-  }
-}
-
-template <int N, typename T, int PASS>
-__device__ __forceinline__ void run_cdbg(unsigned char* lds, unsigned long long* vmask,
-                                         const BatchSeg& s, int64_t first, int count) {
-  for (int off = 0; off < count; off += kBatchLanes) {
-    const int c = count - off < kBatchLanes ? count - off : kBatchLanes;
-    cdbg_chunk<N, T, kBatchLanes, PASS>(lds, vmask, s.E, s.mom, s.hel, s.col, s.me2, first + off,
-                                        c, s.idx, cdbgk::DressedCheck{s.tau, s.fcount, s.flist});
-  }
-}
-
-// Persistent: each block pops tile indices from an atomic counter until the
-// queue is empty (every block reaches the exit test).  Tiles are ordered by
-// decreasing estimated cost on the host.
-// WAVES: minimum waves per SIMD the register allocation must allow.  1: the
-// largest branch (n = 7 colour-ordered) keeps all its registers and one
-// block fits on a CU; 2: at most 256 registers per lane, two blocks per CU
-// (the colour-dressed branches need ~130 and gain from the second block, the
-// n = 7 branch spills a little).  The autotuner picks one.  PASS: BatchPass;
-// the re-evaluation pass reads its tile count from n_tiles_dev.
-template <typename T, int WAVES, int PASS>
-__global__ void __launch_bounds__(kBatchLanes, WAVES) batch_kernel(const BatchSegTable segs,
-                                                           const BatchTile* __restrict__ tiles,
-                                                           unsigned n_tiles,
-                                                           const unsigned* __restrict__ n_tiles_dev,
-                                                           unsigned* __restrict__ counter,
-                                                           double* __restrict__ scratch,
-                                                           int64_t scratch_stride) {
-  extern __shared__ __align__(16) unsigned char bg_batch_lds[];
-  unsigned long long* vmask = reinterpret_cast<unsigned long long*>(bg_batch_lds);
-  unsigned* bcast = reinterpret_cast<unsigned*>(bg_batch_lds + 32);
-  unsigned char* lds = bg_batch_lds + kBatchHeader;
-  double* blk = scratch + (size_t)blockIdx.x * (size_t)scratch_stride;
-  const unsigned total = n_tiles_dev ? *n_tiles_dev : n_tiles;
-  for (;;) {
-    if (threadIdx.x == 0) bcast[0] = atomicAdd(counter, 1u);
-    __syncthreads();
-    const unsigned t = (unsigned)__builtin_amdgcn_readfirstlane((int)bcast[0]);
-    __syncthreads();  // every lane has the index before the next pop
-    if (t >= total) break;
-    const BatchTile tile = tiles[t];
-    const BatchSeg s = segs.s[tile.seg];
-    switch (s.kind) {
-      case kBatchCobg + 4: run_cobg<4, T, PASS>(lds, s, blk, tile.first, tile.count); break;
-      case kBatchCobg + 5: run_cobg<5, T, PASS>(lds, s, blk, tile.first, tile.count); break;
-      case kBatchCobg + 6: run_cobg<6, T, PASS>(lds, s, blk, tile.first, tile.count); break;
-      case kBatchCobg + 7: run_cobg<7, T, PASS>(lds, s, blk, tile.first, tile.count); break;
-      case kBatchCdbg + 4: run_cdbg<4, T, PASS>(lds, vmask, s, tile.first, tile.count); break;
-      case kBatchCdbg + 5: run_cdbg<5, T, PASS>(lds, vmask, s, tile.first, tile.count); break;
-      case kBatchCdbg + 6: run_cdbg<6, T, PASS>(lds, vmask, s, tile.first, tile.count); break;
-      case kBatchCdbg + 7: run_cdbg<7, T, PASS>(lds, vmask, s, tile.first, tile.count); break;
-      case kBatchCdbg + 8: run_cdbg<8, T, PASS>(lds, vmask, s, tile.first, tile.count); break;
-      case kBatchCdbg + 9: run_cdbg<9, T, PASS>(lds, vmask, s, tile.first, tile.count); break;
-      default: break;
-    }
-    __syncthreads();  // the next tile rewrites LDS
-  }
-}
-
 // Tiles of the re-evaluation pass: segment s contributes ceil(fcount[s] /
 // step) tiles over its list.  Colour-dressed segments come first and take one
 // event per tile (a listed event is valid and costs a whole block for tens
 // of microseconds, so the queue must spread them over all blocks);
 // colour-ordered segments follow with tiles of 128 events (four 32-event
-// sub-tiles, one per wave).
+// sub-tiles, one per wave).  range[0..5]: the dressed tiles [0, n_cd), the
+// colour-ordered tiles [n_cd, total) and all tiles [0, total).
 __global__ void __launch_bounds__(256) fix_tiles_kernel(const BatchSegTable segs, int n_segs,
                                                        const unsigned* __restrict__ fcount,
                                                        BatchTile* __restrict__ tiles,
-                                                       unsigned* __restrict__ n_tiles) {
+                                                       unsigned* __restrict__ range) {
   __shared__ unsigned start[kBatchMaxSegs];
   __shared__ unsigned ntile[kBatchMaxSegs];
   if (threadIdx.x == 0) {
-    unsigned acc = 0;
+    unsigned acc = 0, n_cd = 0;
     for (int pass = 0; pass < 2; ++pass) {  // dressed segments first
       for (int i = 0; i < n_segs; ++i) {
         const bool cd = segs.s[i].kind >= kBatchCdbg;
@@ -256,8 +173,14 @@ __global__ void __launch_bounds__(256) fix_tiles_kernel(const BatchSegTable segs
         ntile[i] = (fcount[i] + step - 1) / step;
         acc += ntile[i];
       }
+      if (pass == 0) n_cd = acc;
     }
-    *n_tiles = acc;
+    range[0] = 0u;
+    range[1] = n_cd;
+    range[2] = n_cd;
+    range[3] = acc;
+    range[4] = 0u;
+    range[5] = acc;
   }
   __syncthreads();
   for (int i = 0; i < n_segs; ++i) {
@@ -492,82 +415,37 @@ size_t batch_lds_bytes(int kind, int n, bool fp32, bool chk) {
 
 int batch_scratch_doubles(int n) { return fusedk::kBatchWaves * cobg_fused_scratch_doubles(n); }
 
-namespace fusedk {
-template <typename T, int WAVES, int PASS>
-int occupancy_of(size_t lds) {
-  int nb = 0;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<T, WAVES, PASS>,
-                                                      kBatchLanes, lds) == hipSuccess
-             ? nb
-             : -1;
-}
-
-template <typename T, int WAVES, int PASS>
-void launch_batch(const BatchSegTable& segs, const BatchTile* tiles, unsigned n_tiles,
-                  const unsigned* n_tiles_dev, unsigned* counter, double* scratch,
-                  int64_t scratch_stride, int grid, size_t lds, hipStream_t stream) {
-  hipLaunchKernelGGL((batch_kernel<T, WAVES, PASS>), dim3(grid), dim3(kBatchLanes), lds, stream,
-                     segs, tiles, n_tiles, n_tiles_dev, counter, scratch, scratch_stride);
-}
-
-// Instances: FP32 plain and checked, FP64 plain and re-evaluation.
-template <int WAVES>
-int occupancy_pass(bool fp32, int pass, size_t lds) {
-  if (fp32)
-    return pass == kBatchCheck ? occupancy_of<float, WAVES, kBatchCheck>(lds)
-                               : occupancy_of<float, WAVES, kBatchPlain>(lds);
-  return pass == kBatchFix ? occupancy_of<double, WAVES, kBatchFix>(lds)
-                           : occupancy_of<double, WAVES, kBatchPlain>(lds);
-}
-
-template <int WAVES>
-void launch_pass(bool fp32, int pass, const BatchSegTable& segs, const BatchTile* tiles,
-                 unsigned n_tiles, const unsigned* n_tiles_dev, unsigned* counter,
-                 double* scratch, int64_t scratch_stride, int grid, size_t lds,
-                 hipStream_t stream) {
-  if (fp32) {
-    if (pass == kBatchCheck)
-      launch_batch<float, WAVES, kBatchCheck>(segs, tiles, n_tiles, n_tiles_dev, counter, scratch,
-                                              scratch_stride, grid, lds, stream);
-    else
-      launch_batch<float, WAVES, kBatchPlain>(segs, tiles, n_tiles, n_tiles_dev, counter, scratch,
-                                              scratch_stride, grid, lds, stream);
-  } else {
-    if (pass == kBatchFix)
-      launch_batch<double, WAVES, kBatchFix>(segs, tiles, n_tiles, n_tiles_dev, counter, scratch,
-                                             scratch_stride, grid, lds, stream);
-    else
-      launch_batch<double, WAVES, kBatchPlain>(segs, tiles, n_tiles, n_tiles_dev, counter,
-                                               scratch, scratch_stride, grid, lds, stream);
+int batch_blocks_per_cu(bool fp32, int waves, int pass, int kinds, size_t lds) {
+  if ((fp32 && pass == kBatchFix) || (!fp32 && pass == kBatchCheck)) return -1;
+  switch (kinds) {
+    case kBatchKindsAll: return batch_occupancy_kinds<kBatchKindsAll>(fp32, waves, pass, lds);
+    case kBatchKindsCobg: return batch_occupancy_kinds<kBatchKindsCobg>(fp32, waves, pass, lds);
+    case kBatchKindsCdbg: return batch_occupancy_kinds<kBatchKindsCdbg>(fp32, waves, pass, lds);
+    default: return -1;
   }
 }
-}  // namespace fusedk
 
-int batch_blocks_per_cu(bool fp32, int waves, int pass, size_t lds) {
-  if ((fp32 && pass == kBatchFix) || (!fp32 && pass == kBatchCheck)) return -1;
-  return waves == 2 ? fusedk::occupancy_pass<2>(fp32, pass, lds)
-                    : fusedk::occupancy_pass<1>(fp32, pass, lds);
-}
-
-int batch_launch(bool fp32, int waves, int pass, const BatchSegTable& segs,
-                 const BatchTile* tiles, unsigned n_tiles, const unsigned* n_tiles_dev,
-                 unsigned* counter, double* scratch, int64_t scratch_stride, int grid, size_t lds,
-                 hipStream_t stream) {
+int batch_launch(bool fp32, int waves, int pass, int kinds, const BatchSegTable& segs,
+                 const BatchTile* tiles, unsigned t_begin, unsigned t_end,
+                 const unsigned* range_dev, unsigned* counter, double* scratch,
+                 int64_t scratch_stride, int grid, size_t lds, hipStream_t stream) {
   if ((fp32 && pass == kBatchFix) || (!fp32 && pass == kBatchCheck)) return -2;
+  if (kinds < kBatchKindsAll || kinds > kBatchKindsCdbg) return -2;
   hipLaunchKernelGGL(fusedk::zero_counter_kernel, dim3(1), dim3(64), 0, stream, counter);
-  if (waves == 2)
-    fusedk::launch_pass<2>(fp32, pass, segs, tiles, n_tiles, n_tiles_dev, counter, scratch,
-                           scratch_stride, grid, lds, stream);
-  else
-    fusedk::launch_pass<1>(fp32, pass, segs, tiles, n_tiles, n_tiles_dev, counter, scratch,
-                           scratch_stride, grid, lds, stream);
+#define BG_K(KK)                                                                             \
+  batch_launch_kinds<KK>(fp32, waves, pass, segs, tiles, t_begin, t_end, range_dev, counter, \
+                         scratch, scratch_stride, grid, lds, stream)
+  if (kinds == kBatchKindsAll) BG_K(kBatchKindsAll);
+  else if (kinds == kBatchKindsCobg) BG_K(kBatchKindsCobg);
+  else BG_K(kBatchKindsCdbg);
+#undef BG_K
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int batch_fix_tiles(const BatchSegTable& segs, int n_segs, const unsigned* fcount,
-                    BatchTile* tiles, unsigned* n_tiles, hipStream_t stream) {
+                    BatchTile* tiles, unsigned* range, hipStream_t stream) {
   hipLaunchKernelGGL(fusedk::fix_tiles_kernel, dim3(1), dim3(256), 0, stream, segs, n_segs, fcount,
-                     tiles, n_tiles);
+                     tiles, range);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

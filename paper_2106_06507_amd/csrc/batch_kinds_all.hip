@@ -1,0 +1,12 @@
+// Instances of the persistent batch kernel for segment kinds: kBatchKindsAll.
+#include "batch_impl.h"
+
+namespace bg {
+
+template int batch_occupancy_kinds<kBatchKindsAll>(bool, int, int, size_t);
+template void batch_launch_kinds<kBatchKindsAll>(bool, int, int, const BatchSegTable&,
+                                                 const BatchTile*, unsigned, unsigned,
+                                                 const unsigned*, unsigned*, double*, int64_t, int,
+                                                 size_t, hipStream_t);
+
+}  // namespace bg

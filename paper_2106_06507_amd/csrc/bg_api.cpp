@@ -29,15 +29,17 @@ struct BatchPlan {
   std::vector<int64_t> key;
   bg::BatchTile* tiles = nullptr;
   unsigned n_tiles = 0;
+  unsigned n_tiles_cobg = 0;  // split plans: colour-ordered tiles first, then the dressed ones
   uint64_t last_use = 0;
   // FP32 plans: workspace of the check and of the FP64 re-evaluation pass:
-  // words [0, 32) listed-event counts per segment, word 32 the re-evaluation
-  // tile count, from word 64 the per-segment lists (list_off), then the
-  // re-evaluation tiles (at most max_fix_tiles).
+  // words [0, 32) listed-event counts per segment, words [32, 38) the
+  // re-evaluation tile ranges (dressed, colour-ordered, all), from word 64
+  // the per-segment lists (list_off), then the re-evaluation tiles (at most
+  // max_fix_cd dressed ones, then at most max_fix_co colour-ordered ones).
   unsigned* chk_ws = nullptr;
   std::vector<size_t> list_off;
   bg::BatchTile* fix_tiles = nullptr;
-  unsigned max_fix_tiles = 0;
+  unsigned max_fix_cd = 0, max_fix_co = 0;
 };
 
 void free_plan(BatchPlan& pl) {
@@ -82,15 +84,15 @@ struct bg_context {
   void* cdmc_state = nullptr;                // per-block state slabs (FP64, n = 9)
   size_t cdmc_state_bytes = 0;
   int occ_cdmc[BG_N_MAX + 1][2] = {};
-  bg_batch_config bcfg[2] = {{0, 128, 256, 2}, {0, 128, 256, 2}};
+  bg_batch_config bcfg[2] = {{0, 128, 256, 2, 1}, {0, 128, 256, 2, 1}};
   std::vector<BatchPlan> plans;
   uint64_t clock = 0;
   int occ_fused[2][2][2] = {};               // blocks per CU of the persistent fused kernel
                                              // [fp32][helicity sum][checked], 0 = unknown
-  int occ_batch[4][2] = {};                  // of the batch kernel [fp32 * 2 + (pass != plain)]
+  int occ_batch[3][4][2] = {};               // of the batch kernel [kinds][fp32 * 2 + (pass != plain)][waves - 1]
                                              // [variant] at its last LDS size
   int occ_cdbg[BG_N_MAX + 1][2] = {};        // of the colour-dressed event kernel
-  size_t occ_batch_lds[4][2] = {};
+  size_t occ_batch_lds[3][4][2] = {};
   uint32_t flags = 0;                        // BG_FLAG_* applied to every request
   float fp32_tau[4][BG_N_MAX + 1] = {};      // FP32 check thresholds [COBG, CDBG, COMC, LC][n]
   int occ_lc_fix[BG_N_MAX + 1] = {};         // of the FP64 leading-colour re-evaluation
@@ -1151,7 +1153,7 @@ int batch_plan(bg_context* ctx, const bg_request* segs, int n_segs, const bg_bat
                bool capturing, BatchPlan** out) {
   const int prec = segs[0].precision;
   const bool fp32 = prec == BG_PREC_FP32_MIXED;
-  std::vector<int64_t> key = {prec, cfg.cobg_tile_events, cfg.cdbg_tile_events};
+  std::vector<int64_t> key = {prec, cfg.cobg_tile_events, cfg.cdbg_tile_events, cfg.split_kinds};
   for (int i = 0; i < n_segs; ++i) {
     key.push_back(segs[i].n * 2 + (resolved_mode(&segs[i]) == BG_MODE_CDBG ? 1 : 0));
     key.push_back(segs[i].n_events);
@@ -1169,6 +1171,7 @@ int batch_plan(bg_context* ctx, const bg_request* segs, int n_segs, const bg_bat
   }
   struct Item {
     double cost;
+    bool cd;
     bg::BatchTile t;
   };
   std::vector<Item> items;
@@ -1188,17 +1191,27 @@ int batch_plan(bg_context* ctx, const bg_request* segs, int n_segs, const bg_bat
     const double c = event_cost(r->n, cd, fp32);
     for (int64_t f = 0; f < r->n_events; f += step) {
       const int cnt = (int)std::min<int64_t>(step, r->n_events - f);
-      items.push_back(Item{c * cnt, bg::BatchTile{f, i, cnt}});
+      items.push_back(Item{c * cnt, cd, bg::BatchTile{f, i, cnt}});
     }
   }
   if (items.size() > 0x7fffffffu) return BG_ERANGE;
-  std::stable_sort(items.begin(), items.end(),
-                   [](const Item& a, const Item& b) { return a.cost > b.cost; });
+  // by decreasing cost; split plans keep the colour-ordered tiles ahead of
+  // the dressed ones (one persistent launch each)
+  const bool split = cfg.split_kinds != 0;
+  std::stable_sort(items.begin(), items.end(), [split](const Item& a, const Item& b) {
+    if (split && a.cd != b.cd) return !a.cd;
+    return a.cost > b.cost;
+  });
   std::vector<bg::BatchTile> tiles(items.size());
-  for (size_t i = 0; i < items.size(); ++i) tiles[i] = items[i].t;
+  unsigned n_co = 0;
+  for (size_t i = 0; i < items.size(); ++i) {
+    tiles[i] = items[i].t;
+    n_co += items[i].cd ? 0u : 1u;
+  }
   BatchPlan pl;
   pl.key = key;
   pl.n_tiles = (unsigned)tiles.size();
+  pl.n_tiles_cobg = n_co;
   if (!tiles.empty()) {
     int st = hip_status(hipMalloc(&pl.tiles, sizeof(bg::BatchTile) * tiles.size()),
                         "hipMalloc(tiles)");
@@ -1213,19 +1226,23 @@ int batch_plan(bg_context* ctx, const bg_request* segs, int n_segs, const bg_bat
   }
   if (fp32) {
     size_t words = 64;
-    uint64_t fix_tiles = 0;
+    uint64_t fix_cd = 0, fix_co = 0;
     for (int i = 0; i < n_segs; ++i) {
       pl.list_off.push_back(words);
       words += (size_t)segs[i].n_events;
-      const int64_t step = resolved_mode(&segs[i]) == BG_MODE_CDBG ? 1 : 128;
-      fix_tiles += (uint64_t)((segs[i].n_events + step - 1) / step);
+      if (resolved_mode(&segs[i]) == BG_MODE_CDBG)
+        fix_cd += (uint64_t)segs[i].n_events;
+      else
+        fix_co += (uint64_t)((segs[i].n_events + 127) / 128);
     }
+    const uint64_t fix_tiles = fix_cd + fix_co;
     if (fix_tiles > 0x7fffffffu) {
       free_plan(pl);
       return BG_ERANGE;
     }
     words = (words + 3) / 4 * 4;  // 16-byte alignment of the tile array
-    pl.max_fix_tiles = (unsigned)fix_tiles;
+    pl.max_fix_cd = (unsigned)fix_cd;
+    pl.max_fix_co = (unsigned)fix_co;
     const size_t bytes = sizeof(unsigned) * words + sizeof(bg::BatchTile) * (fix_tiles + 1);
     int st = hip_status(hipMalloc(&pl.chk_ws, bytes), "hipMalloc(batch check)");
     if (st) {
@@ -1254,16 +1271,21 @@ int batch_plan(bg_context* ctx, const bg_request* segs, int n_segs, const bg_bat
   return BG_OK;
 }
 
-// Blocks per CU of a batch pass at an LDS size (cached per pass and variant).
-int batch_occ(bg_context* ctx, bool fp32, int waves, int pass, size_t lds, bool capturing) {
+// Blocks per CU of a batch pass at an LDS size (cached per kinds, pass and
+// variant).  The dressed-only kernel exists for the two-waves budget only.
+int batch_occ(bg_context* ctx, bool fp32, int waves, int pass, int kinds, size_t lds,
+              bool capturing) {
+  if (kinds == bg::kBatchKindsCdbg) waves = 2;
   const int wi = waves - 1;
   const int k = (fp32 ? 2 : 0) + (pass != bg::kBatchPlain ? 1 : 0);
-  if (ctx->occ_batch[k][wi] <= 0 || ctx->occ_batch_lds[k][wi] != lds) {
+  int& occ = ctx->occ_batch[kinds][k][wi];
+  size_t& at = ctx->occ_batch_lds[kinds][k][wi];
+  if (occ <= 0 || at != lds) {
     if (capturing) return -1;
-    ctx->occ_batch[k][wi] = bg::batch_blocks_per_cu(fp32, waves, pass, lds);
-    ctx->occ_batch_lds[k][wi] = lds;
+    occ = bg::batch_blocks_per_cu(fp32, waves, pass, kinds, lds);
+    at = lds;
   }
-  return ctx->occ_batch[k][wi];
+  return occ;
 }
 
 int batch_run(bg_context* ctx, const bg_request* segs, int n_segs, const bg_batch_config& cfg,
@@ -1277,7 +1299,7 @@ int batch_run(bg_context* ctx, const bg_request* segs, int n_segs, const bg_batc
         check = true;
   bg::BatchSegTable tab;
   memset(&tab, 0, sizeof(tab));
-  size_t lds = 0, lds64 = 0;
+  size_t lds[2] = {0, 0}, lds64[2] = {0, 0};  // [colour-ordered, colour-dressed]
   int64_t stride = 0;
   for (int i = 0; i < n_segs; ++i) {
     const bg_request* r = &segs[i];
@@ -1300,34 +1322,71 @@ int batch_run(bg_context* ctx, const bg_request* segs, int n_segs, const bg_batc
       b.Cl = ctx->Cb_dev[r->n];
       stride = std::max<int64_t>(stride, bg::batch_scratch_doubles(r->n));
     }
-    lds = std::max(lds, bg::batch_lds_bytes(kind, r->n, fp32, check));
-    lds64 = std::max(lds64, bg::batch_lds_bytes(kind, r->n, false));
+    lds[cd] = std::max(lds[cd], bg::batch_lds_bytes(kind, r->n, fp32, check));
+    lds64[cd] = std::max(lds64[cd], bg::batch_lds_bytes(kind, r->n, false));
   }
   BatchPlan* pl = nullptr;
   int st = batch_plan(ctx, segs, n_segs, cfg, capturing, &pl);
   if (st) return st;
   if (pl->n_tiles == 0) return BG_OK;
-  const int waves = cfg.waves_per_simd == 1 ? 1 : 2;
-  const int pass = check ? bg::kBatchCheck : bg::kBatchPlain;
-  const int occ = batch_occ(ctx, fp32, waves, pass, lds, capturing);
-  if (occ == -1 && capturing) return BG_EINVAL;
-  if (occ <= 0) return BG_EUNSUPPORTED;
-  const int bpc = cfg.blocks_per_cu > 0 ? std::min(cfg.blocks_per_cu, occ) : occ;
-  const int64_t grid = std::min<int64_t>((int64_t)ctx->num_cus * bpc, pl->n_tiles);
-  // the re-evaluation pass runs the FP64 variant with the FP64 config's register budget
+  // One persistent launch per pass over every tile, or (split_kinds) one
+  // over the colour-ordered tiles and one over the dressed tiles, each with
+  // the LDS and register budget of its own kind.  The re-evaluation pass
+  // runs the FP64 variant with the FP64 config's register budget, over tile
+  // ranges built on the device.
+  struct Launch {
+    int kinds, waves;
+    unsigned b, e;              // host tile range, or
+    const unsigned* range;      // the device one
+    uint64_t max_tiles;
+    size_t lds;
+    int64_t grid;
+  };
   const bg_batch_config& cfg64 = ctx->bcfg[0];
+  const int waves = cfg.waves_per_simd == 1 ? 1 : 2;
   const int waves64 = cfg64.waves_per_simd == 1 ? 1 : 2;
-  int64_t grid64 = 0;
-  if (check) {
-    const int occ64 = batch_occ(ctx, false, waves64, bg::kBatchFix, lds64, capturing);
-    if (occ64 == -1 && capturing) return BG_EINVAL;
-    if (occ64 <= 0) return BG_EUNSUPPORTED;
-    const int bpc64 = cfg64.blocks_per_cu > 0 ? std::min(cfg64.blocks_per_cu, occ64) : occ64;
-    grid64 = std::min<int64_t>((int64_t)ctx->num_cus * bpc64, pl->max_fix_tiles);
-    grid64 = std::max<int64_t>(grid64, 1);
+  unsigned* const range = fp32 && pl->chk_ws ? pl->chk_ws + 32 : nullptr;
+  Launch main_l[2], fix_l[2];
+  int n_main = 0, n_fix = 0;
+  if (!cfg.split_kinds) {
+    main_l[n_main++] = Launch{bg::kBatchKindsAll, waves, 0u, pl->n_tiles, nullptr, pl->n_tiles,
+                              std::max(lds[0], lds[1]), 0};
+    if (check)
+      fix_l[n_fix++] = Launch{bg::kBatchKindsAll, waves64, 0u, 0u, range + 4,
+                              (uint64_t)pl->max_fix_cd + pl->max_fix_co,
+                              std::max(lds64[0], lds64[1]), 0};
+  } else {
+    if (pl->n_tiles_cobg > 0)
+      main_l[n_main++] = Launch{bg::kBatchKindsCobg, waves, 0u, pl->n_tiles_cobg, nullptr,
+                                pl->n_tiles_cobg, lds[0], 0};
+    if (pl->n_tiles > pl->n_tiles_cobg)
+      main_l[n_main++] = Launch{bg::kBatchKindsCdbg, 2, pl->n_tiles_cobg, pl->n_tiles, nullptr,
+                                pl->n_tiles - pl->n_tiles_cobg, lds[1], 0};
+    if (check && pl->max_fix_cd > 0)
+      fix_l[n_fix++] = Launch{bg::kBatchKindsCdbg, 2, 0u, 0u, range + 0, pl->max_fix_cd,
+                              lds64[1], 0};
+    if (check && pl->max_fix_co > 0)
+      fix_l[n_fix++] = Launch{bg::kBatchKindsCobg, waves64, 0u, 0u, range + 2, pl->max_fix_co,
+                              lds64[0], 0};
   }
-  const size_t need = sizeof(double) * (size_t)std::max(grid, grid64) * (size_t)stride;
-  if (ctx->scratch_bytes < std::max<size_t>(need, 256) || !ctx->counter) {
+  size_t need = 256;
+  auto size_grid = [&](Launch& l, bool f32, int ps, const bg_batch_config& c) -> int {
+    const int occ = batch_occ(ctx, f32, l.waves, ps, l.kinds, l.lds, capturing);
+    if (occ == -1 && capturing) return BG_EINVAL;
+    if (occ <= 0) return BG_EUNSUPPORTED;
+    const int bpc = c.blocks_per_cu > 0 ? std::min(c.blocks_per_cu, occ) : occ;
+    l.grid = std::max<int64_t>(
+        1, std::min<int64_t>((int64_t)ctx->num_cus * bpc, (int64_t)std::max<uint64_t>(l.max_tiles, 1)));
+    if (l.kinds != bg::kBatchKindsCdbg)
+      need = std::max(need, sizeof(double) * (size_t)l.grid * (size_t)stride);
+    return BG_OK;
+  };
+  const int pass = check ? bg::kBatchCheck : bg::kBatchPlain;
+  for (int i = 0; i < n_main; ++i)
+    if ((st = size_grid(main_l[i], fp32, pass, cfg))) return st;
+  for (int i = 0; i < n_fix; ++i)
+    if ((st = size_grid(fix_l[i], false, bg::kBatchFix, cfg64))) return st;
+  if (ctx->scratch_bytes < need || !ctx->counter) {
     if (capturing) {
       BG_LOG("bg_me2_batch: workspace not prepared before graph capture");
       return BG_EINVAL;
@@ -1336,10 +1395,19 @@ int batch_run(bg_context* ctx, const bg_request* segs, int n_segs, const bg_batc
     if (!st) st = ensure_counters(ctx);
     if (st) return st;
   }
-  if (!check)
-    return launch_status(bg::batch_launch(fp32, waves, bg::kBatchPlain, tab, pl->tiles,
-                                          pl->n_tiles, nullptr, ctx->counter, ctx->scratch,
-                                          stride, (int)grid, lds, stream));
+  auto run = [&](const Launch& l, bool f32, int ps) -> int {
+    // the dressed-only kernel never touches the colour-ordered scratch
+    const int64_t sstride = l.kinds == bg::kBatchKindsCdbg ? 0 : stride;
+    return launch_status(bg::batch_launch(f32, l.waves, ps, l.kinds, tab, ps == bg::kBatchFix
+                                                                          ? pl->fix_tiles
+                                                                          : pl->tiles,
+                                          l.b, l.e, l.range, ctx->counter, ctx->scratch, sstride,
+                                          (int)l.grid, l.lds, stream));
+  };
+  if (!check) {
+    for (int i = 0; i < n_main && !st; ++i) st = run(main_l[i], fp32, bg::kBatchPlain);
+    return st;
+  }
   for (int i = 0; i < n_segs; ++i) {
     const bg_request* r = &segs[i];
     bg::BatchSeg& b = tab.s[i];
@@ -1349,26 +1417,22 @@ int batch_run(bg_context* ctx, const bg_request* segs, int n_segs, const bg_batc
     b.tau = ((r->flags | ctx->flags) & BG_FLAG_FP32_UNCHECKED) ? INFINITY
                                                                : ctx->fp32_tau[cd ? 1 : 0][r->n];
   }
-  st = launch_status(bg::fill_u32(pl->chk_ws, 33, 0u, stream));
+  st = launch_status(bg::fill_u32(pl->chk_ws, 38, 0u, stream));
+  for (int i = 0; i < n_main && !st; ++i) st = run(main_l[i], true, bg::kBatchCheck);
   if (!st)
-    st = launch_status(bg::batch_launch(true, waves, bg::kBatchCheck, tab, pl->tiles, pl->n_tiles,
-                                        nullptr, ctx->counter, ctx->scratch, stride, (int)grid,
-                                        lds, stream));
-  if (!st)
-    st = launch_status(bg::batch_fix_tiles(tab, n_segs, pl->chk_ws, pl->fix_tiles,
-                                           pl->chk_ws + 32, stream));
+    st = launch_status(bg::batch_fix_tiles(tab, n_segs, pl->chk_ws, pl->fix_tiles, range, stream));
   if (st) return st;
   for (int i = 0; i < n_segs; ++i) tab.s[i].idx = tab.s[i].flist;
-  return launch_status(bg::batch_launch(false, waves64, bg::kBatchFix, tab, pl->fix_tiles, 0,
-                                        pl->chk_ws + 32, ctx->counter, ctx->scratch, stride,
-                                        (int)grid64, lds64, stream));
+  for (int i = 0; i < n_fix && !st; ++i) st = run(fix_l[i], false, bg::kBatchFix);
+  return st;
 }
 
 bool valid_config(const bg_batch_config* c) {
   return c && c->blocks_per_cu >= 0 && c->blocks_per_cu <= 64 && c->cobg_tile_events >= 128 &&
          c->cobg_tile_events <= 8192 && c->cobg_tile_events % 128 == 0 &&
          c->cdbg_tile_events >= 256 && c->cdbg_tile_events <= 8192 &&
-         c->cdbg_tile_events % 256 == 0 && (c->waves_per_simd == 1 || c->waves_per_simd == 2);
+         c->cdbg_tile_events % 256 == 0 && (c->waves_per_simd == 1 || c->waves_per_simd == 2) &&
+         (c->split_kinds == 0 || c->split_kinds == 1);
 }
 
 }  // namespace
@@ -1418,7 +1482,7 @@ int bg_me2_batch_tune(bg_context* ctx, const bg_request* segs, int n_segs, bg_ba
   hipEvent_t e0 = nullptr, e1 = nullptr;
   st = hip_status(hipEventCreate(&e0), "hipEventCreate");
   if (!st) st = hip_status(hipEventCreate(&e1), "hipEventCreate");
-  bg_batch_config cur = {0, 128, 256, 2};
+  bg_batch_config cur = {0, 128, 256, 2, 1};
   double cur_ms = 1e300;
   auto time_cfg = [&](const bg_batch_config& c, double* ms) -> int {
     int r = batch_run(ctx, segs, n_segs, c, s);  // warm-up, builds the plan
@@ -1441,8 +1505,9 @@ int bg_me2_batch_tune(bg_context* ctx, const bg_request* segs, int n_segs, bg_ba
     double ms = 0.0;
     int r = time_cfg(c, &ms);
     if (r) return r;
-    BG_LOG("tune: waves/SIMD %d blocks/CU %d cobg tile %d cdbg tile %d -> %.3f ms",
-           c.waves_per_simd, c.blocks_per_cu, c.cobg_tile_events, c.cdbg_tile_events, ms);
+    BG_LOG("tune: split %d waves/SIMD %d blocks/CU %d cobg tile %d cdbg tile %d -> %.3f ms",
+           c.split_kinds, c.waves_per_simd, c.blocks_per_cu, c.cobg_tile_events,
+           c.cdbg_tile_events, ms);
     if (ms < cur_ms) {
       cur_ms = ms;
       cur = c;
@@ -1451,12 +1516,16 @@ int bg_me2_batch_tune(bg_context* ctx, const bg_request* segs, int n_segs, bg_ba
   };
   if (!st) {
     const bg_batch_config base = cur;
-    for (int v : {2, 1}) {
-      for (int b : {0, 1}) {
-        bg_batch_config c = base;
-        c.waves_per_simd = v;
-        c.blocks_per_cu = b;
-        if ((st = try_cfg(c))) break;
+    for (int sp : {1, 0}) {
+      for (int v : {2, 1}) {
+        for (int b : {0, 1}) {
+          bg_batch_config c = base;
+          c.split_kinds = sp;
+          c.waves_per_simd = v;
+          c.blocks_per_cu = b;
+          if ((st = try_cfg(c))) break;
+        }
+        if (st) break;
       }
       if (st) break;
     }

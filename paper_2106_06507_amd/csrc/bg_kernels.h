@@ -172,20 +172,33 @@ int batch_scratch_doubles(int n);
 // Pass of the batch kernel: plain, checked FP32 (lists ill-conditioned
 // events per segment), or the FP64 re-evaluation of the listed events.
 enum BatchPass { kBatchPlain = 0, kBatchCheck = 1, kBatchFix = 2 };
+// Segment kinds a batch kernel instance evaluates: every kind, colour-ordered
+// only, colour-dressed only (tiles of other kinds are skipped).
+enum BatchKinds { kBatchKindsAll = 0, kBatchKindsCobg = 1, kBatchKindsCdbg = 2 };
 // waves: register budget variant, 1 (one wave per SIMD, no cap) or 2 (at
-// most 256 registers per lane).
-int batch_blocks_per_cu(bool fp32, int waves, int pass, size_t lds);
-// Enqueues the counter reset and the persistent kernel on stream.  n_tiles_dev
-// (may be null): the tile count is read on the device instead.
-int batch_launch(bool fp32, int waves, int pass, const BatchSegTable& segs,
-                 const BatchTile* tiles, unsigned n_tiles, const unsigned* n_tiles_dev,
-                 unsigned* counter, double* scratch, int64_t scratch_stride, int grid, size_t lds,
-                 hipStream_t stream);
+// most 256 registers per lane; the only variant of the dressed-only kernel).
+int batch_blocks_per_cu(bool fp32, int waves, int pass, int kinds, size_t lds);
+// Enqueues the counter reset and the persistent kernel on stream over the
+// tiles [t_begin, t_end), or [range_dev[0], range_dev[1]) read on the device
+// when range_dev is given.
+int batch_launch(bool fp32, int waves, int pass, int kinds, const BatchSegTable& segs,
+                 const BatchTile* tiles, unsigned t_begin, unsigned t_end,
+                 const unsigned* range_dev, unsigned* counter, double* scratch,
+                 int64_t scratch_stride, int grid, size_t lds, hipStream_t stream);
+// Per-kinds instances (batch_kinds_*.hip).
+template <int KINDS>
+int batch_occupancy_kinds(bool fp32, int waves, int pass, size_t lds);
+template <int KINDS>
+void batch_launch_kinds(bool fp32, int waves, int pass, const BatchSegTable& segs,
+                        const BatchTile* tiles, unsigned t_begin, unsigned t_end,
+                        const unsigned* range_dev, unsigned* counter, double* scratch,
+                        int64_t scratch_stride, int grid, size_t lds, hipStream_t stream);
 // Tiles of the re-evaluation pass from the per-segment counts fcount[s] of
 // listed events: colour-dressed tiles of one listed event (queued first),
-// colour-ordered tiles of up to 128; tiles[], *n_tiles on the device.
+// colour-ordered tiles of up to 128; tiles[] and range[0..5] on the device:
+// the dressed tiles, the colour-ordered tiles, all tiles (begin, end each).
 int batch_fix_tiles(const BatchSegTable& segs, int n_segs, const unsigned* fcount,
-                    BatchTile* tiles, unsigned* n_tiles, hipStream_t stream);
+                    BatchTile* tiles, unsigned* range, hipStream_t stream);
 
 // Colour-sampled colour-ordered |A|^2 (comc.hip).  count: counts, offsets
 // and the valid-event list [E] each, block_items and block_valid
