@@ -247,7 +247,7 @@ int bg_me2_grad(bg_context* ctx, const bg_request* req, const double* grad_me2,
  * error bars: bg_me2 runs FP64 n = 7 in two stages (1/P^2 from prefix sums,
  * another colour-sum order), the FP32 kernels may contract products into multiply-adds
  * differently, a colour-dressed event is split over 256 lanes here and over
- * 128 or 256 in bg_me2, and an FP32 event close to the check threshold of
+ * 64, 128 or 256 in bg_me2, and an FP32 event close to the check threshold of
  * bg_fp32_check_set may be re-evaluated in FP64 by one path only.
  * BG_PREC_FP32_MIXED batches apply that check per segment (threshold of the
  * segment's mode and n; BG_FLAG_FP32_UNCHECKED in a segment's flags turns it

@@ -43,18 +43,23 @@ __global__ void zero_u32_kernel(unsigned* p, int n) {
   if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
 }
 
-// Lanes per event of the standalone kernel (measured on MI355X for 2^20
-// sampled flows: n = 8 fastest with two waves per event, n = 9 with four).
-template <int N>
+// Lanes per event of the standalone kernel, measured on MI355X for 2^20
+// sampled flows with the packed colour entries (ms, 64 / 128 / 256 lanes):
+// n = 7 FP64 0.93 / 1.89 / -, FP32 0.72 / 0.98 / -; n = 8 FP64 2.60 / 2.64 /
+// -, FP32 1.17 / 1.41 / -; n = 9 FP64 - / 7.85 / 6.89, FP32 - / 3.26 / 3.60.
+// Fewer lanes per event keep more events in flight and idle fewer lanes on
+// the levels with few targets, until the per-event LDS (n = 9 FP64: 64 KB)
+// caps the events per CU.
+template <int N, typename T>
 struct EventLanes {
-  static constexpr int value = N <= 8 ? 128 : 256;
+  static constexpr int value = N <= 8 ? 64 : (sizeof(T) == 4 ? 128 : 256);
 };
 
 template <int N, typename T, bool EST = false>
 int launch_events(int64_t E, const double* mom, const int8_t* hel, const int8_t* col,
                   const unsigned* list, const unsigned* count, unsigned* work, double* me2,
                   int grid, DressedCheck chk, hipStream_t stream) {
-  constexpr int NL = EventLanes<N>::value;
+  constexpr int NL = EventLanes<N, T>::value;
   hipLaunchKernelGGL((cdbg_event_kernel<N, T, NL, EST>), dim3(grid), dim3(NL),
                      (Lay<N, T, EST>::bytes()), stream, E, mom, hel, col, list, count, work, me2,
                      chk);
@@ -63,7 +68,7 @@ int launch_events(int64_t E, const double* mom, const int8_t* hel, const int8_t*
 
 template <int N, typename T, bool EST = false>
 int event_occupancy() {
-  constexpr int NL = EventLanes<N>::value;
+  constexpr int NL = EventLanes<N, T>::value;
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cdbg_event_kernel<N, T, NL, EST>, NL,
                                                    Lay<N, T, EST>::bytes()) != hipSuccess)

@@ -402,7 +402,6 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
   constexpr int NS = L::NS;
   constexpr int NW = NL / kWave;
   static_assert(NL % kWave == 0 && NW <= 4, "one to four waves per event");
-  static_assert(NS <= NL, "one subset per lane in the set-up");
   const int lane = threadIdx.x;
   const int w = lane / kWave, lw = lane % kWave;
   // ---- event set-up -------------------------------------------------
@@ -412,10 +411,9 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
   }
   if (lane < 4 * N) sm.pm[lane] = mom[(int64_t)lane * E + e];  // [k][mu] = row 4k + mu
   __syncthreads();
-  // subset codes, momenta, 1/P^2 (FP64 sums); lane l takes subset l + 1
-  int code = 0;
-  const int mask = lane + 1;
-  if (mask < NS) {
+  // subset codes, momenta, 1/P^2 (FP64 sums); subset index x + 1 for
+  // x = lane, lane + NL, ...
+  for (int mask = lane + 1; mask < NS; mask += NL) {
     double q[4] = {0.0, 0.0, 0.0, 0.0};
     double en = 0.0;
     ColourGraph g;
@@ -427,15 +425,20 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
       g.add(sm.cj[k], sm.ci[k]);
     }
     if constexpr (EST) sm.en[mask] = (T)en;
-    code = g.code();
+    sm.code[mask] = g.code();
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) sm.P[mask * 4 + mu] = (T)q[mu];
     const double p2 = q[0] * q[0] - q[1] * q[1] - q[2] * q[2] - q[3] * q[3];
     sm.ip2[mask] = (T)(1.0 / p2);
   }
+  __syncthreads();
   // first packed slot of every subset: exclusive prefix sum of the slot
-  // counts in mask order (a shuffle scan per wave, then the wave totals)
-  {
+  // counts in subset order, NL subsets per round (a shuffle scan per wave,
+  // then the wave totals), carried over the rounds
+  int total = 0;
+  for (int base = 1; base < NS; base += NL) {
+    const int mask = base + lane;
+    const int code = mask < NS ? sm.code[mask] : 0;
     const int cnt = slot_count(code);
     int incl = cnt;
 #pragma unroll
@@ -445,23 +448,23 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
     }
     if (lw == kWave - 1) sm.misc[w] = incl;
     __syncthreads();
-    int first = incl - cnt, total = 0;
+    int first = total + incl - cnt;
 #pragma unroll
     for (int v = 0; v < NW; ++v) {
       const int tv = sm.misc[v];
       first += v < w ? tv : 0;
       total += tv;
     }
-    // a valid flow holds at most kCap slots (exhaustive count over all flows);
-    // the guard keeps the packed arrays in bounds regardless
-    if (total > L::kCap) {
-      if (lane == 0) me2[e] = __builtin_nan("");
-      __syncthreads();  // misc is read by every lane before it is rewritten
-      return;           // uniform over the block
-    }
+    __syncthreads();  // misc is read by every lane before the next round rewrites it
     if (mask < NS) sm.code[mask] = code | (first << 9);
-    __syncthreads();
   }
+  // a valid flow holds at most kCap slots (exhaustive count over all flows);
+  // the guard keeps the packed arrays in bounds regardless
+  if (total > L::kCap) {
+    if (lane == 0) me2[e] = __builtin_nan("");
+    return;  // uniform over the block
+  }
+  __syncthreads();
   // external currents of gluons 0..M-1 into their colour slot (the tensor
   // of a single gluon is 0)
   if (lane < M) {

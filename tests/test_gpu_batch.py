@@ -61,7 +61,7 @@ def _same(segs, got, ref, precision, label=""):
     path forms 1/P^2 from prefix sums and sums the colours in another order;
     FP32: multiply-add contraction, and an event near the check's threshold
     may be re-evaluated in FP64 by one path only; colour-dressed: the batch
-    evaluates an event on 256 lanes, the single request on 128 or 256, which
+    evaluates an event on 256 lanes, the single request on 64, 128 or 256, which
     splits the vertex sums differently).  Both sides meet their per-event
     bars, so they differ by at most twice a bar: FP32 2 FP32_MAX = 6e-4
     (median 1e-6); FP64 2e-12 relative, or for events above that twice the
