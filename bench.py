@@ -39,8 +39,8 @@ sys.path.insert(0, ROOT)
 CSRC = os.path.join(ROOT, "paper_2106_06507_amd", "csrc")
 # sources whose change invalidates the committed counter readings of the
 # fused colour-ordered kernels
-FUSED_SOURCES = ["bg_device.h", "bg_pair.h", "cobg_pair_impl.h", "cdbg_impl.h", "fused_impl.h",
-                 "batch.hip"]
+FUSED_SOURCES = ["bg_device.h", "bg_pair.h", "cobg_pair_impl.h", "cobg_path_impl.h", "cdbg_impl.h",
+                 "fused_impl.h", "batch_impl.h", "batch.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 HEADLINE_KERNEL = "cobg_fused_kernel<6,double,false>"
 
@@ -281,10 +281,10 @@ def section_cdbg(args, api, wm, torch):
         "flops_per_event": flops_event,
         "flops_per_valid_event": flops_event / max(float(valid.mean()), 1e-12),
     }
-    for p, kern, peak in (("fp64", "cdbg_event_kernel<8,double,128>", wm.PEAK_FP64_VALU_TFLOPS),
-                          ("fp32", "cdbg_event_kernel<8,float,128,true> + FP64 re-evaluation",
+    for p, kern, peak in (("fp64", "cdbg_event_kernel<8,double,64>", wm.PEAK_FP64_VALU_TFLOPS),
+                          ("fp32", "cdbg_event_kernel<8,float,64,true> + FP64 re-evaluation",
                            wm.PEAK_FP32_VALU_NOPK_TFLOPS),
-                          ("fp32_unchecked", "cdbg_event_kernel<8,float,128>",
+                          ("fp32_unchecked", "cdbg_event_kernel<8,float,64>",
                            wm.PEAK_FP32_VALU_NOPK_TFLOPS)):
         r = {"value": E / (ms[p] * 1e-3), "ms": ms[p],
              "valid_events_per_s": valid.sum() / (ms[p] * 1e-3),
