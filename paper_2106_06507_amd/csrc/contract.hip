@@ -161,11 +161,52 @@ __global__ void __launch_bounds__(256) contract_y_kernel(int K, int64_t E,
   if (me2) me2[e] = acc;
 }
 
+// The same for K <= 24 with the event's 2K amplitudes held in registers:
+// each is read from HBM once (the loop above re-reads every amplitude K
+// times, and the blocks' working sets overflow L2), and the sums run in the
+// same order, so the results are identical.
+template <int K>
+__global__ void __launch_bounds__(256) contract_y_reg_kernel(int64_t E,
+                                                             const double* __restrict__ amp,
+                                                             const double* __restrict__ C,
+                                                             double* __restrict__ Y,
+                                                             double* __restrict__ me2) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  double x[K], y[K];
+#pragma unroll
+  for (int t = 0; t < K; ++t) {
+    x[t] = amp[(int64_t)t * E + e];
+    y[t] = amp[((int64_t)K + t) * E + e];
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int s = 0; s < K; ++s) {
+    double zx = 0.0, zy = 0.0;
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      const double c = C[s * K + t];
+      zx += c * x[t];
+      zy += c * y[t];
+    }
+    Y[(int64_t)s * E + e] = zx;
+    Y[((int64_t)K + s) * E + e] = zy;
+    acc += x[s] * zx + y[s] * zy;
+  }
+  if (me2) me2[e] = acc;
+}
+
 int contract_y(int K, int64_t E, const double* amp, const double* C, double* Y, double* me2,
                hipStream_t stream) {
   if (E <= 0) return 0;
-  hipLaunchKernelGGL(contract_y_kernel, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, stream, K,
-                     E, amp, C, Y, me2);
+  const dim3 grid((unsigned)((E + 255) / 256));
+  switch (K) {
+    case 2: hipLaunchKernelGGL(contract_y_reg_kernel<2>, grid, dim3(256), 0, stream, E, amp, C, Y, me2); break;
+    case 6: hipLaunchKernelGGL(contract_y_reg_kernel<6>, grid, dim3(256), 0, stream, E, amp, C, Y, me2); break;
+    case 24: hipLaunchKernelGGL(contract_y_reg_kernel<24>, grid, dim3(256), 0, stream, E, amp, C, Y, me2); break;
+    default:
+      hipLaunchKernelGGL(contract_y_kernel, grid, dim3(256), 0, stream, K, E, amp, C, Y, me2);
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
