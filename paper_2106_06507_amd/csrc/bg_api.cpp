@@ -716,8 +716,10 @@ static int fix_listed_two_stage(bg_context* ctx, const bg_request* r, const unsi
   for (int64_t f0 = 0; f0 < E && !st; f0 += slice) {
     const int64_t c = std::min<int64_t>(slice, E - f0);
     for (int hc = 0; hc < nh && !st; ++hc) {
+      // the listed events are a small share: four ordering ranges per block
+      // of 32 of them, so that the short list still spreads over the CUs
       st = launch_status(bg::cobg_path_amplitudes(n, E, f0, c, r->mom, r->hel, hc, ws, list,
-                                                  count, stream));
+                                                  count, stream, 4));
       if (!st)
         st = launch_status(bg::contract_mfma((int)K, c, ws, ctx->C_dev[n], r->me2, hc > 0 ? 1 : 0,
                                              stream, list, count, f0));

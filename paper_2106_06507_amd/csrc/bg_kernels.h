@@ -219,10 +219,12 @@ int comc_reduce(const unsigned* valid, unsigned n_valid, const unsigned* counts,
 // FP64 colour-ordered amplitudes for n = 7, 8 with one straight path per
 // ordering (comc.hip, cobg_path_impl.h): amp [2][K][count] as
 // cobg_amplitudes_range.  idx non-null: column j is event idx[e0 + j] for
-// e0 + j < *cnt (listed events; other columns untouched).
+// e0 + j < *cnt (listed events; other columns untouched).  osplit (n = 7):
+// blocks per 32 events, each taking a contiguous range of the orderings
+// (divides 120).
 int cobg_path_amplitudes(int n, int64_t E, int64_t e0, int64_t count, const double* mom,
                          const int8_t* hel, int hconf, double* amp, const unsigned* idx,
-                         const unsigned* cnt, hipStream_t stream);
+                         const unsigned* cnt, hipStream_t stream, int osplit = 1);
 // FP32 check (bnd from comc_amplitudes with fp32 and bnd non-null): events
 // with B^2 > tau |A|^2 are appended to flist (count fcount[0]) and their
 // items to sel (count fcount[1]; both zeroed beforehand); then the listed

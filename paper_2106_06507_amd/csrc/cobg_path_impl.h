@@ -112,10 +112,11 @@ __device__ __forceinline__ uint32_t lex_code(int sigma) {
   return code;
 }
 
-// All K = (n-2)! amplitudes A(1, sigma, n) of event e on this lane pair,
-// scaled by the couplings, in FP64 to amp[((h K + sigma) astride) + acol]
-// when live (plane h of the lane).  lds: this wave's Lds<N>::bytes<T>(); each
-// lane reads back only its own slots, so no barrier is needed.  EST (T =
+// The amplitudes A(1, sigma, n) of event e on this lane pair for the
+// orderings of lexicographic rank sig0 <= sigma < sig1 (default: all K =
+// (n-2)!), scaled by the couplings, in FP64 to amp[((h K + sigma) astride) +
+// acol] when live (plane h of the lane).  lds: this wave's Lds<N>::bytes<T>();
+// each lane reads back only its own slots, so no barrier is needed.  EST (T =
 // float): est[0] += S_top^2 and est[1] += |A|^2 over the orderings (see
 // pairk::cobg_pair_body).
 template <int N, typename T, bool EST = false>
@@ -123,7 +124,9 @@ __device__ __forceinline__ void cobg_path_body(unsigned char* lds, int64_t E,
                                                const double* __restrict__ mom,
                                                const int8_t* __restrict__ hel, int hconf,
                                                int64_t e, bool live, double* __restrict__ amp,
-                                               int64_t astride, int64_t acol, T* est = nullptr) {
+                                               int64_t astride, int64_t acol, T* est = nullptr,
+                                               int sig0 = 0,
+                                               int sig1 = (int)Factorial<N - 2>::value) {
   constexpr int K = (int)Factorial<N - 2>::value;
   constexpr bool NODT = N >= 8;
   const int lane = threadIdx.x & 63;
@@ -184,7 +187,7 @@ __device__ __forceinline__ void cobg_path_body(unsigned char* lds, int64_t E,
   }
   T s2 = T(0), a2 = T(0);
 #pragma unroll 1
-  for (int sig = 0; sig < K; ++sig) {  // wave-uniform
+  for (int sig = sig0; sig < sig1; ++sig) {  // wave-uniform
     Cx<T> top;
     T topb = T(0);
     path<N, T, 1>(s, c, lex_code<N>(sig), top, topb);

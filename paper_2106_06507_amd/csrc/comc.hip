@@ -522,7 +522,9 @@ __global__ void __launch_bounds__(kThreads) reduce_listed_kernel(
 // (the layout of cobg_pair_kernel), one straight path per ordering
 // (cobg_path_impl.h).  idx (re-evaluation of listed events): column j holds
 // event idx[e0 + j] for e0 + j < *cnt (blocks past the list length return at
-// once).
+// once).  gridDim.y splits the orderings: block (x, y) evaluates ranks
+// [y K / gridDim.y, (y + 1) K / gridDim.y) of its 32 events (more, shorter
+// tasks when few events are listed).
 template <int N, typename T>
 __global__ void __launch_bounds__(64) cobg_path_kernel(int64_t E, int64_t e0, int64_t count,
                                                       const double* __restrict__ mom,
@@ -544,15 +546,18 @@ __global__ void __launch_bounds__(64) cobg_path_kernel(int64_t E, int64_t e0, in
   } else {
     e = e0 + (live ? j : count - 1);
   }
-  pathk::cobg_path_body<N, T>(bg_path_lds, E, mom, hel, hconf, e, live, amp, count, j);
+  constexpr int K = (int)Factorial<N - 2>::value;
+  const int sig0 = (int)(blockIdx.y * K / gridDim.y), sig1 = (int)((blockIdx.y + 1) * K / gridDim.y);
+  pathk::cobg_path_body<N, T>(bg_path_lds, E, mom, hel, hconf, e, live, amp, count, j, nullptr,
+                              sig0, sig1);
 }
 
 template <int N, typename T>
 int path_launch(int64_t E, int64_t e0, int64_t count, const double* mom, const int8_t* hel,
-                int hconf, double* amp, const unsigned* idx, const unsigned* cnt,
+                int hconf, double* amp, const unsigned* idx, const unsigned* cnt, int osplit,
                 hipStream_t stream) {
   const unsigned grid = (unsigned)((count + 31) / 32);
-  hipLaunchKernelGGL((cobg_path_kernel<N, T>), dim3(grid), dim3(64),
+  hipLaunchKernelGGL((cobg_path_kernel<N, T>), dim3(grid, (unsigned)osplit), dim3(64),
                      (pathk::Lds<N>::template bytes<T>()), stream, E, e0, count, mom, hel, hconf,
                      amp, idx, cnt);
   return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -746,10 +751,13 @@ int comc_amplitudes_listed(int n, int64_t E, const double* mom, const int8_t* he
 
 int cobg_path_amplitudes(int n, int64_t E, int64_t e0, int64_t count, const double* mom,
                          const int8_t* hel, int hconf, double* amp, const unsigned* idx,
-                         const unsigned* cnt, hipStream_t stream) {
+                         const unsigned* cnt, hipStream_t stream, int osplit) {
   if (count <= 0) return 0;
+  if (osplit < 1 || osplit > 120 || 120 % osplit != 0) return -2;
   switch (n) {
-    case 7: return comck::path_launch<7, double>(E, e0, count, mom, hel, hconf, amp, idx, cnt, stream);
+    case 7:
+      return comck::path_launch<7, double>(E, e0, count, mom, hel, hconf, amp, idx, cnt, osplit,
+                                           stream);
     case 8: return comck::path_launch_q<8>(E, e0, count, mom, hel, hconf, amp, idx, cnt, stream);
     default: return -2;
   }
