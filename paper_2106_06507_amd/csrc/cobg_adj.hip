@@ -344,6 +344,9 @@ __global__ void __launch_bounds__(64) cobg_adj_kernel(int64_t E, const double* _
   c.g0 = h == 0 ? T(1) : T(-1);
   const bool hi = h != 0;
 
+  // set-up: the momenta and helicities are read again for the final
+  // pull-back instead of being held in registers through the orderings
+  {
   double p[N][4];
 #pragma unroll
   for (int i = 0; i < N; ++i)
@@ -378,6 +381,7 @@ __global__ void __launch_bounds__(64) cobg_adj_kernel(int64_t E, const double* _
       }
     const double p2 = q[0] * q[0] - q[1] * q[1] - q[2] * q[2] - q[3] * q[3];
     c.ip2[mask * L::kPairs + pair] = (T)(1.0 / p2);
+  }
   }
   __syncthreads();
 
@@ -549,8 +553,11 @@ __global__ void __launch_bounds__(64) cobg_adj_kernel(int64_t E, const double* _
       ebi0 += epsNb.im[0];
       ebi1 += epsNb.im[1];
     }
+    double pi[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) pi[m] = mom[((int64_t)i * 4 + m) * E + e];
     double dre[4][4], dim[4][4];
-    polarization_jacobian(p[i], hv[i], dre, dim);
+    polarization_jacobian(pi, (int)hel[(int64_t)i * E + e], dre, dim);
     // this lane's eps_bar as a full four-vector with zeros in the partner's slots
     double ebr[4], ebi[4];
     if (hi) {
