@@ -410,7 +410,9 @@ def two_stage_row(api, wm, torch, n, mom, hel, steps):
             else f"contract_mfma_kernel<{K}>" if K in (24, 120) else f"contract_valu<{K}>")
     row = {"events": E, "K": K, "value": E / ((rms + cms) * 1e-3), "recursion_ms": rms,
            "contraction_ms": cms,
-           "roofline_recursion": roofline(f"cobg_pair_kernel<{n},double>", wm.cobg_flops_per_event(n),
+           "roofline_recursion": roofline({7: "cobg_path_kernel<7,double>", 8: "cobg_path_kernel_q<8>"}
+                                          .get(n, f"cobg_pair_kernel<{n},double>"),
+                                          wm.cobg_flops_per_event(n),
                                           E, rms, wm.PEAK_FP64_VALU_TFLOPS,
                                           "colour-ordered recursion, FP64 flops per event"),
            "roofline_contraction": dict(
