@@ -49,12 +49,32 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def fused_source_hash():
+def source_hash(files):
     h = hashlib.sha256()
-    for f in FUSED_SOURCES:
+    for f in files:
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def fused_source_hash():
+    return source_hash(FUSED_SOURCES)
+
+
+def stored_traffic(kernel, units):
+    """HBM bytes per launch (FETCH + WRITE, calibrated) recorded for `kernel`
+    in profiles/hbm_traffic.json, or None when there is no record for this
+    unit count or the kernel's sources changed since it was measured."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh).get(kernel)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("events") != units:
+        return None
+    if rec.get("source_hash") != source_hash(rec.get("sources", FUSED_SOURCES)):
+        return None
+    return rec["fetch_bytes"] + rec["write_bytes"]
 
 
 def nonvanishing(hel):
@@ -101,7 +121,7 @@ def roofline(kernel, flops_per_unit, units, ms, peak, what, **extra):
     achieved = flops_per_unit * units / (ms * 1e-3) / 1e12
     row = {"bound": "alu", "kernel": kernel, "achieved": achieved, "peak": peak,
            "unit": "TFLOP/s", "frac": achieved / peak, "flops_per_unit": flops_per_unit,
-           "units": units, "what": what}
+           "units": units, "what": what, "traffic": stored_traffic(kernel, units)}
     row.update(extra)
     return row
 
@@ -178,15 +198,7 @@ def section_headline(args, api, wm, torch):
     rec_flops = wm.cobg_flops_per_event(n)
     col_flops = wm.colour_sum_flops_per_event(n)
     flops = rec_flops + col_flops
-    traffic = None
-    try:
-        with open(TRAFFIC_FILE) as fh:
-            t = json.load(fh)
-        k = t.get(HEADLINE_KERNEL)
-        if k and k.get("source_hash") == fused_source_hash() and k.get("events") == E:
-            traffic = k["fetch_bytes"] + k["write_bytes"]
-    except (OSError, ValueError, KeyError):
-        traffic = None
+    traffic = stored_traffic(HEADLINE_KERNEL, E)
 
     rf = roofline(HEADLINE_KERNEL, flops, E, kms64, wm.PEAK_FP64_VALU_TFLOPS,
                   "recursion (prefix-shared walk) + fused colour sum, FP64 flops per event",
