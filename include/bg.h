@@ -277,7 +277,9 @@ typedef struct bg_batch_config {
     int blocks_per_cu;      /* persistent 256-lane blocks per compute unit; 0 = as many
                                as registers and LDS allow */
     int cobg_tile_events;   /* events per colour-ordered tile, multiple of 128, <= 8192 */
-    int cdbg_tile_events;   /* events per colour-dressed tile, multiple of 256, <= 8192 */
+    int cdbg_tile_events;   /* events per colour-dressed tile, multiple of 32, <= 8192 (a tile
+                               of ~5 % valid flows is evaluated event by event, so smaller
+                               tiles shorten the queue's tail) */
     int waves_per_simd;     /* register budget of the kernel: 1 = all registers the
                                largest branch wants (one block per CU), 2 = at most 256
                                per lane (two blocks per CU, some spilling at n = 7) */
@@ -298,7 +300,7 @@ int bg_batch_config_set(bg_context* ctx, int precision, const bg_batch_config* c
  * written) for candidate configs -- split {1, 0} x register budget {2, 1} x
  * blocks per CU {max, 1}, then
  * colour-ordered tile {128, 256, 512, 1024}, then colour-dressed tile
- * {256, 512, 1024}, each stage keeping the best -- with HIP events on
+ * {32, 64, 128, 256, 512}, each stage keeping the best -- with HIP events on
  * `stream`, and installs the fastest config for the segments' precision.
  * Synchronous; writes the chosen config and its time in milliseconds to
  * *best and *best_ms when non-NULL.  Must not be called during graph capture. */

@@ -1432,8 +1432,8 @@ int batch_run(bg_context* ctx, const bg_request* segs, int n_segs, const bg_batc
 bool valid_config(const bg_batch_config* c) {
   return c && c->blocks_per_cu >= 0 && c->blocks_per_cu <= 64 && c->cobg_tile_events >= 128 &&
          c->cobg_tile_events <= 8192 && c->cobg_tile_events % 128 == 0 &&
-         c->cdbg_tile_events >= 256 && c->cdbg_tile_events <= 8192 &&
-         c->cdbg_tile_events % 256 == 0 && (c->waves_per_simd == 1 || c->waves_per_simd == 2) &&
+         c->cdbg_tile_events >= 32 && c->cdbg_tile_events <= 8192 &&
+         c->cdbg_tile_events % 32 == 0 && (c->waves_per_simd == 1 || c->waves_per_simd == 2) &&
          (c->split_kinds == 0 || c->split_kinds == 1);
 }
 
@@ -1542,7 +1542,7 @@ int bg_me2_batch_tune(bg_context* ctx, const bg_request* segs, int n_segs, bg_ba
   }
   if (!st) {
     const bg_batch_config base = cur;
-    for (int t : {256, 512, 1024}) {
+    for (int t : {32, 64, 128, 256, 512}) {
       bg_batch_config c = base;
       c.cdbg_tile_events = t;
       if ((st = try_cfg(c))) break;

@@ -152,6 +152,7 @@ def test_batch_spot_checks_against_oracle(api):
 @pytest.mark.parametrize("cfg", [
     dict(blocks_per_cu=1, cobg_tile_events=128, cdbg_tile_events=256, waves_per_simd=1),
     dict(blocks_per_cu=2, cobg_tile_events=256, cdbg_tile_events=512, waves_per_simd=2),
+    dict(blocks_per_cu=0, cobg_tile_events=128, cdbg_tile_events=64, waves_per_simd=2),
     dict(blocks_per_cu=0, cobg_tile_events=8192, cdbg_tile_events=8192, waves_per_simd=1),
     dict(blocks_per_cu=0, cobg_tile_events=256, cdbg_tile_events=256, waves_per_simd=2,
          split_kinds=0),
