@@ -16,11 +16,20 @@ namespace fusedk {
 // scratch slice; every wave runs the same number of rounds (a wave without a
 // sub-tile evaluates a stand-in event and stores nothing), because the tile
 // routine synchronises the block.  A colour-dressed tile is evaluated by all
-// 256 lanes, one valid event at a time.  LDS: a 64-byte header (validity
+// the block's lanes (256; 128 in the FP32 dressed-only kernel), one valid
+// event at a time.  LDS: a 64-byte header (validity
 // masks, tile broadcast) followed by the tile region.
 constexpr int kBatchWaves = 4;
 constexpr int kBatchLanes = 64 * kBatchWaves;
 constexpr size_t kBatchHeader = 64;
+
+// Lanes per block: 256, except the FP32 dressed-only kernel, which runs one
+// event on 128 lanes (two waves), so that twice as many events are in flight
+// per CU within the same LDS (measured best for FP32 dressed events alone).
+template <typename T, int KINDS>
+struct BatchLanes {
+  static constexpr int value = (KINDS == kBatchKindsCdbg && sizeof(T) == 4) ? 128 : kBatchLanes;
+};
 
 // n >= 6 re-read FP64 momenta from global memory so that four waves of
 // colour-ordered tiles fit in the LDS of one block.
@@ -53,12 +62,12 @@ __device__ __forceinline__ void run_cobg(unsigned char* lds, const BatchSeg& s, 
   }
 }
 
-template <int N, typename T, int PASS>
+template <int N, typename T, int PASS, int NL>
 __device__ __forceinline__ void run_cdbg(unsigned char* lds, unsigned long long* vmask,
                                          const BatchSeg& s, int64_t first, int count) {
-  for (int off = 0; off < count; off += kBatchLanes) {
-    const int c = count - off < kBatchLanes ? count - off : kBatchLanes;
-    cdbg_chunk<N, T, kBatchLanes, PASS>(lds, vmask, s.E, s.mom, s.hel, s.col, s.me2, first + off,
+  for (int off = 0; off < count; off += NL) {
+    const int c = count - off < NL ? count - off : NL;
+    cdbg_chunk<N, T, NL, PASS>(lds, vmask, s.E, s.mom, s.hel, s.col, s.me2, first + off,
                                         c, s.idx, cdbgk::DressedCheck{s.tau, s.fcount, s.flist});
   }
 }
@@ -76,7 +85,8 @@ __device__ __forceinline__ void run_cdbg(unsigned char* lds, unsigned long long*
 // the segment kinds this instance evaluates; tiles of another kind are
 // skipped.  PASS: BatchPass.
 template <typename T, int WAVES, int PASS, int KINDS>
-__global__ void __launch_bounds__(kBatchLanes, WAVES) batch_kernel(const BatchSegTable segs,
+__global__ void __launch_bounds__((BatchLanes<T, KINDS>::value), WAVES) batch_kernel(
+                                                           const BatchSegTable segs,
                                                            const BatchTile* __restrict__ tiles,
                                                            unsigned t_begin, unsigned t_end,
                                                            const unsigned* __restrict__ range_dev,
@@ -106,7 +116,9 @@ __global__ void __launch_bounds__(kBatchLanes, WAVES) batch_kernel(const BatchSe
     break;
 #define BG_CD(NN)                                                                       \
   case kBatchCdbg + NN:                                                                 \
-    if constexpr (kCd) run_cdbg<NN, T, PASS>(lds, vmask, s, tile.first, tile.count);    \
+    if constexpr (kCd)                                                                  \
+      run_cdbg<NN, T, PASS, BatchLanes<T, KINDS>::value>(lds, vmask, s, tile.first,      \
+                                                         tile.count);                    \
     break;
       BG_CO(4) BG_CO(5) BG_CO(6) BG_CO(7)
       BG_CD(4) BG_CD(5) BG_CD(6) BG_CD(7) BG_CD(8) BG_CD(9)
@@ -122,7 +134,8 @@ template <typename T, int WAVES, int PASS, int KINDS>
 int occupancy_of(size_t lds) {
   int nb = 0;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<T, WAVES, PASS, KINDS>,
-                                                      kBatchLanes, lds) == hipSuccess
+                                                      BatchLanes<T, KINDS>::value,
+                                                      lds) == hipSuccess
              ? nb
              : -1;
 }
@@ -143,7 +156,8 @@ void launch_pass(bool fp32, int pass, const BatchSegTable& segs, const BatchTile
                  double* scratch, int64_t scratch_stride, int grid, size_t lds,
                  hipStream_t stream) {
 #define BG_L(TT, PP)                                                                          \
-  hipLaunchKernelGGL((batch_kernel<TT, WAVES, PP, KINDS>), dim3(grid), dim3(kBatchLanes), lds, \
+  hipLaunchKernelGGL((batch_kernel<TT, WAVES, PP, KINDS>), dim3(grid),                        \
+                     dim3(BatchLanes<TT, KINDS>::value), lds,                                  \
                      stream, segs, tiles, t_begin, t_end, range_dev, counter, scratch,          \
                      scratch_stride)
   if (fp32) {

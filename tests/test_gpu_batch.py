@@ -266,8 +266,14 @@ def test_batch_autotune(api):
         torch.cuda.synchronize()
     finally:
         api.set_batch_config("fp32", **old)
-    for g, r in zip(got, ref):
-        assert torch.equal(g, r)
+    # the same kernel instances (register budget, one launch per kind or for
+    # all) give the same results bit for bit; other instances round
+    # differently (see test_batch_result_independent_of_config)
+    if (cfg["waves_per_simd"], cfg["split_kinds"]) == (old["waves_per_simd"], old["split_kinds"]):
+        for g, r in zip(got, ref):
+            assert torch.equal(g, r)
+    else:
+        _same(segs, got, ref, "fp32", "tuned config")
 
 
 def test_full_size_mixed_batch(api):
