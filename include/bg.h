@@ -235,9 +235,11 @@ int bg_me2_grad(bg_context* ctx, const bg_request* req, const double* grad_me2,
 
 /* Several requests (mixed multiplicities, uneven event counts) in one
  * persistent kernel launch per pass, or (config split_kinds, the default) one
- * per segment kind: colour-ordered segments, then colour-dressed ones, each
- * with the LDS and register budget of its own kind; either way a fixed
- * sequence of launches that a graph can record.  Mode BG_MODE_AUTO picks COBG for n <= 7 and CDBG
+ * per segment kind, each with the LDS and register budget of its own kind:
+ * the colour-ordered launch on `stream` and the colour-dressed one
+ * concurrently on a side stream that the context owns, forked from and
+ * joined back into `stream` through events; either way a fixed set of
+ * launches that a graph recording `stream` captures.  Mode BG_MODE_AUTO picks COBG for n <= 7 and CDBG
  * for n >= 8 per segment; explicit modes are honoured (COBG needs n <= 7).
  * Every segment must have the same precision, hel non-NULL, me2 non-NULL when
  * its n_events > 0, and col for CDBG; at most BG_BATCH_MAX_SEGS segments.

@@ -105,6 +105,9 @@ struct bg_context {
   hipEvent_t ws_event = nullptr;             // recorded after each call that uses the workspace
   hipStream_t ws_stream = nullptr;           // stream of that call
   bool ws_pending = false;
+  // batch: side stream of the concurrent per-kind launches, fork/join events
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
 };
 
 namespace {
@@ -605,6 +608,9 @@ void bg_context_destroy(bg_context* ctx) {
   if (ctx->flag_ws) (void)hipFree(ctx->flag_ws);
   if (ctx->val_dev) (void)hipFree(ctx->val_dev);
   if (ctx->ws_event) (void)hipEventDestroy(ctx->ws_event);
+  if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+  if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
+  if (ctx->side) (void)hipStreamDestroy(ctx->side);
   for (BatchPlan& pl : ctx->plans) free_plan(pl);
   delete ctx;
 }
@@ -1397,19 +1403,44 @@ int batch_run(bg_context* ctx, const bg_request* segs, int n_segs, const bg_batc
     if (!st) st = ensure_counters(ctx);
     if (st) return st;
   }
-  auto run = [&](const Launch& l, bool f32, int ps) -> int {
+  auto run = [&](const Launch& l, bool f32, int ps, hipStream_t on, unsigned* head) -> int {
     // the dressed-only kernel never touches the colour-ordered scratch
     const int64_t sstride = l.kinds == bg::kBatchKindsCdbg ? 0 : stride;
     return launch_status(bg::batch_launch(f32, l.waves, ps, l.kinds, tab, ps == bg::kBatchFix
                                                                           ? pl->fix_tiles
                                                                           : pl->tiles,
-                                          l.b, l.e, l.range, ctx->counter, ctx->scratch, sstride,
-                                          (int)l.grid, l.lds, stream));
+                                          l.b, l.e, l.range, head, ctx->scratch, sstride,
+                                          (int)l.grid, l.lds, on));
   };
-  if (!check) {
-    for (int i = 0; i < n_main && !st; ++i) st = run(main_l[i], fp32, bg::kBatchPlain);
-    return st;
+  // The launches of one pass.  Split into kinds, the two run concurrently:
+  // the colour-ordered one on `stream`, the dressed one on the context's side
+  // stream (forked and joined through events, so a graph records both), each
+  // with its own queue head.  The colour-ordered launch is enqueued first: its
+  // blocks (the larger LDS) take their CUs before the dressed blocks fill the
+  // rest, and as each CU's colour-ordered block runs out of tiles (the long
+  // n = 7 tasks end at different times) dressed blocks take its place.
+  if (cfg.split_kinds && !ctx->side && !capturing) {
+    st = hip_status(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking), "hipStreamCreate");
+    if (!st) st = hip_status(hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming), "hipEventCreate");
+    if (!st) st = hip_status(hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming), "hipEventCreate");
+    if (st) return st;
   }
+  auto run_pass = [&](const Launch* ls, int nl, bool f32, int ps) -> int {
+    if (nl == 2 && ctx->side && ctx->fork_ev && ctx->join_ev) {
+      const int a = ls[0].kinds == bg::kBatchKindsCobg ? 0 : 1;  // colour-ordered first
+      int r = hip_status(hipEventRecord(ctx->fork_ev, stream), "hipEventRecord");
+      if (!r) r = hip_status(hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0), "hipStreamWaitEvent");
+      if (!r) r = run(ls[a], f32, ps, stream, ctx->counter);
+      if (!r) r = run(ls[1 - a], f32, ps, ctx->side, ctx->counter + 2);
+      if (!r) r = hip_status(hipEventRecord(ctx->join_ev, ctx->side), "hipEventRecord");
+      if (!r) r = hip_status(hipStreamWaitEvent(stream, ctx->join_ev, 0), "hipStreamWaitEvent");
+      return r;
+    }
+    int r = BG_OK;
+    for (int i = 0; i < nl && !r; ++i) r = run(ls[i], f32, ps, stream, ctx->counter);
+    return r;
+  };
+  if (!check) return run_pass(main_l, n_main, fp32, bg::kBatchPlain);
   for (int i = 0; i < n_segs; ++i) {
     const bg_request* r = &segs[i];
     bg::BatchSeg& b = tab.s[i];
@@ -1420,13 +1451,12 @@ int batch_run(bg_context* ctx, const bg_request* segs, int n_segs, const bg_batc
                                                                : ctx->fp32_tau[cd ? 1 : 0][r->n];
   }
   st = launch_status(bg::fill_u32(pl->chk_ws, 38, 0u, stream));
-  for (int i = 0; i < n_main && !st; ++i) st = run(main_l[i], true, bg::kBatchCheck);
+  if (!st) st = run_pass(main_l, n_main, true, bg::kBatchCheck);
   if (!st)
     st = launch_status(bg::batch_fix_tiles(tab, n_segs, pl->chk_ws, pl->fix_tiles, range, stream));
   if (st) return st;
   for (int i = 0; i < n_segs; ++i) tab.s[i].idx = tab.s[i].flist;
-  for (int i = 0; i < n_fix && !st; ++i) st = run(fix_l[i], false, bg::kBatchFix);
-  return st;
+  return run_pass(fix_l, n_fix, false, bg::kBatchFix);
 }
 
 bool valid_config(const bg_batch_config* c) {
