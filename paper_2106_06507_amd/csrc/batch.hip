@@ -116,10 +116,62 @@ __global__ void __launch_bounds__(64) lc_fix_kernel(int64_t E, const double* __r
   }
 }
 
+// FP64 leading colour on straight paths (cobg_path_impl.h), for n = 7, where
+// the depth-first walk's FP64 state spills: 32 events per 64-lane block.
+// idx (re-evaluation of listed events): the block's events are idx[j] for
+// j < *cnt (blocks past the list return at once).
+template <int N>
+__global__ void __launch_bounds__(64) lc_path_kernel(int64_t E, const double* __restrict__ mom,
+                                                    const int8_t* __restrict__ hel,
+                                                    double* __restrict__ me2,
+                                                    const unsigned* __restrict__ idx,
+                                                    const unsigned* __restrict__ cnt) {
+  extern __shared__ __align__(16) unsigned char bg_lcp_lds[];
+  const int pair = (int)threadIdx.x >> 1, h = (int)threadIdx.x & 1;
+  const int64_t j = (int64_t)blockIdx.x * kTileEvents + pair;
+  bool live;
+  int64_t e;
+  if (idx) {
+    const int64_t total = (int64_t)*cnt;
+    const int64_t b0 = (int64_t)blockIdx.x * kTileEvents;
+    if (b0 >= total) return;  // the whole block (uniform)
+    live = j < total;
+    e = (int64_t)idx[live ? j : b0];
+  } else {
+    live = j < E;
+    e = live ? j : E - 1;
+  }
+  const double q = pathk::cobg_path_body<N, double, false, true>(bg_lcp_lds, E, mom, hel, 0, e,
+                                                                 false, nullptr, 0, 0);
+  double colour = 8.0;  // N^(n-2) (N^2 - 1)
+#pragma unroll
+  for (int i = 0; i < N - 2; ++i) colour *= 3.0;
+  if (live && h == 0) me2[e] = q * colour;
+}
+
 template <int N, typename T>
 int lc_launch(int64_t E, const double* mom, const int8_t* hel, double* me2, const CheckArgs* chk,
               int fix_grid, hipStream_t stream) {
   const unsigned tiles = (unsigned)((E + kTileEvents - 1) / kTileEvents);
+  if constexpr (N == 7) {
+    // FP64 (the plain path and the re-evaluation of listed events) on
+    // straight paths
+    const size_t lds = pathk::Lds<N>::template bytes<double>();
+    if (!chk) {
+      if constexpr (sizeof(T) == 8) {
+        hipLaunchKernelGGL((lc_path_kernel<N>), dim3(tiles), dim3(64), lds, stream, E, mom, hel,
+                           me2, nullptr, nullptr);
+        return hipGetLastError() == hipSuccess ? 0 : -1;
+      }
+    } else {
+      hipLaunchKernelGGL((lc_kernel<N, float, true>), dim3(tiles), dim3(64),
+                         (pairk::Lds<N, true>::template bytes<float>()), stream, E, mom, hel, me2,
+                         TileCheck{chk->tau, chk->count, chk->list});
+      hipLaunchKernelGGL((lc_path_kernel<N>), dim3(tiles), dim3(64), lds, stream, E, mom, hel,
+                         me2, chk->list, chk->count);
+      return hipGetLastError() == hipSuccess ? 0 : -1;
+    }
+  }
   if (!chk) {
     hipLaunchKernelGGL((lc_kernel<N, T>), dim3(tiles), dim3(64),
                        (pairk::Lds<N, true>::template bytes<T>()), stream, E, mom, hel, me2,

@@ -112,15 +112,43 @@ __device__ __forceinline__ uint32_t lex_code(int sigma) {
   return code;
 }
 
+// Code of the rho-th ordering (1, rho) of gluons 1..n-1 in lexicographic
+// order, every gluon allowed at every position including the closing one
+// (the (n-1)! orderings of the leading-colour sum, Section 3.1): the
+// permutation unranked in the factorial number system.  Wave-uniform when
+// rho is.
+template <int N>
+__device__ __forceinline__ uint32_t lc_code(int rho) {
+  constexpr int KM = N - 1;
+  uint32_t code = 0u;
+  int avail = ((1 << KM) - 1) << 1;  // bits 1..KM: gluons not yet placed
+  int f = (int)Factorial<KM - 1>::value;
+  int r = rho;
+#pragma unroll
+  for (int k = 0; k < KM; ++k) {
+    const int d = r / f;
+    r -= d * f;
+    if (k < KM - 1) f /= (KM - 1 - k);
+    int a = avail;
+    for (int i = 0; i < d; ++i) a &= a - 1;
+    const int gl = __builtin_ctz(a);
+    avail &= ~(1 << gl);
+    code |= (uint32_t)gl << (4 * k);
+  }
+  return code;
+}
+
 // The amplitudes A(1, sigma, n) of event e on this lane pair for the
 // orderings of lexicographic rank sig0 <= sigma < sig1 (default: all K =
 // (n-2)!), scaled by the couplings, in FP64 to amp[((h K + sigma) astride) +
 // acol] when live (plane h of the lane).  lds: this wave's Lds<N>::bytes<T>();
 // each lane reads back only its own slots, so no barrier is needed.  EST (T =
 // float): est[0] += S_top^2 and est[1] += |A|^2 over the orderings (see
-// pairk::cobg_pair_body).
-template <int N, typename T, bool EST = false>
-__device__ __forceinline__ void cobg_path_body(unsigned char* lds, int64_t E,
+// pairk::cobg_pair_body).  LC: instead, the sum of |A(1, rho)|^2 over the
+// (n-1)! leading-colour orderings (lc_code), scaled by the couplings and
+// returned (both lanes of the pair); nothing is written.
+template <int N, typename T, bool EST = false, bool LC = false>
+__device__ __forceinline__ double cobg_path_body(unsigned char* lds, int64_t E,
                                                const double* __restrict__ mom,
                                                const int8_t* __restrict__ hel, int hconf,
                                                int64_t e, bool live, double* __restrict__ amp,
@@ -185,6 +213,17 @@ __device__ __forceinline__ void cobg_path_body(unsigned char* lds, int64_t E,
     s.Sb[0][0] = T(1);
     s.Ep[0] = e0p;
   }
+  if constexpr (LC) {
+    double q = 0.0;
+#pragma unroll 1
+    for (int rho = 0; rho < (int)Factorial<N - 1>::value; ++rho) {  // wave-uniform
+      Cx<T> top;
+      T topb = T(0);
+      path<N, T, 1>(s, c, lc_code<N>(rho), top, topb);
+      q += (double)top.re * (double)top.re + (double)top.im * (double)top.im;
+    }
+    return q * scale * scale;
+  }
   T s2 = T(0), a2 = T(0);
 #pragma unroll 1
   for (int sig = sig0; sig < sig1; ++sig) {  // wave-uniform
@@ -201,6 +240,7 @@ __device__ __forceinline__ void cobg_path_body(unsigned char* lds, int64_t E,
     est[0] += s2;
     est[1] += a2;
   }
+  return 0.0;
 }
 
 }  // namespace pathk
