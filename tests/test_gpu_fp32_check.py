@@ -150,7 +150,7 @@ def test_leading_colour_fp32_p99(api, n):
 
 
 @pytest.mark.parametrize("mode,n", [("cobg", 5), ("cobg", 6), ("cobg", 7), ("cdbg", 6), ("cdbg", 8),
-                                    ("comc", 6), ("comc", 8), ("lc", 6)])
+                                    ("comc", 6), ("comc", 8), ("lc", 6), ("lc", 7)])
 def test_threshold_extremes(api, mode, n):
     """tau = 0: every non-vanishing event is re-evaluated in FP64, so the
     result equals the FP64 path bit for bit; tau = inf: none is, so it equals
