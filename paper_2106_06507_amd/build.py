@@ -30,7 +30,7 @@ COMMON = [
 SOURCES = ["bg_api.cpp", "colour_matrix.cpp", "cobg_pair.hip", "cobg_adj.hip", "cdbg.hip",
            "contract.hip", "batch.hip", "rambo.hip", "comc.hip", "cdmc.hip", "util.hip",
            "noalloc.hip", "full_colour.hip", "batch_kinds_all.hip", "batch_kinds_cobg.hip",
-           "batch_kinds_cdbg.hip"]
+           "batch_kinds_cdbg.hip", "hsum.hip"]
 
 
 def _compile(src, extra):

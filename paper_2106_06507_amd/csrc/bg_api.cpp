@@ -734,6 +734,10 @@ static int fix_listed_two_stage(bg_context* ctx, const bg_request* r, const unsi
   return st;
 }
 
+// Helicity-summed requests up to this many events take the split path
+// (below ~16 k events the tiles of the fused kernel do not fill the GPU).
+constexpr int64_t kHsumSplitEvents = 16384;
+
 static int me2_cobg(bg_context* ctx, const bg_request* r, uint32_t flags, hipStream_t stream,
                     const FixedWs* fixed = nullptr) {
   const int n = r->n;
@@ -757,6 +761,15 @@ static int me2_cobg(bg_context* ctx, const bg_request* r, uint32_t flags, hipStr
       fixed ? (int64_t)(fixed->scratch_bytes /
                         (sizeof(double) * (size_t)std::max(1, bg::cobg_fused_scratch_doubles(n))))
             : INT64_MAX;
+  // few events with the helicities summed (FP64, n <= 6): one block per
+  // (tile, configuration) instead of the configurations in turn on one block
+  // per tile, which would leave most CUs idle; the same bits
+  if (hsum && !fp32 && !fixed && n <= 6 && E <= kHsumSplitEvents) {
+    st = ensure_ws(ctx, sizeof(double) * 2 * ((size_t)1 << n) * (size_t)E);
+    if (st) return st;
+    return launch_status(
+        bg::cobg_hsum_split(n, E, r->mom, ctx->Cb_dev[n], ctx->ws, r->me2, stream));
+  }
   int64_t grid = 0, fix_grid = 0;
   if (check) {
     int& occ = ctx->occ_fix[n][hsum ? 1 : 0];

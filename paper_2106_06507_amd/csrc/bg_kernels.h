@@ -51,6 +51,12 @@ int cobg_amplitudes_range(int n, bool fp32, int64_t E, int64_t e0, int64_t count
                           const double* mom, const int8_t* hel, int hconf, double* amp,
                           hipStream_t stream);
 
+// Helicity-summed colour-ordered |M|^2 in FP64 for n = 4..6 (hsum.hip): one
+// block per (32-event tile, configuration), part [2^n][2][E] doubles of
+// workspace, then the per-event sums; the fused kernel's bits.
+int cobg_hsum_split(int n, int64_t E, const double* mom, const double* Cb, double* part,
+                    double* me2, hipStream_t stream);
+
 // Gradient of sum_st C_st Re(A_s conj(A_t)) scaled by gme2[e] (null = 1),
 // given Y = C A [2][K][E]; perms [K][n-2] lists the middle gluons of each
 // ordering; grad [n][4][E].

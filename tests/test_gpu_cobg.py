@@ -132,6 +132,21 @@ def test_helicity_sum_fused(api, n):
     assert np.max(np.abs(got - ref) / ref) < FP64_ME2_RTOL
 
 
+@pytest.mark.parametrize("n", [4, 5, 6])
+def test_helicity_sum_split_equals_fused(api, n):
+    """Helicity-summed FP64 requests of up to 16384 events run one block per
+    (tile, configuration) and add the configurations afterwards; larger ones
+    run the configurations in turn in the fused kernel.  Same operations in
+    the same order: the first events agree bit for bit, ragged tail included."""
+    E_big, E_small = 16500, 1001
+    ev = make_events(n, E_big, seed=9600 + n, cuts=True)
+    big = api.me2(_dev(ev["mom"]), None, precision="fp64").cpu().numpy()
+    small = api.me2(_dev(np.ascontiguousarray(ev["mom"][:, :, :E_small])), None,
+                    precision="fp64").cpu().numpy()
+    _say(f"helicity-sum split n={n}: {E_small} events against the fused kernel's {E_big}")
+    assert np.array_equal(small, big[:E_small])
+
+
 @pytest.mark.parametrize("n", [4, 5, 6, 7])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_fused_equals_two_stage(api, n, precision):
