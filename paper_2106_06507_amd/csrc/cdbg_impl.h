@@ -31,7 +31,12 @@
 // ordered splits (S1, S2) of S:
 //   J(S) = 1/P_S^2 sum [ V3(P1, P2; J1, J2) + T2.J1 - T1.J2 ],
 //   T(S) = sum [ J1^a J2^b - J1^b J2^a ],     (T.J)^nu = T^{nu beta} J_beta,
-// and A = (g_s/sqrt2)^(n-2) eps_n . (P^2 J)_{i_n j_n}(1..n-1).
+// and A = (g_s/sqrt2)^(n-2) eps_n . (P^2 J)_{i_n j_n}(1..n-1).  The bracket
+// and the tensor term change sign when the two operands (with their momenta)
+// are exchanged, so the kernel sums over unordered splits with the colour
+// commutator [J1, J2] instead (pair_slots): splits of two balanced subsets
+// drop out, a trail and a balanced subset take one evaluation, and half the
+// candidate splits are visited.
 //
 // Parallel layout (gfx950): one 64-lane wave per valid event, persistent
 // blocks pulling events from a compacted list.  Currents, tensors, momenta and
@@ -168,37 +173,44 @@ __device__ __forceinline__ T shfl_down_t(T v, int off) {
   return __shfl_down(v, (unsigned)off, kWave);
 }
 
-// Operand slots of split (S1, S2) feeding target slot t of S; false if none
-// (including a balanced operand that does not touch the colour asked of it:
-// its current has no such entry).
-__device__ __forceinline__ bool split_slots(int c1, int c2, int t, int& s1, int& s2) {
+// Unordered split {m1, m2} of S feeding target slot t of S.  The ordered
+// contribution F(P1, P2; X1, X2) (X = current and tensor field) is bilinear
+// and changes sign when the two operands are exchanged, so the two orders of
+// a split combine into one evaluation F(P_L, P_R; X_L, X_R) with the colour
+// commutator in the right operand:
+//   two trails:           at most one order gives entry t (both orders
+//                         give different diagonal entries of a balanced S);
+//   trail (r, c) U and balanced D:  X_R = X_D(c, c) - X_D(r, r), L = U
+//                         (entry (r, c) of [X_U, X_D]);
+//   both balanced:        diagonal matrices commute, the orders cancel.
+// Returns false if the split contributes nothing; otherwise swap tells
+// whether L is m2, iL is L's slot and X_R = X[ip] - X[im] (an index < 0
+// stands for a colour the balanced operand does not touch: a zero entry).
+__device__ __forceinline__ bool pair_slots(int c1, int c2, int t, bool& swap, int& iL, int& ip,
+                                           int& im) {
   if ((c1 & 3) == 0 || (c2 & 3) == 0) return false;  // zero currents
   const bool b1 = (c1 & 3) == 2, b2 = (c2 & 3) == 2;
+  if (b1 && b2) return false;
   if (!b1 && !b2) {
-    const int r1 = (c1 >> 2) & 3, cc1 = (c1 >> 4) & 3;
-    const int r2 = (c2 >> 2) & 3, cc2 = (c2 >> 4) & 3;
-    if (cc1 != r2) return false;
-    const int tt = (r1 == cc2) ? r1 : 0;
-    if (tt != t) return false;
-    s1 = 0;
-    s2 = 0;
+    const int r1 = (c1 >> 2) & 3, k1 = (c1 >> 4) & 3;
+    const int r2 = (c2 >> 2) & 3, k2 = (c2 >> 4) & 3;
+    if (k1 == r2 && (r1 == k2 ? r1 : 0) == t) swap = false;
+    else if (k2 == r1 && (r2 == k1 ? r2 : 0) == t) swap = true;
+    else return false;
+    iL = (swap ? c2 : c1) >> 9;
+    ip = (swap ? c1 : c2) >> 9;
+    im = -1;
     return true;
   }
-  if (!b1 && b2) {
-    if (t != 0) return false;
-    s1 = 0;
-    s2 = (c1 >> 4) & 3;
-    return ((c2 >> (6 + s2)) & 1) != 0;
-  }
-  if (b1 && !b2) {
-    if (t != 0) return false;
-    s1 = (c2 >> 2) & 3;
-    s2 = 0;
-    return ((c1 >> (6 + s1)) & 1) != 0;
-  }
-  s1 = t;
-  s2 = t;
-  return ((c1 & c2) >> (6 + t) & 1) != 0;
+  if (t != 0) return false;
+  swap = b1;
+  const int cu = b1 ? c2 : c1, cd = b1 ? c1 : c2;
+  const int r = (cu >> 2) & 3, c = (cu >> 4) & 3, touched = (cd >> 6) & 7;
+  const int first = cd >> 9;
+  ip = (touched >> c) & 1 ? first + __popc(touched & ((1 << c) - 1)) : -1;
+  im = (touched >> r) & 1 ? first + __popc(touched & ((1 << r) - 1)) : -1;
+  iL = cu >> 9;
+  return ip >= 0 || im >= 0;
 }
 
 // Packed index of colour slot s of a subset with code word c (s a slot the
@@ -214,22 +226,39 @@ __device__ __forceinline__ int slot_count(int c) {
   return (c & 3) == 1 ? 1 : ((c & 3) == 2 ? __popc((c >> 6) & 7) : 0);
 }
 
-// Accumulate the contribution of split (m1, m2) whose operands are the
-// packed slots i1, i2.
+// Accumulate F(P_L, P_R; X_L, X_R) for left operand slot iL of subset mL
+// and right operand X[ip] - X[im] of subset mR (see pair_slots).
 template <int N, typename T>
-__device__ __forceinline__ void split_contrib(const Sm<N, T>& sm, int m1, int m2, int i1, int i2,
-                                              bool want_tensor, T* gre, T* gim, T* tre, T* tim) {
-  const T* J1 = sm.J + i1 * 8;
-  const T* J2 = sm.J + i2 * 8;
+__device__ __forceinline__ void split_contrib(const Sm<N, T>& sm, int mL, int mR, int iL, int ip,
+                                              int im, bool want_tensor, T* gre, T* gim, T* tre,
+                                              T* tim) {
+  const T* J1 = sm.J + iL * 8;
   T a_re[4], a_im[4], b_re[4], b_im[4], P1[4], P2[4];
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
     a_re[mu] = J1[mu];
     a_im[mu] = J1[4 + mu];
-    b_re[mu] = J2[mu];
-    b_im[mu] = J2[4 + mu];
-    P1[mu] = sm.P[m1 * 4 + mu];
-    P2[mu] = sm.P[m2 * 4 + mu];
+    P1[mu] = sm.P[mL * 4 + mu];
+    P2[mu] = sm.P[mR * 4 + mu];
+  }
+  if (ip >= 0) {
+    const T* J2 = sm.J + ip * 8;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      b_re[mu] = J2[mu];
+      b_im[mu] = J2[4 + mu];
+    }
+  } else {
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) b_re[mu] = b_im[mu] = T(0);
+  }
+  if (im >= 0) {
+    const T* J2 = sm.J + im * 8;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      b_re[mu] -= J2[mu];
+      b_im[mu] -= J2[4 + mu];
+    }
   }
   // V3(P1, P2; J1, J2) = (J1.J2)(P1-P2) + ((2P2+P1).J1) J2 - ((2P1+P2).J2) J1
   T abr = a_re[0] * b_re[0] - a_im[0] * b_im[0];
@@ -263,14 +292,27 @@ __device__ __forceinline__ void split_contrib(const Sm<N, T>& sm, int m1, int m2
     gim[mu] -= c2i * a_re[mu];
   }
   // tensor couplings: + T2.J1 - T1.J2
-  const T* T1 = sm.Tt + i1 * 12;
-  const T* T2 = sm.Tt + i2 * 12;
+  const T* T1 = sm.Tt + iL * 12;
   {
     T t_re[6], t_im[6];
+    if (ip >= 0) {
+      const T* T2 = sm.Tt + ip * 12;
 #pragma unroll
-    for (int x = 0; x < 6; ++x) {
-      t_re[x] = T2[x];
-      t_im[x] = T2[6 + x];
+      for (int x = 0; x < 6; ++x) {
+        t_re[x] = T2[x];
+        t_im[x] = T2[6 + x];
+      }
+    } else {
+#pragma unroll
+      for (int x = 0; x < 6; ++x) t_re[x] = t_im[x] = T(0);
+    }
+    if (im >= 0) {
+      const T* T2 = sm.Tt + im * 12;
+#pragma unroll
+      for (int x = 0; x < 6; ++x) {
+        t_re[x] -= T2[x];
+        t_im[x] -= T2[6 + x];
+      }
     }
     tdotj_acc(gre, gim, t_re, t_im, a_re, a_im, T(1));
 #pragma unroll
@@ -543,7 +585,7 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
     q = q < 1 ? 1 : (q > kWave ? kWave : q);
     const int gpw = kWave / q;  // targets per wave and round
     const int per_round = gpw * NW;
-    const int nsplit = (1 << size) - 2;
+    const int nsplit = (1 << (size - 1)) - 1;  // unordered splits (pair_slots)
     for (int r0 = 0; r0 < nitems; r0 += per_round) {
       const int grp = lw / q;
       const int it = r0 + w * gpw + grp;
@@ -559,25 +601,29 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
         t = item & 3;
         T enS = T(0);
         if constexpr (EST) enS = sm.en[S];
-        // a contiguous range of splits per lane: the first sub-mask is
-        // deposited into S's bits, the next ones follow as (m1 - S) & S
+        // a contiguous range of splits per lane: the first sub-mask (of
+        // S's members below its highest one, so each unordered split comes
+        // once) is deposited into S's bits, the next ones follow as
+        // (m1 - S) & S
         const int per = (nsplit + q - 1) / q;
         const int k0 = sub * per;
         const int k1 = k0 + per < nsplit ? k0 + per : nsplit;
         int m1 = k0 < k1 ? subset_of<M>(k0 + 1, S) : 0;
         for (int k = k0; k < k1; ++k, m1 = (m1 - S) & S) {
           const int m2 = S ^ m1;
-          const int c1 = sm.code[m1], c2 = sm.code[m2];
-          int s1, s2;
-          if (!split_slots(c1, c2, t, s1, s2)) continue;
-          const int i1 = slot_index(c1, s1), i2 = slot_index(c2, s2);
-          split_contrib<N, T>(sm, m1, m2, i1, i2, !top, gre, gim, tre, tim);
+          bool swap;
+          int iL, ip, im;
+          if (!pair_slots(sm.code[m1], sm.code[m2], t, swap, iL, ip, im)) continue;
+          split_contrib<N, T>(sm, swap ? m2 : m1, swap ? m1 : m2, iL, ip, im, !top, gre, gim, tre,
+                              tim);
           if constexpr (EST) {
-            const T j1 = sm.bJ[i1], j2 = sm.bJ[i2];
+            const T j1 = sm.bJ[iL];
+            const T j2 = (ip >= 0 ? sm.bJ[ip] : T(0)) + (im >= 0 ? sm.bJ[im] : T(0));
+            const T t2 = (ip >= 0 ? sm.bT[ip] : T(0)) + (im >= 0 ? sm.bT[im] : T(0));
             const T jj = j1 * j2;
             bv += enS * jj;
-            bv += sm.bT[i2] * j1;
-            bv += sm.bT[i1] * j2;
+            bv += t2 * j1;
+            bv += sm.bT[iL] * j2;
             bt += jj;
           }
         }
