@@ -579,13 +579,14 @@ __device__ __forceinline__ void cdbg_one_event(const Sm<N, T>& sm, int64_t E,
       }
     }
     __syncthreads();
-    // q adjacent lanes of one wave per target, each taking a contiguous
-    // range of its splits
+    // q adjacent lanes of one wave per target (no more than it has splits),
+    // each taking a contiguous range of its splits
+    const int nsplit = (1 << (size - 1)) - 1;  // unordered splits (pair_slots)
     int q = nitems == 0 ? 1 : NL / nitems;
+    q = q > nsplit ? nsplit : q;
     q = q < 1 ? 1 : (q > kWave ? kWave : q);
     const int gpw = kWave / q;  // targets per wave and round
     const int per_round = gpw * NW;
-    const int nsplit = (1 << (size - 1)) - 1;  // unordered splits (pair_slots)
     for (int r0 = 0; r0 < nitems; r0 += per_round) {
       const int grp = lw / q;
       const int it = r0 + w * gpw + grp;
