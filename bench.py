@@ -301,9 +301,10 @@ def section_cdbg(args, api, wm, torch):
         r = {"value": E / (ms[p] * 1e-3), "ms": ms[p],
              "valid_events_per_s": valid.sum() / (ms[p] * 1e-3),
              "roofline": roofline(kern, flops_event, E, ms[p], peak,
-                                  "contributing (colour-compatible) splits of the dressed "
-                                  "recursion per sampled event (workmodel.cdbg_flops_per_event, "
-                                  "mean over 2^15 events; invalid flows cost 0)")}
+                                  "contributing unordered splits (colour commutator) of the "
+                                  "dressed recursion per sampled event "
+                                  "(workmodel.cdbg_flops_per_event, mean over 2^15 events; "
+                                  "invalid flows cost 0)")}
         if p == "fp64":
             r["rel_err_vs_long_double_oracle"] = rel_err_stats(res[p][idx], ref)
         else:

@@ -174,10 +174,13 @@ def cdbg_flops_per_event(col):
     """Algorithmic flops of the colour-dressed recursion for each event of
     col [2][n][E] (colour labels i_k = col[0][k], j_k = col[1][k]): the sum
     over subsets S of gluons 0..n-2 (|S| >= 2), over their non-zero colour
-    entries and over the ordered splits (S1, S2) of S whose colour product
-    reaches that entry, of the per-split costs above.  Events whose flow does
-    not close (no closed chain of all n edges) cost 0: they are classified
-    and skip the recursion."""
+    entries and over the unordered splits {S1, S2} of S whose colour
+    commutator reaches that entry, of the per-split costs above.  The
+    kinematic part of a split changes sign when its operands are exchanged,
+    so its two orders take one evaluation, and a split of two balanced
+    subsets (diagonal currents, which commute) costs nothing.  Events whose
+    flow does not close (no closed chain of all n edges) cost 0: they are
+    classified and skip the recursion."""
     n, E = col.shape[1], col.shape[2]
     M = n - 1
     i, j = col[0].astype(np.int64), col[1].astype(np.int64)
@@ -196,14 +199,18 @@ def cdbg_flops_per_event(col):
             if not okS.any():
                 continue
             nsplit = np.zeros(E)
+            top = 1 << (S.bit_length() - 1)
             A = (S - 1) & S
             while A:
-                B = S ^ A
-                e1, e2 = ent[A], ent[B]
-                hit = np.zeros(E, dtype=bool)
-                for k in range(3):
-                    hit |= e1[(r, k)] & e2[(k, c)]
-                nsplit += hit
+                if not A & top:  # each unordered split once
+                    B = S ^ A
+                    e1, e2 = ent[A], ent[B]
+                    hit = np.zeros(E, dtype=bool)
+                    for k in range(3):
+                        hit |= (e1[(r, k)] & e2[(k, c)]) | (e2[(r, k)] & e1[(k, c)])
+                    bal1 = e1[(0, 0)] | e1[(1, 1)] | e1[(2, 2)]
+                    bal2 = e2[(0, 0)] | e2[(1, 1)] | e2[(2, 2)]
+                    nsplit += hit & ~(bal1 & bal2)
                 A = (A - 1) & S
             per = FLOP_CD_SPLIT + (0 if S == full else FLOP_CD_TENSOR)
             flops += okS * (nsplit * per + (32 if S == full else 8))

@@ -51,6 +51,35 @@ def test_dressed_n8_few_events():
     assert _scale_rel(d, bf) < 1e-12
 
 
+@pytest.mark.parametrize("n", [5, 6])
+def test_dressed_currents_traceless(n):
+    """The kinematic part of a split (three-gluon vertex and tensor terms)
+    changes sign when its two operands are exchanged, so the two orders of a
+    split enter eq. color_dressed_currents as the colour commutator
+    [J(S1), J(S2)], and every dressed current of two or more gluons has zero
+    colour trace.  A vertex term with a wrong sign or momentum (which breaks
+    that antisymmetry) leaves an O(1) trace; a reversed colour product flips
+    the sign of every current alike and is not seen here.  Currents that are themselves cancellation noise (subsets
+    of diagonal gluons of one colour) are left out by their size, and so are
+    flows of diagonal gluons only, where every such current is noise."""
+    E = 48
+    rng = np.random.default_rng(1400 + n)
+    ev = make_events(n, E, seed=1400 + n, cuts=True)
+    col = valid_colours(n, E, rng)
+    J = cdbg.dressed_currents(ev["mom"], ev["hel"], col)
+    checked = 0
+    for size in range(2, n):
+        masks = [S for S in J if bin(S).count("1") == size]
+        mag = {S: np.max(np.abs(J[S]), axis=(0, 1, 2)) for S in masks}  # [E]
+        top = np.max([mag[S] for S in masks], axis=0)
+        for S in masks:
+            tr = np.max(np.abs(J[S][0, 0] + J[S][1, 1] + J[S][2, 2]), axis=0)
+            use = (mag[S] > 1e-6 * top) & np.any(col[0] != col[1], axis=0)
+            assert np.all(tr[use] <= 1e-10 * mag[S][use]), (n, size, S)
+            checked += int(use.sum())
+    assert checked > E
+
+
 def test_invalid_colour_flows_vanish():
     """No closed colour chain -> every delta chain is zero -> amplitude exactly 0."""
     n = 6
